@@ -1,0 +1,379 @@
+"""AIM operators with the numerically filtered grid kernel (oracle).
+
+Test infrastructure.  Passages followed (Sec. III):
+  * grid of m x m points with step eps, centred at the origin, side
+    2L = (m-1) eps, point (ix, iy) at (-L + ix eps, -L + iy eps), row-major
+    index iy*m + ix                                                (Sec. III-A)
+  * G_nodes ~ Lambda^T G_grid Lambda with a sparse projection Lambda and a
+    Toeplitz G_grid whose entries are g at grid offsets            (Sec. III-A)
+  * the Toeplitz product through a zero-padded circulant embedding (eq. (8))
+  * numerical filter: the DFT of the circulant kernel truncated to the disc
+    |kappa| <= alpha                                               (Sec. III-B)
+  * filtered operator S^alpha = Lambda^T [F^-1(F(c^alpha) F(b))]_restr
+    Lambda                                                         (eq. (10))
+  * the self-interaction of G_grid is set to zero                  (Sec. III-C)
+
+Readings taken where the paper is silent:
+  * Lambda is folded with the quadrature weights and basis values of eq. (7)
+    into one 4 x 4 tensor-product cubic Lagrange stencil per basis function,
+    anchored at the cell holding the basis centre (pulse: segment midpoint,
+    hat: its vertex): W_j[t*4+s] = sum_k w_k v_j(r_k) l_s(x_k) l_t(y_k).
+  * padding n = 2m (default) with the ring |d| = m of the kernel zero, or the
+    paper's n = 2m - 1.
+  * the cutoff keeps bins with qx^2 + qy^2 <= (alpha n eps / 2 pi)^2,
+    inclusive, with q in FFT order.
+  * the accurate operators S and N get a near-field correction
+    C = (exact Galerkin - Lambda^T G_grid Lambda) on pairs whose anchors are
+    within a Chebyshev distance R_near; S^alpha has none (eq. (10)).
+
+The grid product is evaluated here by a direct sum over the active grid
+points (the union of all stencils), which is the Toeplitz definition itself;
+the filtered kernel values come from one inverse DFT of the masked spectrum
+(the definition of c^alpha).  An FFT form of eq. (8) is kept only as a
+cross-check.
+
+Pinned by: tests/test_oracle_aim.py (moment reproduction of the stencil
+weights, FFT = direct Toeplitz sum, alpha >= sqrt(2) pi/eps is the identity
+filter, kept-bin fraction, symmetry x^T A y = y^T A x, S_AIM -> dense S,
+circle spectrum of S^alpha_AIM vs the analytic filter).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+from . import galerkin
+from .geometry import gauss_legendre01, segments
+from .green import green
+
+CHANNELS_S = ('phi',)
+CHANNELS_N = ('dphi', 'tx', 'ty')
+
+
+class GeometryError(ValueError):
+    pass
+
+
+class Grid:
+    def __init__(self, m: int, eps: float, pad: int = 0):
+        self.m = int(m)
+        self.eps = float(eps)
+        self.L = 0.5 * (self.m - 1) * self.eps
+        self.n = 2 * self.m if pad == 0 else 2 * self.m - 1
+        self.pad = pad
+
+    def coord(self, i):
+        return -self.L + np.asarray(i) * self.eps
+
+
+def lagrange_cubic(tt):
+    """Cubic Lagrange basis on nodes -1, 0, 1, 2 evaluated at tt: (..., 4)."""
+    tt = np.asarray(tt, dtype=float)
+    l0 = -tt * (tt - 1.0) * (tt - 2.0) / 6.0
+    l1 = (tt + 1.0) * (tt - 1.0) * (tt - 2.0) / 2.0
+    l2 = -(tt + 1.0) * tt * (tt - 2.0) / 2.0
+    l3 = (tt + 1.0) * tt * (tt - 1.0) / 6.0
+    return np.stack([l0, l1, l2, l3], axis=-1)
+
+
+def basis_centers(xy, basis):
+    xy = np.asarray(xy, dtype=float)
+    if basis == 0:
+        return 0.5 * (xy + np.roll(xy, -1, axis=0))
+    return xy.copy()
+
+
+def anchors(xy, basis, grid: Grid):
+    """Anchor cell (ix0, iy0) per basis: floor((c + L)/eps)."""
+    c = basis_centers(xy, basis)
+    a = np.floor((c + grid.L) / grid.eps).astype(np.int64)
+    if a.min() - 1 < 0 or a.max() + 2 > grid.m - 1:
+        raise GeometryError("stencil leaves the grid")
+    return a
+
+
+def stencil_weights(xy, basis, grid: Grid, p: int, channel: str):
+    """Weights W (N, 16) and grid linear indices G (N, 16) of one channel.
+
+    channel 'phi': v = phi_j; 'dphi': arc-length derivative; 'tx', 'ty':
+    tangent component times phi_j.  Entry e = t*4 + s, stencil point
+    (ix0 - 1 + s, iy0 - 1 + t)."""
+    xy = np.asarray(xy, dtype=float)
+    nb = xy.shape[0]
+    A0, A1, h, t, _ = segments(xy)
+    anc = anchors(xy, basis, grid)
+    tau, w = gauss_legendre01(p)
+    if basis == 0:
+        pieces = [(np.arange(nb), np.ones(nb), np.zeros(nb))]
+    else:
+        j = np.arange(nb)
+        pieces = [((j - 1) % nb, np.zeros(nb), np.ones(nb)),
+                  (j, np.ones(nb), -np.ones(nb))]
+    W = np.zeros((nb, 4, 4))
+    for seg, c0, c1 in pieces:
+        pts = A0[seg, None, :] + (A1 - A0)[seg, None, :] * tau[None, :, None]   # (nb,p,2)
+        wk = h[seg, None] * w[None, :]
+        phi = c0[:, None] + c1[:, None] * tau[None, :]
+        if channel == 'phi':
+            val = phi
+        elif channel == 'dphi':
+            val = np.broadcast_to((c1 / h[seg])[:, None], phi.shape)
+        elif channel == 'tx':
+            val = t[seg, 0][:, None] * phi
+        elif channel == 'ty':
+            val = t[seg, 1][:, None] * phi
+        else:
+            raise ValueError(channel)
+        tx = (pts[..., 0] + grid.L) / grid.eps - anc[:, 0, None]
+        ty = (pts[..., 1] + grid.L) / grid.eps - anc[:, 1, None]
+        lx = lagrange_cubic(tx)          # (nb,p,4)
+        ly = lagrange_cubic(ty)
+        W += np.einsum('bk,bkt,bks->bts', wk * val, ly, lx)
+    s = np.arange(4)
+    ix = anc[:, 0, None, None] - 1 + s[None, None, :]
+    iy = anc[:, 1, None, None] - 1 + s[None, :, None]
+    G = iy * grid.m + ix
+    return W.reshape(nb, 16), G.reshape(nb, 16)
+
+
+def kernel_table(grid: Grid, k: float):
+    """T[dy, dx] = g(eps |d|) for 0 <= dx, dy <= m-1, T[0, 0] = 0 (Sec. III-C)."""
+    d = np.arange(grid.m) * grid.eps
+    R = np.hypot(d[:, None], d[None, :])
+    T = np.zeros((grid.m, grid.m), dtype=complex)
+    nz = R > 0
+    T[nz] = green(R[nz], k)
+    return T
+
+
+def circulant_kernel(grid: Grid, T):
+    """Circulant embedding c (n x n, FFT order) of the Toeplitz kernel."""
+    n, m = grid.n, grid.m
+    q = np.arange(n)
+    d = np.where(q <= m - 1, q, q - n)
+    valid = np.abs(d) <= m - 1
+    ad = np.abs(d)
+    c = np.zeros((n, n), dtype=complex)
+    vy, vx = np.meshgrid(valid, valid, indexing='ij')
+    ay, ax = np.meshgrid(ad, ad, indexing='ij')
+    ok = vy & vx
+    c[ok] = T[ay[ok], ax[ok]]
+    return c
+
+
+def cutoff_threshold(grid: Grid, alpha: float) -> float:
+    """Integer-lattice form of |kappa| <= alpha with kappa = 2 pi q / (n eps)."""
+    return ((alpha * grid.n) * grid.eps / (2.0 * math.pi)) ** 2
+
+
+def filter_mask(grid: Grid, alpha: float):
+    n = grid.n
+    q = np.fft.fftfreq(n) * n
+    q = np.rint(q)
+    r2 = q[:, None] ** 2 + q[None, :] ** 2
+    if not math.isfinite(alpha):
+        return np.ones((n, n), dtype=bool)
+    return r2 <= cutoff_threshold(grid, alpha)
+
+
+def spectrum(grid: Grid, T):
+    """F(c_grid): unnormalised 2D DFT of the circulant kernel (eq. (8))."""
+    return np.fft.fft2(circulant_kernel(grid, T))
+
+
+def filtered_table(grid: Grid, T, alpha):
+    """Toeplitz table of c^alpha = F^-1(mask F(c_grid)) (Sec. III-B).
+
+    c^alpha is even in each axis, so the table over 0 <= dx, dy <= m-1
+    defines the whole restricted operator."""
+    C = spectrum(grid, T)
+    ca = np.fft.ifft2(C * filter_mask(grid, alpha))
+    return ca[:grid.m, :grid.m].copy(), ca
+
+
+class AimOracle:
+    """The discrete AIM operators of one geometry / frequency / grid."""
+
+    def __init__(self, xy, k, eta, basis, m, eps, p=10, near_radius=6, pad=0,
+                 alpha=math.inf, near=True, near_rows=None):
+        self.xy = np.asarray(xy, dtype=float)
+        self.k, self.eta, self.basis = float(k), float(eta), int(basis)
+        self.N = self.xy.shape[0]
+        self.grid = Grid(m, eps, pad)
+        self.p = p
+        self.R = near_radius
+        self.anc = anchors(self.xy, basis, self.grid)
+        chans = CHANNELS_S + (CHANNELS_N if basis == 1 else ())
+        self.W, self.Gidx = {}, {}
+        for ch in chans:
+            self.W[ch], self.Gidx[ch] = stencil_weights(self.xy, basis, self.grid, p, ch)
+        gidx = self.Gidx['phi']
+        self.act = np.unique(gidx)                       # sorted linear indices
+        self.aidx = np.searchsorted(self.act, gidx)      # (N, 16) active indices
+        self.act_ix = self.act % m
+        self.act_iy = self.act // m
+        self.T = kernel_table(self.grid, self.k)
+        self.Ta = None
+        self.alpha = None
+        self.set_alpha(alpha)
+        self.near_pairs = self._near_pairs() if near else None
+        self.Cnear = {}
+        if near:
+            rows = near_rows
+            self._build_near(('S', 'N') if basis == 1 else ('S',), rows)
+
+    # ------------------------------------------------------------------
+    def set_alpha(self, alpha):
+        self.alpha = alpha
+        self.Ta, _ = filtered_table(self.grid, self.T, alpha)
+
+    def _near_pairs(self):
+        tree = cKDTree(self.anc.astype(float))
+        pr = tree.query_pairs(r=self.R + 0.5, p=np.inf, output_type='ndarray')
+        idx = np.arange(self.N)
+        allp = np.concatenate([pr, pr[:, ::-1], np.stack([idx, idx], axis=1)])
+        order = np.lexsort((allp[:, 1], allp[:, 0]))
+        return allp[order]
+
+    def grid_block(self, table, rows_act, cols_act):
+        """Dense block K[a, b] = table[|dy|, |dx|] over active indices."""
+        dx = np.abs(self.act_ix[rows_act, None] - self.act_ix[None, cols_act])
+        dy = np.abs(self.act_iy[rows_act, None] - self.act_iy[None, cols_act])
+        return table[dy, dx]
+
+    def grid_pair_entries(self, table, pairs, ch_i, ch_j):
+        """(Lambda_i^T G Lambda_j) for basis pairs, 16 x 16 stencil sums."""
+        out = np.empty(pairs.shape[0], dtype=complex)
+        gi = self.Gidx['phi']
+        m = self.grid.m
+        chunk = 20000
+        for s in range(0, pairs.shape[0], chunk):
+            pi = pairs[s:s + chunk, 0]
+            pj = pairs[s:s + chunk, 1]
+            a = gi[pi]
+            b = gi[pj]
+            dx = np.abs((a % m)[:, :, None] - (b % m)[:, None, :])
+            dy = np.abs((a // m)[:, :, None] - (b // m)[:, None, :])
+            K = table[dy, dx]
+            out[s:s + chunk] = np.einsum('pe,pef,pf->p', self.W[ch_i][pi], K, self.W[ch_j][pj])
+        return out
+
+    def _build_near(self, ops, rows=None):
+        pairs = self.near_pairs
+        if rows is not None:
+            sel = np.isin(pairs[:, 0], np.asarray(rows))
+            pairs = pairs[sel]
+        self.near_sel_pairs = pairs
+        for op in ops:
+            exact = galerkin.assemble_entries(self.xy, self.basis, self.k, pairs, op,
+                                              p_far=16, p_near=16)
+            if op == 'S':
+                approx = self.grid_pair_entries(self.T, pairs, 'phi', 'phi')
+            else:
+                approx = self.grid_pair_entries(self.T, pairs, 'dphi', 'dphi') - self.k ** 2 * (
+                    self.grid_pair_entries(self.T, pairs, 'tx', 'tx')
+                    + self.grid_pair_entries(self.T, pairs, 'ty', 'ty'))
+            self.Cnear[op] = exact - approx
+
+    # ------------------------------------------------------------------
+    def anterpolate(self, ch, x):
+        """u_act = Lambda x for one channel (active grid points)."""
+        u = np.zeros((self.act.size,) + x.shape[1:], dtype=complex)
+        Wx = self.W[ch][..., None] * x[:, None, ...] if x.ndim == 2 else self.W[ch] * x[:, None]
+        np.add.at(u, self.aidx.ravel(), Wx.reshape((-1,) + x.shape[1:]))
+        return u
+
+    def interpolate(self, ch, v):
+        """y = Lambda^T v for one channel."""
+        g = v[self.aidx]                                  # (N,16,...)
+        if v.ndim == 2:
+            return np.einsum('ne,ner->nr', self.W[ch], g)
+        return np.einsum('ne,ne->n', self.W[ch], g)
+
+    def grid_apply(self, table, u, block=4096):
+        """v = K u over the active set by direct Toeplitz sums."""
+        na = self.act.size
+        v = np.zeros_like(u)
+        for s in range(0, na, block):
+            rows = np.arange(s, min(na, s + block))
+            for t0 in range(0, na, block):
+                cols = np.arange(t0, min(na, t0 + block))
+                v[rows] += self.grid_block(table, rows, cols) @ u[cols]
+        return v
+
+    def near_apply(self, op, x):
+        pairs = self.near_sel_pairs
+        C = self.Cnear[op]
+        y = np.zeros((self.N,) + x.shape[1:], dtype=complex)
+        contrib = C[:, None] * x[pairs[:, 1]] if x.ndim == 2 else C * x[pairs[:, 1]]
+        np.add.at(y, pairs[:, 0], contrib)
+        return y
+
+    def op_S(self, x, near=True):
+        y = self.interpolate('phi', self.grid_apply(self.T, self.anterpolate('phi', x)))
+        return y + self.near_apply('S', x) if near else y
+
+    def op_S_alpha(self, x):
+        return self.interpolate('phi', self.grid_apply(self.Ta, self.anterpolate('phi', x)))
+
+    def op_N(self, x, near=True):
+        y = self.interpolate('dphi', self.grid_apply(self.T, self.anterpolate('dphi', x)))
+        yt = (self.interpolate('tx', self.grid_apply(self.T, self.anterpolate('tx', x)))
+              + self.interpolate('ty', self.grid_apply(self.T, self.anterpolate('ty', x))))
+        y = y - self.k ** 2 * yt
+        return y + self.near_apply('N', x) if near else y
+
+    def gram_inv(self, x):
+        return galerkin.gram_solve(self.xy, self.basis, x)
+
+    def op_TM(self, x):
+        return 1j * self.k * self.eta * self.op_S(x)
+
+    def op_TE_CP(self, x, filtered=True):
+        z = self.gram_inv(self.op_N(x))
+        z = self.op_S_alpha(z) if filtered else self.op_S(z)
+        return self.gram_inv(z)
+
+    def apply(self, op, x):
+        x = np.asarray(x, dtype=complex)
+        return {
+            'S': self.op_S,
+            'S_ALPHA': self.op_S_alpha,
+            'N': self.op_N,
+            'GRAM_INV': self.gram_inv,
+            'TM': self.op_TM,
+            'TE_CP': lambda v: self.op_TE_CP(v, True),
+            'TE_CP_UNF': lambda v: self.op_TE_CP(v, False),
+        }[op](x)
+
+    # ------------------------------------------------------------------
+    def rows_apply(self, op, x, rows):
+        """Selected output rows of S, S_ALPHA or N (near field restricted to
+        the rows the oracle was built with)."""
+        rows = np.asarray(rows)
+        chans = {'S': ('phi',), 'S_ALPHA': ('phi',), 'N': CHANNELS_N}[op]
+        table = self.Ta if op == 'S_ALPHA' else self.T
+        need = np.unique(self.aidx[rows].ravel())
+        y = np.zeros(rows.size, dtype=complex)
+        allc = np.arange(self.act.size)
+        for ch in chans:
+            u = self.anterpolate(ch, x)
+            v = np.zeros(self.act.size, dtype=complex)
+            v[need] = self.grid_block(table, need, allc) @ u
+            yc = np.einsum('ne,ne->n', self.W[ch][rows], v[self.aidx[rows]])
+            y += yc if ch in ('phi', 'dphi') else -self.k ** 2 * yc
+        if op in ('S', 'N'):
+            full = self.near_apply(op, x)
+            y += full[rows]
+        return y
+
+    # ------------------------------------------------------------------
+    def grid_apply_fft(self, spectrum_full, u):
+        """Cross-check of eq. (8): pad, FFT, multiply, inverse FFT, restrict."""
+        n, m = self.grid.n, self.grid.m
+        b = np.zeros((n, n), dtype=complex)
+        b[self.act_iy, self.act_ix] = u
+        r = np.fft.ifft2(spectrum_full * np.fft.fft2(b))
+        return r[self.act_iy, self.act_ix]

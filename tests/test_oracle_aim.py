@@ -1,0 +1,213 @@
+"""Pins of oracle.aim: stencil weights, grid kernel, filter, near field."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import aim, galerkin, mie
+from oracle.geometry import gauss_legendre01, segments
+from paper_2606_10784_amd import workloads as wl
+
+K = 2 * math.pi
+
+
+def _small_star(n=60, a=1.0, eps=0.1):
+    xy = wl.star5(a, n)
+    return xy, wl.grid_side_for(xy, eps), eps
+
+
+@pytest.mark.parametrize("basis,channel", [(0, 'phi'), (1, 'phi'), (1, 'dphi'), (1, 'tx')])
+def test_stencil_reproduces_moments_to_degree_three(basis, channel):
+    """Cubic tensor Lagrange is exact on x^a y^b, a, b <= 3, so the stencil
+    weights must reproduce the quadrature moments of the basis function."""
+    xy, m, eps = _small_star()
+    grid = aim.Grid(m, eps)
+    W, G = aim.stencil_weights(xy, basis, grid, 10, channel)
+    X = grid.coord(G % m)
+    Y = grid.coord(G // m)
+    A0, A1, h, t, _ = segments(xy)
+    tau, w = gauss_legendre01(10)
+    nb = xy.shape[0]
+    for j in range(0, nb, 7):
+        if basis == 0:
+            pcs = [(j, 1.0, 0.0)]
+        else:
+            pcs = [((j - 1) % nb, 0.0, 1.0), (j, 1.0, -1.0)]
+        for a_ in range(4):
+            for b_ in range(4):
+                ref = 0.0
+                for s, c0, c1 in pcs:
+                    pts = A0[s] + np.outer(tau, A1[s] - A0[s])
+                    phi = c0 + c1 * tau
+                    val = {'phi': phi, 'dphi': np.full_like(tau, c1 / h[s]), 'tx': t[s, 0] * phi}[channel]
+                    ref += np.sum(w * h[s] * val * pts[:, 0] ** a_ * pts[:, 1] ** b_)
+                got = np.sum(W[j] * X[j] ** a_ * Y[j] ** b_)
+                scale = np.sum(np.abs(W[j])) * (np.max(np.abs(X[j])) + np.max(np.abs(Y[j]))) ** (a_ + b_)
+                assert abs(got - ref) < 1e-13 * scale
+
+
+def test_stencil_rejects_contour_leaving_grid():
+    xy = wl.circle(1.0, 32)
+    with pytest.raises(aim.GeometryError):
+        aim.stencil_weights(xy, 0, aim.Grid(16, 0.1), 4, 'phi')
+
+
+def _dft_matrix(n):
+    q = np.arange(n)
+    return np.exp(-2j * math.pi * np.outer(q, q) / n)
+
+
+@pytest.mark.parametrize("pad", [0, 1])
+def test_filtered_kernel_against_explicit_dft(pad):
+    """c^alpha = F^-1(mask . F(c)) written with explicit DFT matrices on a
+    tiny grid, then compared with the oracle table."""
+    grid = aim.Grid(6, 0.1, pad)
+    T = aim.kernel_table(grid, K)
+    c = aim.circulant_kernel(grid, T)
+    n = grid.n
+    F = _dft_matrix(n)
+    C = F @ c @ F.T
+    q = np.where(np.arange(n) <= n // 2 - (1 if n % 2 == 0 else 0), np.arange(n), np.arange(n) - n)
+    if n % 2 == 0:
+        q[n // 2] = -n // 2
+    alpha = 2.2 * math.pi / (n * grid.eps) * 2.0
+    kap = 2 * math.pi * q / (n * grid.eps)
+    mask = (kap[:, None] ** 2 + kap[None, :] ** 2) <= alpha ** 2
+    Finv = np.conj(F) / n
+    ca = Finv @ (mask * C) @ Finv.T
+    Ta, _ = aim.filtered_table(grid, T, alpha)
+    assert np.max(np.abs(Ta - ca[:6, :6])) < 1e-14 * np.max(np.abs(T))
+    # even symmetry of the filtered circulant kernel in each axis
+    idx = (-np.arange(n)) % n
+    assert np.max(np.abs(ca - ca[idx][:, idx])) < 1e-14 * np.max(np.abs(T))
+
+
+def test_circulant_embedding_ring_and_self_term():
+    grid = aim.Grid(8, 0.1)
+    T = aim.kernel_table(grid, K)
+    assert T[0, 0] == 0
+    c = aim.circulant_kernel(grid, T)
+    assert np.all(c[grid.m, :] == 0) and np.all(c[:, grid.m] == 0)
+    assert c[0, 0] == 0
+    assert c[3, grid.n - 2] == T[3, 2]
+
+
+def test_identity_filter_and_kept_fraction():
+    grid = aim.Grid(64, 0.1)
+    T = aim.kernel_table(grid, K)
+    Ta, _ = aim.filtered_table(grid, T, math.sqrt(2) * math.pi / grid.eps * 1.0001)
+    assert np.max(np.abs(Ta - T)) < 1e-14 * np.max(np.abs(T))
+    frac = aim.filter_mask(grid, wl.alpha_half_bins(grid.eps)).mean()
+    assert abs(frac - 0.5) < 1e-3
+
+
+@pytest.fixture(scope="module")
+def small_cyl():
+    """Circle a = 1, N = 128 pulses, grid 64 x 64 at lambda/10."""
+    xy = wl.circle(1.0, 128)
+    return xy, aim.AimOracle(xy, K, wl.ETA0, 0, 64, 0.1, alpha=wl.alpha_half_bins(0.1))
+
+
+def test_fft_equals_direct_toeplitz(small_cyl):
+    xy, A = small_cyl
+    x = wl.probe_vector(128, seed=1)
+    u = A.anterpolate('phi', x)
+    C = aim.spectrum(A.grid, A.T)
+    v1, v2 = A.grid_apply(A.T, u), A.grid_apply_fft(C, u)
+    assert np.linalg.norm(v1 - v2) < 1e-13 * np.linalg.norm(v1)
+    Ca = C * aim.filter_mask(A.grid, A.alpha)
+    v3, v4 = A.grid_apply(A.Ta, u), A.grid_apply_fft(Ca, u)
+    assert np.linalg.norm(v3 - v4) < 1e-13 * np.linalg.norm(v3)
+
+
+def test_operators_complex_symmetric(small_cyl):
+    xy, A = small_cyl
+    x, y = wl.probe_vector(128, seed=2), wl.probe_vector(128, seed=3)
+    for op in ('S', 'S_ALPHA', 'TM'):
+        a1, a2 = y @ A.apply(op, x), x @ A.apply(op, y)
+        assert abs(a1 - a2) < 1e-13 * abs(a1)
+
+
+def test_near_field_covering_all_pairs_reproduces_dense():
+    """With every pair in the near zone, AIM + correction equals the dense
+    Galerkin matrix exactly; this ties the 16 x 16 stencil sums of the
+    correction to the active-point Toeplitz product."""
+    xy = wl.circle(0.6, 48)
+    for basis in (0, 1):
+        A = aim.AimOracle(xy, K, wl.ETA0, basis, 32, 0.1, near_radius=64)
+        x = wl.probe_vector(48, seed=4)
+        for op in (('S', 'N') if basis == 1 else ('S',)):
+            D = galerkin.dense_matrix(xy, basis, K, op, p_far=16)
+            yd = D @ x
+            ya = A.apply(op, x)
+            assert np.linalg.norm(ya - yd) < 1e-13 * np.linalg.norm(yd)
+
+
+def test_self_term_value_is_irrelevant_with_near_field(small_cyl):
+    """R_near >= 3 keeps every pair that touches the grid self-term inside the
+    corrected zone, so the value of c[0] cannot change S_AIM."""
+    xy, A = small_cyl
+    x = wl.probe_vector(128, seed=5)
+    y0 = A.op_S(x)
+    B = aim.AimOracle(xy, K, wl.ETA0, 0, 64, 0.1, near=False)
+    B.T = B.T.copy()
+    B.T[0, 0] = 3.0 - 1.0j
+    B.near_pairs = A.near_pairs
+    B._build_near(('S',))
+    y1 = B.op_S(x)
+    assert np.linalg.norm(y1 - y0) < 1e-13 * np.linalg.norm(y0)
+
+
+def test_aim_converges_to_dense_with_grid_refinement():
+    """Cubic stencils: the far-interaction error drops ~h^4 when eps halves."""
+    xy = wl.circle(0.7, 160)
+    D = galerkin.dense_matrix(xy, 0, K, 'S')
+    x = wl.probe_vector(160, seed=6)
+    errs = []
+    for eps in (0.1, 0.05):
+        m = wl.grid_side_for(xy, eps)
+        A = aim.AimOracle(xy, K, wl.ETA0, 0, m, eps)
+        errs.append(np.linalg.norm(A.op_S(x) - D @ x) / np.linalg.norm(D @ x))
+    assert errs[0] < 1e-2
+    assert errs[1] < errs[0] / 6
+
+
+def test_numeric_filter_tracks_analytic_filter_on_circle():
+    """At paper-like parameters (alpha well below the grid Nyquist) the
+    Fourier-mode spectrum of S^alpha_AIM follows the analytic filtered
+    eigenvalues (eq. (6) on the circle), the gap shrinking as eps -> 0
+    (self-term argument of Sec. III-C), and decays past n = alpha a
+    (Sec. IV)."""
+    a, N = 1.0, 256
+    xy = wl.circle(a, N)
+    alpha = 3 * K
+    h = 2 * a * math.sin(math.pi / N)
+    th = 2 * math.pi * (np.arange(N) + 0.5) / N
+    ns = np.array([0, 3, 6, 9, 12, 15, 30, 36])
+    ex = mie.circle_eig_S_alpha(ns, K, a, alpha)
+    low = ns < 0.8 * alpha * a
+    high = ns > 1.3 * alpha * a
+    gaps = []
+    for eps, m in ((1.0 / 40, 128), (1.0 / 80, 256)):
+        A = aim.AimOracle(xy, K, wl.ETA0, 0, m, eps, alpha=alpha, near=False)
+        lam = np.array([np.vdot(np.exp(1j * n * th), A.op_S_alpha(np.exp(1j * n * th))) / (N * h)
+                        for n in ns])
+        gaps.append(np.abs(lam[low] - ex[low]) / np.abs(ex[low]))
+        assert np.all(np.abs(lam[high]) < 0.1 * np.abs(lam[0]))
+    assert np.all(gaps[1] < 4e-2)
+    assert np.all(gaps[1] < 0.55 * gaps[0])
+
+
+def test_row_sampled_evaluation_matches_full(small_cyl):
+    xy, A = small_cyl
+    rows = np.array([0, 17, 64, 127])
+    B = aim.AimOracle(xy, K, wl.ETA0, 0, 64, 0.1, alpha=A.alpha, near_rows=rows)
+    x = wl.probe_vector(128, seed=7)
+    for op in ('S', 'S_ALPHA'):
+        full = A.apply(op, x)[rows]
+        assert np.max(np.abs(B.rows_apply(op, x, rows) - full)) < 1e-13 * np.max(np.abs(full))
+    xh = wl.circle(0.6, 48)
+    C = aim.AimOracle(xh, K, wl.ETA0, 1, 32, 0.1)
+    D = aim.AimOracle(xh, K, wl.ETA0, 1, 32, 0.1, near_rows=[5, 30])
+    xx = wl.probe_vector(48, seed=8)
+    assert np.max(np.abs(D.rows_apply('N', xx, [5, 30]) - C.apply('N', xx)[[5, 30]])) < 1e-12 * np.max(np.abs(C.apply('N', xx)))
