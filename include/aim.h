@@ -1,0 +1,185 @@
+/*
+ * aim.h - C ABI of libaim: the Adaptive Integral Method (AIM) product for the
+ * Galerkin-discretised 2D EFIE with a numerically filtered grid kernel, and
+ * the restarted GMRES solve that applies it, on one AMD Instinct MI355X.
+ *
+ * Paper: "A Numerical Approach to Operator Filtering within the Adaptive
+ * Integral Method for Electromagnetic Integral Equations".
+ *   Sec. II, eqs. (1)-(4)   TE-EFIE with the hypersingular operator N, the
+ *                           single-layer operator S, Gram matrix G and the
+ *                           Calderon-preconditioned system G^-1 S G^-1 N
+ *   Sec. III-A, eqs. (7)-(8) quadrature factorisation and the AIM product
+ *                           Lambda^T [F^-1(F(c_grid) . F(b))]_restr
+ *   Sec. III-B, eq. (10)    numerical filter: F(c_grid) truncated to |kappa|<=alpha
+ *   Sec. III-C              self-interaction of the grid kernel set to zero
+ *
+ * Conventions
+ *  - Time convention e^{jwt}; g(R) = -(j/4) H0^(2)(kR).
+ *  - Complex vectors are interleaved (re, im) doubles ("c128"), column-major
+ *    N x nrhs (column r starts at element r*N).  All *_dev pointers are HIP
+ *    device pointers owned by the caller; *_host pointers are host memory.
+ *  - The library owns everything inside an aim_ctx (grid tables, spectra,
+ *    near field, work buffers); it allocates only in aim_setup / aim_solve
+ *    set-up, never inside aim_matvec.
+ *  - Every call returns an aim_status; on error the outputs are untouched
+ *    (except AIM_E_NOCONV, which returns the best iterate and its info).
+ *  - Calls are asynchronous on the context's stream except aim_setup, the
+ *    *_host outputs and aim_solve (which synchronises to test convergence).
+ *    A context is not thread-safe; distinct contexts may run concurrently on
+ *    distinct streams.
+ */
+#ifndef AIM_H
+#define AIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aim_ctx_s* aim_ctx;
+
+typedef enum {
+  AIM_OK = 0,
+  AIM_E_ARG = 1,      /* invalid argument (null pointer, size, enum)          */
+  AIM_E_GEOM = 2,     /* a 4x4 stencil leaves the m x m grid                   */
+  AIM_E_OOM = 3,      /* device allocation failed                              */
+  AIM_E_HIP = 4,      /* HIP runtime error                                     */
+  AIM_E_STATE = 5,    /* call not valid in this context state                  */
+  AIM_E_NOCONV = 6,   /* GMRES reached maxit; x holds the best iterate         */
+  AIM_E_NUMERIC = 7   /* NaN/Inf in a residual                                  */
+} aim_status;
+
+enum { AIM_PULSE = 0, AIM_HAT = 1 };
+
+/* Operators of aim_matvec (op argument).                                     */
+enum {
+  AIM_OP_S = 0,        /* S_AIM x: eq. (8) with the unfiltered kernel plus the
+                          near-field correction (exact Galerkin entries of
+                          eq. (4) minus their grid approximation)             */
+  AIM_OP_S_ALPHA = 1,  /* S^alpha x: eq. (10), filtered kernel, no near field */
+  AIM_OP_N = 2,        /* N_AIM x: Maue form of eq. (2) on three grid channels
+                          (phi', t_x phi, t_y phi) plus near field; hats only */
+  AIM_OP_GRAM_INV = 3, /* G^-1 x, G the Gram matrix of Sec. II                */
+  AIM_OP_TM = 4,       /* jk eta S_AIM x (TM-EFIE operator)                    */
+  AIM_OP_TE_CP = 5,    /* G^-1 S^alpha G^-1 N x, eq. (3) with S^alpha          */
+  AIM_OP_TE_CP_UNF = 6 /* G^-1 S_AIM G^-1 N x, eq. (3) unfiltered              */
+};
+/* OR-ed into op: run the grid part (maps + FFT convolution) in complex FP32;
+   the near field and the in/out vectors stay FP64.  Requires a context set up
+   with precision = AIM_MIXED.                                                */
+#define AIM_OP_GRID_FP32 0x100
+
+/* Systems of aim_solve (form argument).                                      */
+enum {
+  AIM_TM_EFIE = 0,                 /* jk eta S j = b                          */
+  AIM_TE_CALDERON = 1,             /* G^-1 S^a G^-1 N j = G^-1 S^a G^-1 b     */
+  AIM_TE_CALDERON_UNFILTERED = 2   /* G^-1 S G^-1 N j = G^-1 S G^-1 b          */
+};
+
+enum { AIM_FP64 = 0, AIM_MIXED = 1 };
+
+typedef struct {
+  int32_t n_vertices;     /* N >= 3: closed polygon, CCW, segment j = v_j -> v_{j+1} */
+  const double* xy;       /* host, 2N interleaved (x, y); copied during aim_setup   */
+  double k;               /* wavenumber (rad / length unit), > 0                    */
+  double eta;             /* medium impedance (ohm)                                 */
+  int32_t basis;          /* AIM_PULSE (TM systems) or AIM_HAT (TE systems)         */
+  int32_t m;              /* grid points per side (power of two, 16..4096)          */
+  double eps;             /* grid step; grid centred at 0, L = (m-1) eps / 2        */
+  int32_t quad;           /* Gauss-Legendre nodes per segment in the stencils (>=1) */
+  int32_t near_radius;    /* anchor Chebyshev radius of the near zone (>= 3)        */
+  int32_t precision;      /* AIM_FP64 or AIM_MIXED (also builds the FP32 grid data) */
+  int32_t max_rhs;        /* largest nrhs of later calls (>= 1)                     */
+  void* stream;           /* hipStream_t for all device work (NULL: default stream) */
+} aim_params;
+
+typedef struct {
+  int32_t n_unknowns, m, n_pad, n_active, active_rows, basis;
+  int64_t near_nnz_s, near_nnz_n;   /* nonzeros of the near-field corrections   */
+  double k, eps, alpha;             /* alpha = +inf when no filter is set        */
+  size_t device_bytes;              /* bytes held on the device by the context   */
+} aim_ctx_info;
+
+typedef struct {
+  int32_t iterations;    /* Arnoldi steps taken (inner steps for AIM_MIXED)     */
+  int32_t matvecs;       /* operator applications, all precisions               */
+  int32_t restarts;
+  int32_t outer;         /* iterative-refinement steps (AIM_MIXED), else 0      */
+  int32_t converged;     /* 1 if the stopping test was met                       */
+  double resid_est;      /* last Arnoldi residual estimate / ||b||              */
+  double resid_true;     /* ||b - A x|| / ||b|| with the FP64 operator            */
+  double seconds;        /* wall time of the call                                */
+} aim_solve_info;
+
+/* Device bytes aim_setup would allocate for these parameters (host-only
+   estimate used for admission control; no device call).                      */
+size_t aim_footprint_bytes(const aim_params* p, int32_t restart);
+
+/* Build a context: host geometry, Gauss-Legendre nodes (eq. (7)), stencil
+   weights and near-zone pairs; on the device the grid kernel samples with
+   the self term zeroed (Sec. III-C), its spectrum F(c_grid) (eq. (8)) and the
+   FP64 near-field correction.  Synchronous.  Errors: AIM_E_ARG, AIM_E_GEOM,
+   AIM_E_OOM, AIM_E_HIP.  On success *out owns device memory until
+   aim_destroy.                                                                */
+aim_status aim_setup(const aim_params* p, aim_ctx* out);
+
+/* Numerical filter of Sec. III-B: keep the spectral bins with
+   qx^2 + qy^2 <= (alpha n eps / 2 pi)^2 (q in FFT order, inclusive) of
+   F(c_grid), giving F(c_grid^alpha) for AIM_OP_S_ALPHA and the TE-CP
+   operator.  alpha = INFINITY keeps every bin.  Errors: AIM_E_ARG (alpha <= 0
+   or NaN).                                                                    */
+aim_status aim_filter(aim_ctx ctx, double alpha);
+
+/* y = op(x) for nrhs columns (1 <= nrhs <= max_rhs); x_dev and y_dev are
+   c128 N x nrhs device arrays and must not overlap.  Asynchronous.  Errors:
+   AIM_E_ARG (op invalid for the basis or precision), AIM_E_STATE.             */
+aim_status aim_matvec(aim_ctx ctx, int32_t op, int32_t nrhs, const void* x_dev, void* y_dev);
+
+/* Plane-wave right-hand sides, one column per angle (propagation direction
+   (cos phi, sin phi), amplitude amp): pulse basis b_i = <phi_i, E_z^inc>
+   (TM); hat basis b_i = <phi_i, (jk/eta) t.E^inc> with
+   E^inc = eta amp (z x khat) e^{-jk khat.r} (Sec. II).  b_dev: c128 N x nrhs.  */
+aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_host,
+                             double amp, void* b_dev);
+
+/* Solve the system of `form` for nrhs right-hand sides by restarted GMRES
+   (left-preconditioned for the Calderon forms, stopping when the Arnoldi
+   residual estimate of that system is <= tol ||b||).  x_dev holds the
+   initial guess on entry and the solution on exit.  precision AIM_MIXED
+   runs FP64 iterative refinement around an inner GMRES whose grid part is
+   FP32.  info_host: nrhs entries (may be NULL).  Synchronous.  Errors:
+   AIM_E_ARG, AIM_E_NOCONV, AIM_E_NUMERIC, AIM_E_OOM.                          */
+aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
+                     const void* b_dev, void* x_dev, double tol, int32_t maxit,
+                     int32_t restart, aim_solve_info* info_host);
+
+/* Monostatic TM scattering width sigma(phi_i) = (k eta^2 / 4)
+   |sum_j J_j <phi_j, e^{-jk khat_i.r}>|^2 for column i of j_dev (pulse basis,
+   solved at incidence phi_i).  sigma_host: nrhs doubles.  Synchronous.        */
+aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev,
+                              const double* phi_host, double* sigma_host);
+
+/* Introspection (sizes, nonzeros, device bytes).                              */
+aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info);
+
+/* Device evaluation of g(R) = -(j/4) H0^(2)(kR) at n distances (R_dev: n
+   doubles, out_dev: n c128), the kernel every grid sample and near-field
+   entry uses.  Exposed for verification.                                      */
+aim_status aim_eval_green(aim_ctx ctx, int32_t n, const void* R_dev, void* out_dev);
+
+/* Copy n entries of the context's near-field correction rows to host memory
+   (row i: columns and values of the FP64 correction of op AIM_OP_S or
+   AIM_OP_N).  cols_host may be NULL; returns the row length in *len.
+   Exposed for verification; synchronous.                                      */
+aim_status aim_near_row(aim_ctx ctx, int32_t op, int32_t row, int32_t cap,
+                        int32_t* cols_host, double* vals_host, int32_t* len);
+
+void aim_destroy(aim_ctx ctx);
+const char* aim_strerror(aim_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AIM_H */

@@ -1,0 +1,300 @@
+"""Python binding of libaim (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch provides device memory
+and the stream.  Vectors are complex128 CUDA tensors of shape (N,) or
+(nrhs, N) -- one right-hand side per row, i.e. the column-major N x nrhs
+layout of the C ABI.
+
+The names follow the C ABI (aim_setup, aim_filter, aim_matvec, aim_solve,
+...); `Context` wraps the opaque handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaim.so")
+
+AIM_OK, AIM_E_ARG, AIM_E_GEOM, AIM_E_OOM, AIM_E_HIP, AIM_E_STATE, AIM_E_NOCONV, AIM_E_NUMERIC = range(8)
+AIM_PULSE, AIM_HAT = 0, 1
+AIM_OP_S, AIM_OP_S_ALPHA, AIM_OP_N, AIM_OP_GRAM_INV, AIM_OP_TM, AIM_OP_TE_CP, AIM_OP_TE_CP_UNF = range(7)
+AIM_OP_GRID_FP32 = 0x100
+AIM_TM_EFIE, AIM_TE_CALDERON, AIM_TE_CALDERON_UNFILTERED = range(3)
+AIM_FP64, AIM_MIXED = 0, 1
+
+OPS = {'S': AIM_OP_S, 'S_ALPHA': AIM_OP_S_ALPHA, 'N': AIM_OP_N, 'GRAM_INV': AIM_OP_GRAM_INV,
+       'TM': AIM_OP_TM, 'TE_CP': AIM_OP_TE_CP, 'TE_CP_UNF': AIM_OP_TE_CP_UNF}
+FORMS = {'TM': AIM_TM_EFIE, 'TE_CP': AIM_TE_CALDERON, 'TE_CP_UNF': AIM_TE_CALDERON_UNFILTERED}
+
+
+class AimError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {_lib().aim_strerror(status).decode()} (status {status})")
+
+
+class AimParams(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int32), ("xy", ctypes.POINTER(ctypes.c_double)),
+                ("k", ctypes.c_double), ("eta", ctypes.c_double), ("basis", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("eps", ctypes.c_double), ("quad", ctypes.c_int32),
+                ("near_radius", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class AimCtxInfo(ctypes.Structure):
+    _fields_ = [("n_unknowns", ctypes.c_int32), ("m", ctypes.c_int32), ("n_pad", ctypes.c_int32),
+                ("n_active", ctypes.c_int32), ("active_rows", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("near_nnz_s", ctypes.c_int64), ("near_nnz_n", ctypes.c_int64), ("k", ctypes.c_double),
+                ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+
+class AimSolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("outer", ctypes.c_int32), ("converged", ctypes.c_int32), ("resid_est", ctypes.c_double),
+                ("resid_true", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_LIB = None
+
+EXPORTS = {
+    "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimParams), ctypes.c_int32]),
+    "aim_setup": (ctypes.c_int, [ctypes.POINTER(AimParams), ctypes.POINTER(ctypes.c_void_p)]),
+    "aim_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "aim_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "aim_rhs_planewave": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_double, ctypes.c_void_p]),
+    "aim_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(AimSolveInfo)]),
+    "aim_rcs_monostatic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimCtxInfo)]),
+    "aim_eval_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "aim_near_row": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int32)]),
+    "aim_destroy": (None, [ctypes.c_void_p]),
+    "aim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libaim.so not built ({LIB_PATH}); run paper_2606_10784_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(st, what):
+    if st != AIM_OK:
+        raise AimError(st, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_cols(x, N):
+    """(N,) or (nrhs, N) complex128 CUDA tensor -> (tensor, nrhs)."""
+    torch = _torch()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128):
+        raise TypeError("expected a complex128 CUDA tensor")
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if x.dim() == 1:
+        if x.shape[0] != N:
+            raise ValueError("length mismatch")
+        return x, 1
+    if x.dim() != 2 or x.shape[1] != N:
+        raise ValueError("expected shape (nrhs, N)")
+    return x, x.shape[0]
+
+
+def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1, stream=None):
+    arr = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+    p = AimParams()
+    p.n_vertices = arr.shape[0]
+    p.xy = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.k, p.eta, p.basis, p.m, p.eps = float(k), float(eta), int(basis), int(m), float(eps)
+    p.quad, p.near_radius, p.precision, p.max_rhs = int(quad), int(near_radius), int(precision), int(max_rhs)
+    p.stream = stream
+    return p, arr
+
+
+def aim_footprint_bytes(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
+                        restart=100):
+    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None)
+    return int(_lib().aim_footprint_bytes(ctypes.byref(p), int(restart)))
+
+
+class Context:
+    """Owns one aim_ctx (geometry, grid tables, spectra, near field)."""
+
+    def __init__(self, xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
+                 stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libaim needs a HIP device")
+        self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
+        p, self._xy = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs,
+                                  _stream_handle(self._stream_obj))
+        h = ctypes.c_void_p()
+        _check(_lib().aim_setup(ctypes.byref(p), ctypes.byref(h)), "aim_setup")
+        self._h = h
+        self.N = p.n_vertices
+        self.basis = basis
+        self.max_rhs = max_rhs
+        self.precision = precision
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().aim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = AimCtxInfo()
+        _check(_lib().aim_get_info(self._h, ctypes.byref(inf)), "aim_get_info")
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def filter(self, alpha):
+        return aim_filter(self, alpha)
+
+    def matvec(self, op, x, y=None):
+        return aim_matvec(self, op, x, y)
+
+    def solve(self, form, b, x0=None, tol=1e-6, maxit=5000, restart=100, precision=AIM_FP64):
+        return aim_solve(self, form, b, x0, tol, maxit, restart, precision)
+
+    def rhs_planewave(self, phis, amp=1.0):
+        return aim_rhs_planewave(self, phis, amp)
+
+    def rcs(self, J, phis):
+        return aim_rcs_monostatic(self, J, phis)
+
+    def eval_green(self, R):
+        return aim_eval_green(self, R)
+
+    def near_row(self, op, row):
+        return aim_near_row(self, op, row)
+
+
+def aim_setup(xy, k, eta, basis, m, eps, **kw):
+    return Context(xy, k, eta, basis, m, eps, **kw)
+
+
+def aim_filter(ctx, alpha):
+    _check(_lib().aim_filter(ctx.handle, float(alpha)), "aim_filter")
+
+
+def aim_matvec(ctx, op, x, y=None):
+    torch = _torch()
+    opc = OPS[op] if isinstance(op, str) else int(op)
+    x, nrhs = _as_cols(x, ctx.N)
+    if y is None:
+        y = torch.empty_like(x)
+    _as_cols(y, ctx.N)
+    _check(_lib().aim_matvec(ctx.handle, opc, nrhs, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())),
+           "aim_matvec")
+    return y
+
+
+def aim_rhs_planewave(ctx, phis, amp=1.0):
+    torch = _torch()
+    ph = np.ascontiguousarray(np.atleast_1d(np.asarray(phis, dtype=np.float64)))
+    b = torch.empty((ph.size, ctx.N), dtype=torch.complex128, device="cuda")
+    _check(_lib().aim_rhs_planewave(ctx.handle, ph.size, ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    float(amp), ctypes.c_void_p(b.data_ptr())), "aim_rhs_planewave")
+    return b[0] if np.ndim(phis) == 0 else b
+
+
+def aim_solve(ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100, precision=AIM_FP64):
+    """Returns (x, [info dict per rhs]); raises AimError unless converged."""
+    torch = _torch()
+    fc = FORMS[form] if isinstance(form, str) else int(form)
+    b, nrhs = _as_cols(b, ctx.N)
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    infos = (AimSolveInfo * nrhs)()
+    st = _lib().aim_solve(ctx.handle, fc, int(precision), nrhs, ctypes.c_void_p(b.data_ptr()),
+                          ctypes.c_void_p(x.data_ptr()), float(tol), int(maxit), int(restart), infos)
+    out = [infos[i].as_dict() for i in range(nrhs)]
+    if st not in (AIM_OK, AIM_E_NOCONV):
+        raise AimError(st, "aim_solve")
+    if st == AIM_E_NOCONV:
+        for d in out:
+            d['status'] = 'noconv'
+    return x, out
+
+
+def aim_rcs_monostatic(ctx, J, phis):
+    J, nrhs = _as_cols(J, ctx.N)
+    ph = np.ascontiguousarray(np.atleast_1d(np.asarray(phis, dtype=np.float64)))
+    if ph.size != nrhs:
+        raise ValueError("one angle per current column")
+    sig = np.zeros(nrhs)
+    _check(_lib().aim_rcs_monostatic(ctx.handle, nrhs, ctypes.c_void_p(J.data_ptr()),
+                                     ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "aim_rcs_monostatic")
+    return sig
+
+
+def aim_eval_green(ctx, R):
+    torch = _torch()
+    R = R.contiguous()
+    out = torch.empty(R.shape, dtype=torch.complex128, device="cuda")
+    _check(_lib().aim_eval_green(ctx.handle, R.numel(), ctypes.c_void_p(R.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr())), "aim_eval_green")
+    return out
+
+
+def aim_near_row(ctx, op, row):
+    opc = OPS[op] if isinstance(op, str) else int(op)
+    n = ctypes.c_int32()
+    _check(_lib().aim_near_row(ctx.handle, opc, int(row), 0, None, None, ctypes.byref(n)), "aim_near_row")
+    cols = np.zeros(n.value, dtype=np.int32)
+    vals = np.zeros(2 * n.value, dtype=np.float64)
+    _check(_lib().aim_near_row(ctx.handle, opc, int(row), n.value,
+                               cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)),
+           "aim_near_row")
+    return cols, vals[0::2] + 1j * vals[1::2]
+
+
+def header_functions(path=None):
+    """Function names declared in include/aim.h (for export checks)."""
+    import re
+    path = path or os.path.join(os.path.dirname(_HERE), "include", "aim.h")
+    txt = open(path).read()
+    decl = r"^(?:aim_status|size_t|void|const\s+char\s*\*)\s*(aim_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, txt, flags=re.M)))

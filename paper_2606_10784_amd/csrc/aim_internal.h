@@ -1,0 +1,151 @@
+// Internal declarations of libaim (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/aim.h"
+
+namespace aim {
+
+// ---------------------------------------------------------------------------
+// complex helpers (interleaved re/im, HIP vector types)
+// ---------------------------------------------------------------------------
+template <typename T> struct CT;
+template <> struct CT<double> { using type = double2; };
+template <> struct CT<float> { using type = float2; };
+template <typename T> using cplx = typename CT<T>::type;
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T x, T y) { cplx<T> r; r.x = x; r.y = y; return r; }
+template <typename V>
+__host__ __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V>
+__host__ __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V>
+__host__ __device__ __forceinline__ V cmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// a * conj(b)
+template <typename V>
+__host__ __device__ __forceinline__ V cmulc(V a, V b) {
+  V r; r.x = a.x * b.x + a.y * b.y; r.y = a.y * b.x - a.x * b.y; return r;
+}
+template <typename V, typename S>
+__host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
+
+// ---------------------------------------------------------------------------
+// host-side geometry and tables produced by aim_setup (host_setup.cpp)
+// ---------------------------------------------------------------------------
+struct HostTables {
+  int N = 0, basis = 0, m = 0, n = 0, p = 0, R = 0, nch = 1;
+  double k = 0, eta = 0, eps = 0, L = 0;
+  std::vector<double> vx, vy;                 // vertices
+  std::vector<double> h, tx, ty;              // per segment
+  std::vector<int32_t> anc_x, anc_y;          // anchor cells per basis
+  // channels: 0 = phi, 1 = dphi, 2 = t_x phi, 3 = t_y phi (hats use all four)
+  std::vector<double> W[4];                   // N x 16 per channel
+  std::vector<int32_t> aidx;                  // N x 16 active index of each stencil point
+  std::vector<int32_t> act_ix, act_iy;        // active points, sorted row-major
+  int n_act = 0, y0 = 0, nr = 0;              // active rows [y0, y0 + nr)
+  std::vector<int32_t> row_ptr;               // nr + 1 offsets into the active list
+  // transposed stencils: for active point a, entries [at_ptr[a], at_ptr[a+1])
+  std::vector<int32_t> at_ptr, at_basis;
+  std::vector<double> at_w[4];
+  // near zone (CSR over basis rows, sorted columns)
+  std::vector<int32_t> nr_ptr, nr_col;
+  std::vector<double> gl_x, gl_w;             // stencil quadrature rule on [0,1]
+};
+
+// Fills everything above; returns AIM_E_ARG / AIM_E_GEOM on bad input.
+aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& err);
+void gauss_legendre01(int p, std::vector<double>& x, std::vector<double>& w);
+// Twiddle table tw[j] = exp(-2 pi i j / n), j < n, correctly rounded.
+void twiddles(int n, std::vector<double>& re_im);
+
+// ---------------------------------------------------------------------------
+// device context
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct GmresWork {
+  int restart = 0, nrhs = 0;
+  double2 *V = nullptr, *W = nullptr, *H = nullptr, *g = nullptr, *cs = nullptr, *sn = nullptr,
+          *y = nullptr, *hcol = nullptr, *part = nullptr, *r = nullptr, *x64 = nullptr, *d = nullptr,
+          *b2 = nullptr, *nrm = nullptr;
+  double *bnorm = nullptr, *resid = nullptr, *hn = nullptr;
+  int *active = nullptr;
+  double* host_resid = nullptr;   // pinned
+  int nchunk = 0;
+  size_t bytes = 0;
+};
+
+struct Ctx {
+  HostTables t;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int precision = AIM_FP64;
+  int max_rhs = 1;
+  int nch_max = 1;          // grid channels of the widest operator
+  double alpha = 0;         // current filter cutoff (inf: none)
+  bool filtered = false;
+  // geometry
+  double *d_vx = nullptr, *d_vy = nullptr, *d_h = nullptr, *d_tx = nullptr, *d_ty = nullptr;
+  double *d_glx = nullptr, *d_glw = nullptr;
+  // stencils / maps
+  double* d_W[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* d_Wf[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t* d_aidx = nullptr;
+  int32_t *d_act_ix = nullptr, *d_row_ptr = nullptr;
+  int32_t *d_at_ptr = nullptr, *d_at_basis = nullptr;
+  double* d_at_w[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* d_at_wf[4] = {nullptr, nullptr, nullptr, nullptr};
+  // spectra (quarter, [kxq][kyq], pre-scaled by 1/n^2)
+  double2 *d_C = nullptr, *d_Ca = nullptr;
+  float2 *d_Cf = nullptr, *d_Caf = nullptr;
+  double2* d_tw = nullptr;
+  float2* d_twf = nullptr;
+  double2* d_ksmall = nullptr;   // kernel at offsets |d| <= R+3 (rows dy, cols dx)
+  int ks = 0;
+  // near field
+  int32_t *d_nr_ptr = nullptr, *d_nr_col = nullptr;
+  double2 *d_CS = nullptr, *d_CN = nullptr;
+  int64_t nnz = 0;
+  // matvec work (sized for max_rhs x nch_max)
+  void *d_U = nullptr, *d_T = nullptr, *d_V = nullptr;
+  double2 *d_tmp1 = nullptr, *d_tmp2 = nullptr;   // N x max_rhs each
+  double2* d_rhs = nullptr;
+  double* d_red = nullptr;
+  size_t dev_bytes = 0;
+  GmresWork gw;
+  std::vector<void*> allocs;
+};
+
+// kernels / launchers (aim_kernels.hip)
+aim_status dev_alloc(Ctx* c, void** p, size_t bytes);
+aim_status setup_device(Ctx* c);                        // tables, spectrum, near field
+aim_status apply_filter(Ctx* c, double alpha);
+// y(:, r) = op x(:, r), column strides ldx / ldy (elements), FP64 vectors
+aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy);
+aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b);
+aim_status eval_green(Ctx* c, int n, const double* R, double2* out);
+aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma);
+aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
+                 int maxit, int restart, aim_solve_info* info);
+void free_ctx(Ctx* c);
+size_t footprint(const aim_params* p, int restart, const HostTables* t);
+
+#define AIM_HIP_CHECK(call)                                  \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return AIM_E_HIP;                  \
+  } while (0)
+
+}  // namespace aim

@@ -1,0 +1,179 @@
+// C ABI of libaim (declared in include/aim.h).
+#include <cmath>
+#include <cstdio>
+#include <new>
+
+#include "aim_internal.h"
+
+using namespace aim;
+
+struct aim_ctx_s {
+  Ctx c;
+};
+
+namespace aim {
+
+void free_ctx(Ctx* c) {
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  for (void* p : c->allocs) hipFree(p);
+  c->allocs.clear();
+  GmresWork& w = c->gw;
+  for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
+                  (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
+                  (void*)w.resid, (void*)w.hn, (void*)w.active})
+    if (p) hipFree(p);
+  if (w.host_resid) hipHostFree(w.host_resid);
+  w = GmresWork();
+}
+
+size_t footprint(const aim_params* p, int restart, const HostTables* t) {
+  // grid work + spectra + near field + stencils + Krylov space
+  const size_t N = p->n_vertices, m = p->m, n = 2 * m, R = p->max_rhs;
+  const size_t nch = p->basis == AIM_HAT ? 3 : 1;
+  const size_t H = n / 2 + 1;
+  const size_t nr = t ? t->nr : m;
+  const size_t nact = t ? t->n_act : 16 * N;
+  const size_t near = t ? t->nr_col.size() : N * (size_t)((2 * p->near_radius + 1) * 3);
+  size_t b = 0;
+  b += nch * R * (nr * n + 2 * nact) * 16;               // U, T, V
+  b += 2 * H * H * 16 * (p->precision == AIM_MIXED ? 1.5 : 1.0);
+  b += near * (4 + 16 * (p->basis == AIM_HAT ? 2 : 1));
+  b += N * 16 * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
+  b += 3 * N * R * 16;
+  b += (size_t)R * (restart + 1) * N * 16 + (size_t)5 * R * N * 16;
+  return b;
+}
+
+}  // namespace aim
+
+extern "C" {
+
+const char* aim_strerror(aim_status s) {
+  switch (s) {
+    case AIM_OK: return "ok";
+    case AIM_E_ARG: return "invalid argument";
+    case AIM_E_GEOM: return "stencil leaves the grid";
+    case AIM_E_OOM: return "device allocation failed";
+    case AIM_E_HIP: return "HIP runtime error";
+    case AIM_E_STATE: return "invalid context state";
+    case AIM_E_NOCONV: return "GMRES did not converge";
+    case AIM_E_NUMERIC: return "non-finite residual";
+  }
+  return "unknown status";
+}
+
+size_t aim_footprint_bytes(const aim_params* p, int32_t restart) {
+  if (!p || p->n_vertices < 1 || p->m < 1 || p->max_rhs < 1 || restart < 1) return 0;
+  return footprint(p, restart, nullptr);
+}
+
+aim_status aim_setup(const aim_params* p, aim_ctx* out) {
+  if (!p || !out) return AIM_E_ARG;
+  *out = nullptr;
+  if (p->precision != AIM_FP64 && p->precision != AIM_MIXED) return AIM_E_ARG;
+  aim_ctx_s* h = new (std::nothrow) aim_ctx_s();
+  if (!h) return AIM_E_OOM;
+  Ctx* c = &h->c;
+  std::string err;
+  aim_status st = build_host_tables(p, c->t, err);
+  if (st != AIM_OK) {
+    delete h;
+    return st;
+  }
+  c->stream = (hipStream_t)p->stream;
+  c->precision = p->precision;
+  c->max_rhs = p->max_rhs;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete h;
+    return AIM_E_HIP;
+  }
+  st = setup_device(c);
+  if (st != AIM_OK) {
+    free_ctx(c);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return AIM_OK;
+}
+
+aim_status aim_filter(aim_ctx ctx, double alpha) {
+  if (!ctx || std::isnan(alpha) || !(alpha > 0)) return AIM_E_ARG;
+  return apply_filter(&ctx->c, alpha);
+}
+
+aim_status aim_matvec(aim_ctx ctx, int32_t op, int32_t nrhs, const void* x_dev, void* y_dev) {
+  if (!ctx || !x_dev || !y_dev || x_dev == y_dev) return AIM_E_ARG;
+  const int64_t N = ctx->c.t.N;
+  return matvec(&ctx->c, op, nrhs, (const double2*)x_dev, N, (double2*)y_dev, N);
+}
+
+aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_host, double amp, void* b_dev) {
+  if (!ctx || !phi_inc_host || !b_dev || nrhs < 1) return AIM_E_ARG;
+  return rhs_planewave(&ctx->c, nrhs, phi_inc_host, amp, (double2*)b_dev);
+}
+
+aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev, void* x_dev,
+                     double tol, int32_t maxit, int32_t restart, aim_solve_info* info_host) {
+  if (!ctx || !b_dev || !x_dev || b_dev == x_dev) return AIM_E_ARG;
+  return solve(&ctx->c, form, precision, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart,
+               info_host);
+}
+
+aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev, const double* phi_host,
+                              double* sigma_host) {
+  if (!ctx || !j_dev || !phi_host || !sigma_host) return AIM_E_ARG;
+  return rcs(&ctx->c, nrhs, (const double2*)j_dev, phi_host, sigma_host);
+}
+
+aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info) {
+  if (!ctx || !info) return AIM_E_ARG;
+  const Ctx& c = ctx->c;
+  info->n_unknowns = c.t.N;
+  info->m = c.t.m;
+  info->n_pad = c.t.n;
+  info->n_active = c.t.n_act;
+  info->active_rows = c.t.nr;
+  info->basis = c.t.basis;
+  info->near_nnz_s = c.nnz;
+  info->near_nnz_n = c.t.basis == AIM_HAT ? c.nnz : 0;
+  info->k = c.t.k;
+  info->eps = c.t.eps;
+  info->alpha = c.filtered ? c.alpha : INFINITY;
+  info->device_bytes = c.dev_bytes;
+  return AIM_OK;
+}
+
+aim_status aim_eval_green(aim_ctx ctx, int32_t n, const void* R_dev, void* out_dev) {
+  if (!ctx || (n > 0 && (!R_dev || !out_dev))) return AIM_E_ARG;
+  return eval_green(&ctx->c, n, (const double*)R_dev, (double2*)out_dev);
+}
+
+aim_status aim_near_row(aim_ctx ctx, int32_t op, int32_t row, int32_t cap, int32_t* cols_host, double* vals_host,
+                        int32_t* len) {
+  if (!ctx || !len) return AIM_E_ARG;
+  Ctx& c = ctx->c;
+  if (row < 0 || row >= c.t.N) return AIM_E_ARG;
+  const double2* C = op == AIM_OP_S ? c.d_CS : (op == AIM_OP_N ? c.d_CN : nullptr);
+  if (!C) return AIM_E_ARG;
+  const int q0 = c.t.nr_ptr[row], q1 = c.t.nr_ptr[row + 1];
+  *len = q1 - q0;
+  const int cnt = std::min(cap, q1 - q0);
+  if (cnt > 0 && cols_host)
+    for (int q = 0; q < cnt; ++q) cols_host[q] = c.t.nr_col[q0 + q];
+  if (cnt > 0 && vals_host) {
+    if (hipMemcpyAsync(vals_host, C + q0, (size_t)cnt * 16, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+      return AIM_E_HIP;
+    if (hipStreamSynchronize(c.stream) != hipSuccess) return AIM_E_HIP;
+  }
+  return AIM_OK;
+}
+
+void aim_destroy(aim_ctx ctx) {
+  if (!ctx) return;
+  free_ctx(&ctx->c);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,525 @@
+// Restarted GMRES on the device for the AIM systems (FP64 Krylov space).
+//
+// The paper applies its operators inside iterative solvers (abstract, Sec. I)
+// without naming one; this is GMRES(restart) with classical Gram-Schmidt run
+// twice (CGS2) and complex Givens rotations, one independent Krylov space per
+// right-hand side.  Each Arnoldi step is one batched operator application
+// plus a handful of small kernels; the only per-step device-to-host transfer
+// is the residual estimate (8 bytes per right-hand side).  Reductions use a
+// fixed chunking and order, so results do not depend on which other
+// right-hand sides share the batch.
+//
+// AIM_MIXED: iterative refinement  x <- x + d,  A_mixed d ~ b - A_64 x, where
+// A_mixed runs the grid part in complex FP32 and everything else in FP64.
+#include <chrono>
+#include <cmath>
+
+#include "aim_internal.h"
+
+namespace aim {
+
+static constexpr int RED_CHUNK = 2048;
+
+// partial sums of conj(V_i) . w over a chunk, or |w|^2 when V == nullptr
+__global__ __launch_bounds__(256) void k_dots(int N, const double2* __restrict__ V, int64_t ld_rhs_v,
+                                              const double2* __restrict__ w, int64_t ld_w,
+                                              const int* __restrict__ active, double2* __restrict__ part,
+                                              int nchunk, int jmax) {
+  const int chunk = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
+  if (!active[r]) return;
+  const double2* vi = V ? V + (size_t)r * ld_rhs_v + (size_t)i * N : nullptr;
+  const double2* wr = w + (size_t)r * ld_w;
+  double sx = 0, sy = 0;
+  const int n0 = chunk * RED_CHUNK, n1 = min(N, n0 + RED_CHUNK);
+  for (int n = n0 + threadIdx.x; n < n1; n += 256) {
+    const double2 b = wr[n];
+    if (vi) {
+      const double2 a = vi[n];
+      sx += a.x * b.x + a.y * b.y;
+      sy += a.x * b.y - a.y * b.x;
+    } else {
+      sx += b.x * b.x + b.y * b.y;
+    }
+  }
+  __shared__ double rx[256], ry[256];
+  rx[threadIdx.x] = sx;
+  ry[threadIdx.x] = sy;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rx[threadIdx.x] += rx[threadIdx.x + s];
+      ry[threadIdx.x] += ry[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[((size_t)r * jmax + i) * nchunk + chunk] = make_double2(rx[0], ry[0]);
+}
+
+// out[r][i] = sum_chunk part (fixed order); mode 1: accumulate into H column
+__global__ void k_reduce(int nrhs, int j1, int nchunk, int jmax, const double2* part, const int* active,
+                         double2* out, int64_t ld_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= j1 || !active[r]) return;
+  double sx = 0, sy = 0;
+  const double2* p = part + ((size_t)r * jmax + i) * nchunk;
+  for (int c = 0; c < nchunk; ++c) { sx += p[c].x; sy += p[c].y; }
+  out[(size_t)r * ld_out + i] = make_double2(sx, sy);
+}
+
+// w[r] += sgn * sum_i V[r][i] c[r][i]
+__global__ void k_gemv(int N, int j1, const double2* __restrict__ V, int64_t ld_rhs_v,
+                       const double2* __restrict__ c, int64_t ld_c, double sgn, const int* __restrict__ active,
+                       double2* __restrict__ w, int64_t ld_w) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= N || !active[r]) return;
+  const double2* vr = V + (size_t)r * ld_rhs_v;
+  const double2* cr = c + (size_t)r * ld_c;
+  double sx = 0, sy = 0;
+  for (int i = 0; i < j1; ++i) {
+    const double2 a = vr[(size_t)i * N + n], b = cr[i];
+    sx += a.x * b.x - a.y * b.y;
+    sy += a.x * b.y + a.y * b.x;
+  }
+  double2 o = w[(size_t)r * ld_w + n];
+  w[(size_t)r * ld_w + n] = make_double2(o.x + sgn * sx, o.y + sgn * sy);
+}
+
+// H[:, j] (+)= h ; keeps the first CGS pass
+__global__ void k_hacc(int j1, int nrhs, int ldh, int j, const double2* h, int64_t ld_h, int first,
+                       const int* active, double2* H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= j1 || !active[r]) return;
+  double2* Hc = H + (size_t)r * ldh * (ldh - 1) + (size_t)j * ldh;
+  const double2 v = h[(size_t)r * ld_h + i];
+  if (first) Hc[i] = v;
+  else Hc[i] = make_double2(Hc[i].x + v.x, Hc[i].y + v.y);
+}
+
+// v = w / ||w||   (||w|| from the reduction); also records H[j+1, j]
+__global__ void k_normalize(int N, const double2* nrm2, int64_t ld_n, const double2* __restrict__ w, int64_t ld_w,
+                            double2* __restrict__ v, int64_t ld_rhs_v, const int* __restrict__ active, double* hn) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (!active[r]) return;
+  const double nr = sqrt(nrm2[(size_t)r * ld_n].x);
+  if (n == 0) hn[r] = nr;
+  if (n >= N) return;
+  const double s = nr > 0 ? 1.0 / nr : 0.0;
+  const double2 a = w[(size_t)r * ld_w + n];
+  v[(size_t)r * ld_rhs_v + n] = make_double2(a.x * s, a.y * s);
+}
+
+// residual r = b - r (in place on r)
+__global__ void k_bminus(int N, const double2* b, double2* r) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (n >= N) return;
+  const double2 bb = b[(size_t)c * N + n], rr = r[(size_t)c * N + n];
+  r[(size_t)c * N + n] = make_double2(bb.x - rr.x, bb.y - rr.y);
+}
+
+__global__ void k_axpy(int N, const double2* d, double2* x) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (n >= N) return;
+  const double2 a = d[(size_t)c * N + n], o = x[(size_t)c * N + n];
+  x[(size_t)c * N + n] = make_double2(o.x + a.x, o.y + a.y);
+}
+
+// Givens update of column j (one thread per right-hand side)
+__global__ void k_givens(int nrhs, int ldh, int j, const double* hn, const int* active, double2* H, double2* cs,
+                         double2* sn, double2* g, double* resid) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  const int R = ldh - 1;
+  double2* Hc = H + (size_t)r * ldh * R + (size_t)j * ldh;
+  double2* c = cs + (size_t)r * R;
+  double2* s = sn + (size_t)r * R;
+  double2* gg = g + (size_t)r * ldh;
+  Hc[j + 1] = make_double2(hn[r], 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double ci = c[i].x;
+    const double2 si = s[i];
+    const double2 a = Hc[i], b = Hc[i + 1];
+    // [c s; -conj(s) c]
+    const double2 t = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
+    const double2 u = make_double2(-(si.x * a.x + si.y * a.y) + ci * b.x, -(si.x * a.y - si.y * a.x) + ci * b.y);
+    Hc[i] = t;
+    Hc[i + 1] = u;
+  }
+  const double2 a = Hc[j], b = Hc[j + 1];
+  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+  const double den = hypot(na, nb);
+  double ci;
+  double2 si;
+  if (na == 0.0) {
+    ci = 0.0;
+    si = make_double2(1.0, 0.0);
+  } else {
+    ci = na / den;
+    // s = (a/|a|) conj(b) / den
+    const double2 ph = make_double2(a.x / na, a.y / na);
+    si = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);
+  }
+  c[j] = make_double2(ci, 0.0);
+  s[j] = si;
+  Hc[j] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
+  Hc[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = gg[j];
+  gg[j + 1] = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));
+  gg[j] = make_double2(ci * gj.x, ci * gj.y);
+  resid[r] = hypot(gg[j + 1].x, gg[j + 1].y);
+}
+
+// y = H^-1 g (upper triangular, jm x jm), one thread per right-hand side
+__global__ void k_trisolve(int nrhs, int ldh, const int* jm, const double2* H, const double2* g, double2* y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  const int R = ldh - 1;
+  const int m = jm[r];
+  const double2* Hr = H + (size_t)r * ldh * R;
+  const double2* gr = g + (size_t)r * ldh;
+  double2* yr = y + (size_t)r * R;
+  for (int i = m - 1; i >= 0; --i) {
+    double sx = gr[i].x, sy = gr[i].y;
+    for (int k = i + 1; k < m; ++k) {
+      const double2 h = Hr[(size_t)k * ldh + i], v = yr[k];
+      sx -= h.x * v.x - h.y * v.y;
+      sy -= h.x * v.y + h.y * v.x;
+    }
+    const double2 d = Hr[(size_t)i * ldh + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    yr[i] = make_double2((sx * d.x + sy * d.y) / dd, (sy * d.x - sx * d.y) / dd);
+  }
+}
+
+__global__ void k_set_g0(int nrhs, int ldh, const double2* nrm2, const int* active, double2* g) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  g[(size_t)r * ldh] = make_double2(sqrt(nrm2[r].x), 0.0);
+  for (int i = 1; i < ldh; ++i) g[(size_t)r * ldh + i] = make_double2(0, 0);
+}
+
+// ---------------------------------------------------------------------------
+static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
+  GmresWork& w = c->gw;
+  if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
+  for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
+                  (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
+                  (void*)w.resid, (void*)w.hn, (void*)w.active})
+    if (p) hipFree(p);
+  if (w.host_resid) hipHostFree(w.host_resid);
+  c->dev_bytes -= w.bytes;
+  w = GmresWork();
+  const int N = c->t.N;
+  const int ldh = restart + 1;
+  w.restart = restart;
+  w.nrhs = nrhs;
+  w.nchunk = (N + RED_CHUNK - 1) / RED_CHUNK;
+  size_t tot = 0;
+  auto A = [&](void** p, size_t b) -> bool {
+    tot += b;
+    if (hipMalloc(p, b) != hipSuccess) return false;
+    return hipMemset(*p, 0, b) == hipSuccess;
+  };
+  bool ok = A((void**)&w.V, (size_t)nrhs * ldh * N * 16) && A((void**)&w.W, (size_t)nrhs * N * 16) &&
+            A((void**)&w.H, (size_t)nrhs * ldh * restart * 16) && A((void**)&w.g, (size_t)nrhs * ldh * 16) &&
+            A((void**)&w.cs, (size_t)nrhs * restart * 16) && A((void**)&w.sn, (size_t)nrhs * restart * 16) &&
+            A((void**)&w.y, (size_t)nrhs * restart * 16) && A((void**)&w.hcol, (size_t)nrhs * ldh * 16) &&
+            A((void**)&w.part, (size_t)nrhs * ldh * w.nchunk * 16) && A((void**)&w.r, (size_t)nrhs * N * 16) &&
+            A((void**)&w.d, (size_t)nrhs * N * 16) && A((void**)&w.b2, (size_t)nrhs * N * 16) &&
+            A((void**)&w.nrm, (size_t)nrhs * 2 * 16) && A((void**)&w.bnorm, (size_t)nrhs * 8) &&
+            A((void**)&w.resid, (size_t)nrhs * 8) && A((void**)&w.hn, (size_t)nrhs * 8) &&
+            A((void**)&w.active, (size_t)nrhs * 4 * 2);
+  if (!ok) return AIM_E_OOM;
+  if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * 8 * 4) != hipSuccess) return AIM_E_OOM;
+  w.bytes = tot;
+  c->dev_bytes += tot;
+  return AIM_OK;
+}
+
+#define TRY(x)                   \
+  do {                           \
+    aim_status s_ = (x);         \
+    if (s_ != AIM_OK) return s_; \
+  } while (0)
+
+// squared norms of the columns of w into out (double2 .x), active columns only
+static aim_status norms(Ctx* c, int nrhs, const double2* w, int64_t ldw, const int* active, double2* out) {
+  GmresWork& g = c->gw;
+  const int N = c->t.N;
+  hipLaunchKernelGGL(k_dots, dim3(g.nchunk, 1, nrhs), dim3(256), 0, c->stream, N, nullptr, 0, w, ldw, active,
+                     g.part, g.nchunk, 1);
+  hipLaunchKernelGGL(k_reduce, dim3(1, nrhs), dim3(64), 0, c->stream, nrhs, 1, g.nchunk, 1, g.part, active, out,
+                     (int64_t)1);
+  AIM_HIP_CHECK(hipGetLastError());
+  return AIM_OK;
+}
+
+struct GmresResult {
+  std::vector<int> iters, conv;
+  std::vector<double> est;
+  int matvecs = 0, restarts = 0;
+};
+
+// Solve op(x) = b for nrhs columns (b, x: N x nrhs contiguous) to rel. tol.
+static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, double tol, int maxit, int restart,
+                        GmresResult& res) {
+  TRY(ensure_work(c, restart, nrhs));
+  GmresWork& w = c->gw;
+  hipStream_t s = c->stream;
+  const int N = c->t.N;
+  const int ldh = restart + 1;
+  const int64_t ldv = (int64_t)ldh * N;
+  const dim3 gN((N + 255) / 256, nrhs);
+  int* d_all = w.active + nrhs;   // all-ones mask
+  std::vector<int> ones(nrhs, 1), act(nrhs, 1), jdone(nrhs, 0);
+  AIM_HIP_CHECK(hipMemcpyAsync(d_all, ones.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+  // ||b||
+  TRY(norms(c, nrhs, b, N, d_all, w.nrm));
+  std::vector<double2> hb(nrhs);
+  AIM_HIP_CHECK(hipMemcpyAsync(hb.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
+  AIM_HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<double> bn(nrhs);
+  for (int r = 0; r < nrhs; ++r) bn[r] = std::sqrt(hb[r].x);
+  res.iters.assign(nrhs, 0);
+  res.conv.assign(nrhs, 0);
+  res.est.assign(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r)
+    if (bn[r] == 0.0) {   // zero right-hand side: x = 0
+      res.conv[r] = 1;
+      act[r] = 0;
+      AIM_HIP_CHECK(hipMemsetAsync(x + (size_t)r * N, 0, (size_t)N * 16, s));
+    }
+  int total = 0;
+  while (true) {
+    // r0 = b - A x for the unconverged columns (all columns computed)
+    TRY(matvec(c, op, nrhs, x, N, w.W, N));
+    res.matvecs++;
+    hipLaunchKernelGGL(k_bminus, gN, dim3(256), 0, s, N, b, w.W);
+    AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    TRY(norms(c, nrhs, w.W, N, w.active, w.nrm));
+    std::vector<double2> h0(nrhs);
+    AIM_HIP_CHECK(hipMemcpyAsync(h0.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
+    AIM_HIP_CHECK(hipStreamSynchronize(s));
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      const double rel = std::sqrt(h0[r].x) / bn[r];
+      if (!std::isfinite(rel)) return AIM_E_NUMERIC;
+      res.est[r] = rel;
+      if (rel <= tol) { act[r] = 0; res.conv[r] = 1; }
+      else any = true;
+    }
+    if (!any || total >= maxit) break;
+    AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, (int64_t)1, w.W, (int64_t)N, w.V, ldv, w.active,
+                       w.hn);
+    hipLaunchKernelGGL(k_set_g0, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, w.nrm, w.active, w.g);
+    std::fill(jdone.begin(), jdone.end(), 0);
+    std::vector<int> cyc(act);
+    int j = 0;
+    for (; j < restart && total < maxit; ++j) {
+      const int j1 = j + 1;
+      // w = A v_j
+      TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
+      res.matvecs++;
+      // CGS2
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
+                           w.active, w.part, w.nchunk, ldh);
+        hipLaunchKernelGGL(k_reduce, dim3((j1 + 63) / 64, nrhs), dim3(64), 0, s, nrhs, j1, w.nchunk, ldh, w.part,
+                           w.active, w.hcol, (int64_t)ldh);
+        hipLaunchKernelGGL(k_gemv, gN, dim3(256), 0, s, N, j1, w.V, ldv, w.hcol, (int64_t)ldh, -1.0, w.active,
+                           w.W, (int64_t)N);
+        hipLaunchKernelGGL(k_hacc, dim3((j1 + 63) / 64, nrhs), dim3(64), 0, s, j1, nrhs, ldh, j, w.hcol,
+                           (int64_t)ldh, pass == 0 ? 1 : 0, w.active, w.H);
+      }
+      TRY(norms(c, nrhs, w.W, N, w.active, w.nrm));
+      hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, (int64_t)1, w.W, (int64_t)N,
+                         w.V + (size_t)j1 * N, ldv, w.active, w.hn);
+      hipLaunchKernelGGL(k_givens, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, j, w.hn, w.active, w.H, w.cs,
+                         w.sn, w.g, w.resid);
+      AIM_HIP_CHECK(hipGetLastError());
+      AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid, w.resid, nrhs * 8, hipMemcpyDeviceToHost, s));
+      AIM_HIP_CHECK(hipStreamSynchronize(s));
+      total++;
+      bool left = false, changed = false;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!act[r]) continue;
+        res.iters[r]++;
+        jdone[r] = j1;
+        const double rel = w.host_resid[r] / bn[r];
+        if (!std::isfinite(rel)) return AIM_E_NUMERIC;
+        res.est[r] = rel;
+        if (rel <= tol) { act[r] = 0; changed = true; }
+        else left = true;
+      }
+      if (!left) break;
+      if (changed) AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    }
+    // x += V y for every column that took steps in this cycle
+    std::vector<int> upd(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) upd[r] = (cyc[r] && jdone[r] > 0) ? 1 : 0;
+    int* d_jm = (int*)w.part;   // scratch: jm then mask
+    AIM_HIP_CHECK(hipMemcpyAsync(d_jm, jdone.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    AIM_HIP_CHECK(hipMemcpyAsync(w.active, upd.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_trisolve, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, d_jm, w.H, w.g, w.y);
+    int jmax = 0;
+    for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jdone[r]);
+    // columns with fewer steps have y entries beyond jdone that are stale: zero them by the mask of jm
+    std::vector<double2> yh((size_t)nrhs * restart);
+    AIM_HIP_CHECK(hipMemcpyAsync(yh.data(), w.y, yh.size() * 16, hipMemcpyDeviceToHost, s));
+    AIM_HIP_CHECK(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r)
+      for (int i = jdone[r]; i < restart; ++i) yh[(size_t)r * restart + i] = make_double2(0, 0);
+    AIM_HIP_CHECK(hipMemcpyAsync(w.y, yh.data(), yh.size() * 16, hipMemcpyHostToDevice, s));
+    if (jmax > 0)
+      hipLaunchKernelGGL(k_gemv, gN, dim3(256), 0, s, N, jmax, w.V, ldv, w.y, (int64_t)restart, 1.0, w.active, x,
+                         (int64_t)N);
+    AIM_HIP_CHECK(hipGetLastError());
+    res.restarts++;
+    // columns flagged converged by the estimate are re-checked with the true
+    // residual at the top of the next cycle
+    for (int r = 0; r < nrhs; ++r)
+      if (cyc[r]) act[r] = 1;
+    for (int r = 0; r < nrhs; ++r)
+      if (res.conv[r]) act[r] = 0;
+    if (total >= maxit) {
+      // final true residual
+      TRY(matvec(c, op, nrhs, x, N, w.W, N));
+      res.matvecs++;
+      hipLaunchKernelGGL(k_bminus, gN, dim3(256), 0, s, N, b, w.W);
+      TRY(norms(c, nrhs, w.W, N, d_all, w.nrm));
+      AIM_HIP_CHECK(hipMemcpyAsync(h0.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
+      AIM_HIP_CHECK(hipStreamSynchronize(s));
+      for (int r = 0; r < nrhs; ++r)
+        if (bn[r] > 0) {
+          res.est[r] = std::sqrt(h0[r].x) / bn[r];
+          res.conv[r] = res.est[r] <= tol;
+        }
+      break;
+    }
+  }
+  return AIM_OK;
+}
+
+static int form_op(int form) {
+  switch (form) {
+    case AIM_TM_EFIE: return AIM_OP_TM;
+    case AIM_TE_CALDERON: return AIM_OP_TE_CP;
+    case AIM_TE_CALDERON_UNFILTERED: return AIM_OP_TE_CP_UNF;
+  }
+  return -1;
+}
+
+// relative true residuals ||b - op x|| / ||b|| (FP64 operator)
+static aim_status true_resid(Ctx* c, int op, int nrhs, const double2* b, const double2* x, std::vector<double>& out) {
+  GmresWork& w = c->gw;
+  const int N = c->t.N;
+  int* d_all = w.active + nrhs;
+  TRY(matvec(c, op, nrhs, x, N, w.W, N));
+  hipLaunchKernelGGL(k_bminus, dim3((N + 255) / 256, nrhs), dim3(256), 0, c->stream, N, b, w.W);
+  TRY(norms(c, nrhs, w.W, N, d_all, w.nrm));
+  TRY(norms(c, nrhs, b, N, d_all, w.nrm + nrhs));
+  std::vector<double2> h(2 * nrhs);
+  AIM_HIP_CHECK(hipMemcpyAsync(h.data(), w.nrm, 2 * nrhs * 16, hipMemcpyDeviceToHost, c->stream));
+  AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  out.resize(nrhs);
+  for (int r = 0; r < nrhs; ++r) out[r] = h[nrhs + r].x > 0 ? std::sqrt(h[r].x / h[nrhs + r].x) : 0.0;
+  return AIM_OK;
+}
+
+aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol, int maxit,
+                 int restart, aim_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int op = form_op(form);
+  if (op < 0 || nrhs < 1 || nrhs > c->max_rhs || !(tol > 0) || maxit < 1 || restart < 1) return AIM_E_ARG;
+  if (precision == AIM_MIXED && c->precision != AIM_MIXED) return AIM_E_ARG;
+  if (form != AIM_TM_EFIE && c->t.basis != AIM_HAT) return AIM_E_ARG;
+  if (form == AIM_TM_EFIE && c->t.basis != AIM_PULSE) return AIM_E_ARG;
+  TRY(ensure_work(c, restart, nrhs));
+  // keep nrm wide enough for true_resid (2 nrhs)
+  GmresWork& w = c->gw;
+  const int N = c->t.N;
+  hipStream_t s = c->stream;
+  const double2* rhs = b;
+  if (form != AIM_TM_EFIE) {
+    // preconditioned right-hand side G^-1 S G^-1 b
+    TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, b, N, c->d_tmp1, N));
+    TRY(matvec(c, form == AIM_TE_CALDERON ? AIM_OP_S_ALPHA : AIM_OP_S, nrhs, c->d_tmp1, N, c->d_tmp2, N));
+    TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, c->d_tmp2, N, w.b2, N));
+    rhs = w.b2;
+  }
+  std::vector<int> iters(nrhs, 0), conv(nrhs, 0);
+  std::vector<double> est(nrhs, 0.0);
+  int matvecs = 0, restarts = 0, outer = 0;
+  if (precision == AIM_FP64) {
+    GmresResult gr;
+    TRY(gmres(c, op, nrhs, rhs, x, tol, maxit, restart, gr));
+    iters = gr.iters;
+    conv = gr.conv;
+    est = gr.est;
+    matvecs = gr.matvecs;
+    restarts = gr.restarts;
+  } else {
+    // iterative refinement: FP64 residual, FP32-grid inner GMRES
+    std::vector<double> rel;
+    const double tin_min = 1e-4;
+    for (outer = 0; outer < 30; ++outer) {
+      TRY(true_resid(c, op, nrhs, rhs, x, rel));
+      matvecs++;
+      bool done = true;
+      double worst = 0;
+      for (int r = 0; r < nrhs; ++r) {
+        if (!std::isfinite(rel[r])) return AIM_E_NUMERIC;
+        if (rel[r] > tol) done = false;
+        worst = std::max(worst, rel[r]);
+        est[r] = rel[r];
+        conv[r] = rel[r] <= tol;
+      }
+      int tot_it = 0;
+      for (int r = 0; r < nrhs; ++r) tot_it = std::max(tot_it, iters[r]);
+      if (done || tot_it >= maxit) break;
+      // r = b - A x (recomputed into w.r), d = 0
+      TRY(matvec(c, op, nrhs, x, N, w.r, N));
+      matvecs++;
+      hipLaunchKernelGGL(k_bminus, dim3((N + 255) / 256, nrhs), dim3(256), 0, s, N, rhs, w.r);
+      AIM_HIP_CHECK(hipMemsetAsync(w.d, 0, (size_t)N * nrhs * 16, s));
+      const double tin = std::max(tin_min, 0.5 * tol / worst);
+      GmresResult gr;
+      // inner solve works on its own copy of the residual (gmres reads b, writes d)
+      TRY(gmres(c, op | AIM_OP_GRID_FP32, nrhs, w.r, w.d, std::min(tin, 0.5), maxit - tot_it, restart, gr));
+      for (int r = 0; r < nrhs; ++r) iters[r] += gr.iters[r];
+      matvecs += gr.matvecs;
+      restarts += gr.restarts;
+      hipLaunchKernelGGL(k_axpy, dim3((N + 255) / 256, nrhs), dim3(256), 0, s, N, w.d, x);
+      AIM_HIP_CHECK(hipGetLastError());
+    }
+  }
+  std::vector<double> tr;
+  TRY(true_resid(c, op, nrhs, rhs, x, tr));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    if (!std::isfinite(tr[r])) return AIM_E_NUMERIC;
+    const bool cv = precision == AIM_FP64 ? (conv[r] && tr[r] <= tol * 1.5) : (tr[r] <= tol);
+    all = all && cv;
+    if (info) {
+      info[r].iterations = iters[r];
+      info[r].matvecs = matvecs;
+      info[r].restarts = restarts;
+      info[r].outer = outer;
+      info[r].converged = cv ? 1 : 0;
+      info[r].resid_est = est[r];
+      info[r].resid_true = tr[r];
+      info[r].seconds = secs;
+    }
+  }
+  return all ? AIM_OK : AIM_E_NOCONV;
+}
+
+}  // namespace aim

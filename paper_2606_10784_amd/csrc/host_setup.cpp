@@ -1,0 +1,254 @@
+// Host-side set-up of libaim: mesh, quadrature, stencil weights, active grid
+// points and the near-zone pattern.
+//
+// Sec. II: N straight segments, segment j from vertex j to vertex j+1.
+// Eq. (7): p-node Gauss rule per segment.  Sec. III-A: m x m grid of step eps
+// centred at the origin; Lambda projects quadrature nodes onto grid points.
+// Here Lambda is folded with the quadrature weights and the basis values into
+// one 4 x 4 cubic-Lagrange stencil per basis function (16 weights), anchored
+// at the cell that holds the basis centre.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "aim_internal.h"
+
+namespace aim {
+
+void gauss_legendre01(int p, std::vector<double>& x, std::vector<double>& w) {
+  // Newton iteration on the Legendre polynomial P_p in long double, roots
+  // mapped from [-1, 1] to [0, 1].
+  x.assign(p, 0.0);
+  w.assign(p, 0.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < (p + 1) / 2; ++i) {
+    long double z = std::cos(pi * (i + 0.75L) / (p + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = 0.0L;
+      for (int j = 1; j <= p; ++j) {
+        long double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0L * j - 1.0L) * z * p1 - (j - 1.0L) * p2) / j;
+      }
+      dp = p * (z * p0 - p1) / (z * z - 1.0L);
+      long double dz = p0 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    {
+      long double p0 = 1.0L, p1 = 0.0L;
+      for (int j = 1; j <= p; ++j) {
+        long double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0L * j - 1.0L) * z * p1 - (j - 1.0L) * p2) / j;
+      }
+      dp = p * (z * p0 - p1) / (z * z - 1.0L);
+    }
+    long double wt = 1.0L / ((1.0L - z * z) * dp * dp);   // half of 2/((1-z^2)P'^2)
+    // z is the i-th largest root: nodes (1 -+ z)/2
+    x[i] = (double)((1.0L - z) * 0.5L);
+    x[p - 1 - i] = (double)((1.0L + z) * 0.5L);
+    w[i] = (double)wt;
+    w[p - 1 - i] = (double)wt;
+  }
+}
+
+void twiddles(int n, std::vector<double>& tw) {
+  tw.assign(2 * (size_t)n, 0.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < n; ++j) {
+    long double a = 2.0L * pi * (long double)j / (long double)n;
+    tw[2 * j] = (double)std::cos(a);
+    tw[2 * j + 1] = (double)(-std::sin(a));
+  }
+  // exact values at the quarter points
+  for (int q = 0; q < 4; ++q) {
+    int j = q * n / 4;
+    if ((int64_t)j * 4 != (int64_t)q * n) continue;
+    static const double cre[4] = {1, 0, -1, 0}, cim[4] = {0, -1, 0, 1};
+    tw[2 * j] = cre[q];
+    tw[2 * j + 1] = cim[q];
+  }
+}
+
+static inline void lagrange4(double t, double l[4]) {
+  // cubic Lagrange basis on nodes -1, 0, 1, 2
+  l[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
+  l[1] = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+  l[2] = -(t + 1.0) * t * (t - 2.0) / 2.0;
+  l[3] = (t + 1.0) * t * (t - 1.0) / 6.0;
+}
+
+aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& err) {
+  if (!p || !p->xy) { err = "null params"; return AIM_E_ARG; }
+  const int N = p->n_vertices;
+  const int m = p->m;
+  if (N < 8) { err = "need at least 8 vertices"; return AIM_E_ARG; }
+  if (m < 16 || m > 4096 || (m & (m - 1))) { err = "m must be a power of two in [16, 4096]"; return AIM_E_ARG; }
+  if (!(p->eps > 0) || !(p->k > 0) || !(p->eta > 0)) { err = "eps, k, eta must be positive"; return AIM_E_ARG; }
+  if (p->quad < 1 || p->quad > 64) { err = "quad must be in [1, 64]"; return AIM_E_ARG; }
+  if (p->near_radius < 0 || p->near_radius + 3 > m - 1) { err = "near_radius out of range"; return AIM_E_ARG; }
+  if (p->basis != AIM_PULSE && p->basis != AIM_HAT) { err = "basis"; return AIM_E_ARG; }
+  if (p->max_rhs < 1) { err = "max_rhs"; return AIM_E_ARG; }
+  t.N = N;
+  t.basis = p->basis;
+  t.m = m;
+  t.n = 2 * m;
+  t.p = p->quad;
+  t.R = p->near_radius;
+  t.k = p->k;
+  t.eta = p->eta;
+  t.eps = p->eps;
+  t.L = 0.5 * (m - 1) * p->eps;
+  t.nch = (p->basis == AIM_HAT) ? 4 : 1;
+  t.vx.resize(N);
+  t.vy.resize(N);
+  for (int i = 0; i < N; ++i) {
+    t.vx[i] = p->xy[2 * i];
+    t.vy[i] = p->xy[2 * i + 1];
+    if (!std::isfinite(t.vx[i]) || !std::isfinite(t.vy[i])) { err = "non-finite vertex"; return AIM_E_ARG; }
+  }
+  t.h.resize(N);
+  t.tx.resize(N);
+  t.ty.resize(N);
+  for (int j = 0; j < N; ++j) {
+    int j1 = (j + 1) % N;
+    double dx = t.vx[j1] - t.vx[j], dy = t.vy[j1] - t.vy[j];
+    double h = std::hypot(dx, dy);
+    if (!(h > 0)) { err = "degenerate segment"; return AIM_E_ARG; }
+    t.h[j] = h;
+    t.tx[j] = dx / h;
+    t.ty[j] = dy / h;
+  }
+  gauss_legendre01(t.p, t.gl_x, t.gl_w);
+
+  // anchors: floor((c + L) / eps), c = segment midpoint (pulse) or vertex (hat)
+  t.anc_x.resize(N);
+  t.anc_y.resize(N);
+  for (int j = 0; j < N; ++j) {
+    double cx, cy;
+    if (t.basis == AIM_PULSE) {
+      int j1 = (j + 1) % N;
+      cx = 0.5 * (t.vx[j] + t.vx[j1]);
+      cy = 0.5 * (t.vy[j] + t.vy[j1]);
+    } else {
+      cx = t.vx[j];
+      cy = t.vy[j];
+    }
+    double ax = std::floor((cx + t.L) / t.eps), ay = std::floor((cy + t.L) / t.eps);
+    if (!(ax - 1 >= 0 && ax + 2 <= m - 1 && ay - 1 >= 0 && ay + 2 <= m - 1)) {
+      err = "stencil leaves the grid";
+      return AIM_E_GEOM;
+    }
+    t.anc_x[j] = (int32_t)ax;
+    t.anc_y[j] = (int32_t)ay;
+  }
+
+  // stencil weights per channel
+  const int nch = t.nch;
+  for (int c = 0; c < 4; ++c) t.W[c].assign(c < nch ? (size_t)N * 16 : 0, 0.0);
+  for (int j = 0; j < N; ++j) {
+    int nseg = (t.basis == AIM_PULSE) ? 1 : 2;
+    for (int q = 0; q < nseg; ++q) {
+      int s;
+      double c0, c1;
+      if (t.basis == AIM_PULSE) { s = j; c0 = 1.0; c1 = 0.0; }
+      else if (q == 0) { s = (j - 1 + N) % N; c0 = 0.0; c1 = 1.0; }   // rising on segment j-1
+      else { s = j; c0 = 1.0; c1 = -1.0; }                            // falling on segment j
+      int s1 = (s + 1) % N;
+      double ax0 = t.vx[s], ay0 = t.vy[s];
+      double ddx = t.vx[s1] - ax0, ddy = t.vy[s1] - ay0;
+      for (int kq = 0; kq < t.p; ++kq) {
+        double tau = t.gl_x[kq];
+        double px = ax0 + ddx * tau, py = ay0 + ddy * tau;
+        double wk = t.h[s] * t.gl_w[kq];
+        double phi = c0 + c1 * tau;
+        double val[4] = {phi, c1 / t.h[s], t.tx[s] * phi, t.ty[s] * phi};
+        double lx[4], ly[4];
+        lagrange4((px + t.L) / t.eps - t.anc_x[j], lx);
+        lagrange4((py + t.L) / t.eps - t.anc_y[j], ly);
+        for (int c = 0; c < nch; ++c) {
+          double f = wk * val[c];
+          double* Wj = &t.W[c][(size_t)j * 16];
+          for (int tt = 0; tt < 4; ++tt)
+            for (int ss = 0; ss < 4; ++ss) Wj[tt * 4 + ss] += f * lx[ss] * ly[tt];
+        }
+      }
+    }
+  }
+
+  // active grid points: union of stencils, sorted by row-major index
+  std::vector<int64_t> lin((size_t)N * 16);
+  for (int j = 0; j < N; ++j)
+    for (int tt = 0; tt < 4; ++tt)
+      for (int ss = 0; ss < 4; ++ss)
+        lin[(size_t)j * 16 + tt * 4 + ss] = (int64_t)(t.anc_y[j] - 1 + tt) * m + (t.anc_x[j] - 1 + ss);
+  std::vector<int64_t> act(lin);
+  std::sort(act.begin(), act.end());
+  act.erase(std::unique(act.begin(), act.end()), act.end());
+  t.n_act = (int)act.size();
+  t.act_ix.resize(t.n_act);
+  t.act_iy.resize(t.n_act);
+  for (int a = 0; a < t.n_act; ++a) {
+    t.act_ix[a] = (int32_t)(act[a] % m);
+    t.act_iy[a] = (int32_t)(act[a] / m);
+  }
+  t.aidx.resize((size_t)N * 16);
+  for (size_t q = 0; q < lin.size(); ++q)
+    t.aidx[q] = (int32_t)(std::lower_bound(act.begin(), act.end(), lin[q]) - act.begin());
+  t.y0 = t.act_iy.front();
+  t.nr = t.act_iy.back() - t.y0 + 1;
+  t.row_ptr.assign(t.nr + 1, 0);
+  for (int a = 0; a < t.n_act; ++a) t.row_ptr[t.act_iy[a] - t.y0 + 1]++;
+  for (int r = 0; r < t.nr; ++r) t.row_ptr[r + 1] += t.row_ptr[r];
+
+  // transposed stencils (grid point -> contributing bases), for the gather
+  t.at_ptr.assign(t.n_act + 1, 0);
+  for (size_t q = 0; q < t.aidx.size(); ++q) t.at_ptr[t.aidx[q] + 1]++;
+  for (int a = 0; a < t.n_act; ++a) t.at_ptr[a + 1] += t.at_ptr[a];
+  t.at_basis.assign(t.aidx.size(), 0);
+  for (int c = 0; c < 4; ++c) t.at_w[c].assign(c < nch ? t.aidx.size() : 0, 0.0);
+  {
+    std::vector<int32_t> fill(t.at_ptr.begin(), t.at_ptr.end() - 1);
+    for (int j = 0; j < N; ++j)
+      for (int e = 0; e < 16; ++e) {
+        int a = t.aidx[(size_t)j * 16 + e];
+        int pos = fill[a]++;
+        t.at_basis[pos] = j;
+        for (int c = 0; c < nch; ++c) t.at_w[c][pos] = t.W[c][(size_t)j * 16 + e];
+      }
+  }
+
+  // near zone: anchor Chebyshev distance <= R (CSR, sorted columns)
+  std::vector<int64_t> key(N);
+  std::vector<int32_t> ord(N);
+  for (int j = 0; j < N; ++j) key[j] = (int64_t)t.anc_y[j] * m + t.anc_x[j];
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return key[a] < key[b] || (key[a] == key[b] && a < b); });
+  std::vector<int64_t> skey(N);
+  for (int q = 0; q < N; ++q) skey[q] = key[ord[q]];
+  const int R = t.R;
+  t.nr_ptr.assign(N + 1, 0);
+  t.nr_col.clear();
+  std::vector<int32_t> cols;
+  for (int i = 0; i < N; ++i) {
+    cols.clear();
+    int ax = t.anc_x[i], ay = t.anc_y[i];
+    for (int dy = -R; dy <= R; ++dy) {
+      int y = ay + dy;
+      if (y < 0 || y >= m) continue;
+      int64_t lo = (int64_t)y * m + std::max(0, ax - R);
+      int64_t hi = (int64_t)y * m + std::min(m - 1, ax + R);
+      auto b = std::lower_bound(skey.begin(), skey.end(), lo);
+      auto e = std::upper_bound(skey.begin(), skey.end(), hi);
+      for (auto it = b; it != e; ++it) cols.push_back(ord[it - skey.begin()]);
+    }
+    std::sort(cols.begin(), cols.end());
+    t.nr_col.insert(t.nr_col.end(), cols.begin(), cols.end());
+    t.nr_ptr[i + 1] = (int32_t)t.nr_col.size();
+  }
+  return AIM_OK;
+}
+
+}  // namespace aim

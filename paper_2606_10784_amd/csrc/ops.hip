@@ -1,0 +1,937 @@
+// Device set-up and operator application of libaim (gfx950).
+//
+//  * kernel sampling:  c[d] = g(eps |d|), c[0] = 0 (Sec. III-C), ring |d| = m
+//    of the n = 2m embedding zero; spectrum F(c) by the FFT kernels (eq. (8))
+//  * numerical filter: quarter spectrum masked to |kappa| <= alpha (Sec. III-B)
+//  * near field: exact Galerkin entries of eq. (4) / the Maue form of eq. (2)
+//    minus their grid approximation, FP64, one thread per nonzero; singular
+//    segment pairs use the log/regular split g = -(1/2pi) J0(kR) ln R + F(R)
+//  * anterpolation (transposed stencils, gather per active grid point) and
+//    interpolation fused with the near-field product (16 lanes per row)
+//  * Gram solve G^-1 (Sec. II): pulses diagonal, hats cyclic tridiagonal
+#include <cmath>
+#include <cstdio>
+
+#include "aim_internal.h"
+
+namespace aim {
+
+template <typename T>
+aim_status launch_rows_fwd(int n, const cplx<T>* U, int n_act, const int32_t* row_ptr,
+                           const int32_t* act_ix, int nr, int pairs, cplx<T>* Tb,
+                           const cplx<T>* tw, hipStream_t s);
+template <typename T>
+aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_ptr,
+                           const int32_t* act_ix, int pairs, cplx<T>* V, int n_act,
+                           const cplx<T>* tw, hipStream_t s);
+template <typename T>
+aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int pairs, const cplx<T>* Cq,
+                       const cplx<T>* tw, hipStream_t s);
+aim_status launch_rows_fft_inplace(int n, double2* A, const double2* tw, hipStream_t s);
+
+static constexpr double kPi = 3.14159265358979323846264338327950288;
+static constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+static constexpr double kEuler = 0.57721566490153286060651209008240243;
+
+// ---------------------------------------------------------------------------
+// Green's function and its regular part
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 green(double R, double k) {
+  const double x = k * R;
+  return make_double2(-0.25 * y0(x), -0.25 * j0(x));
+}
+
+// F(R) = g(R) + (1/2pi) J0(kR) ln R (entire in R^2).  Ascending series for
+// kR < 2:  Y0(x) = (2/pi)[(ln(x/2) + gamma) J0(x) + sum_{m>=1} (-1)^{m+1} H_m q^m/(m!)^2],
+// q = x^2/4.
+__device__ double2 green_regular(double R, double k) {
+  const double x = k * R;
+  if (x < 2.0) {
+    const double q = 0.25 * x * x;
+    double t = 1.0, jj = 1.0, S = 0.0, Hm = 0.0;
+    for (int m = 1; m < 40; ++m) {
+      t *= q / ((double)m * (double)m);
+      Hm += 1.0 / m;
+      if (m & 1) { jj -= t; S += Hm * t; }
+      else { jj += t; S -= Hm * t; }
+      if (t < 1e-19) break;
+    }
+    return make_double2(-kInv2Pi * (jj * (log(0.5 * k) + kEuler) + S), -0.25 * jj);
+  }
+  double2 g = green(R, k);
+  g.x += kInv2Pi * j0(x) * log(R);
+  return g;
+}
+
+__global__ void k_eval_green(int n, const double* R, double k, double2* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = green(R[i], k);
+}
+
+// ---------------------------------------------------------------------------
+// grid kernel sampling (wrap-around layout of the n x n circulant)
+// ---------------------------------------------------------------------------
+__global__ void k_sample_kernel(int m, int n, double eps, double k, double2* c) {
+  const int qx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int qy = blockIdx.y;
+  if (qx >= n) return;
+  const int dx = qx < m ? qx : qx - n;   // qx == m: ring, |d| = m -> 0
+  const int dy = qy < m ? qy : qy - n;
+  double2 v = make_double2(0.0, 0.0);
+  if (qx != m && qy != m && (dx != 0 || dy != 0)) {
+    const double R = eps * sqrt((double)dx * dx + (double)dy * dy);
+    v = green(R, k);
+  }
+  c[(size_t)qy * n + qx] = v;
+}
+
+// quarter of the spectrum, [kxq][kyq], scaled by 1/n^2
+__global__ void k_extract_quarter(int n, const double2* C, double2* Q, float2* Qf) {
+  const int H = n / 2 + 1;
+  const int ky = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kx = blockIdx.y;
+  if (ky >= H) return;
+  const double s = 1.0 / ((double)n * (double)n);
+  double2 v = C[(size_t)ky * n + kx];
+  v.x *= s;
+  v.y *= s;
+  Q[(size_t)kx * H + ky] = v;
+  if (Qf) Qf[(size_t)kx * H + ky] = make_float2((float)v.x, (float)v.y);
+}
+
+__global__ void k_small_table(int m, int n, int ks, const double2* c, double2* out) {
+  const int dx = threadIdx.x, dy = blockIdx.x;
+  if (dx < ks && dy < ks) out[dy * ks + dx] = c[(size_t)dy * n + dx];
+}
+
+// numerical filter on the quarter: keep qx^2 + qy^2 <= thr
+__global__ void k_filter(int n, double thr, bool all, const double2* Q, double2* Qa, float2* Qaf) {
+  const int H = n / 2 + 1;
+  const int ky = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kx = blockIdx.y;
+  if (ky >= H) return;
+  const double r2 = (double)kx * kx + (double)ky * ky;
+  double2 v = Q[(size_t)kx * H + ky];
+  if (!all && !(r2 <= thr)) v = make_double2(0.0, 0.0);
+  Qa[(size_t)kx * H + ky] = v;
+  if (Qaf) Qaf[(size_t)kx * H + ky] = make_float2((float)v.x, (float)v.y);
+}
+
+// ---------------------------------------------------------------------------
+// singular-quadrature moments of segment pairs (FP64)
+//   M_uv = int_a int_b g(|r - r'|) tau^u sigma^v ds ds'
+// ---------------------------------------------------------------------------
+struct NearGeo {
+  const double *vx, *vy, *h, *tx, *ty;
+  int N;
+  double k;
+  const double* gl;   // [x16 w16 x24 w24 x32 w32]
+};
+
+__device__ void moments_self(const NearGeo& G, double h, double2 M[2][2]) {
+  const double* x24 = G.gl + 32;
+  const double* w24 = G.gl + 56;
+  // Q_uv(delta) coefficients (ascending powers)
+  const double Q00[2] = {2.0, -2.0}, Q10[2] = {1.0, -1.0};
+  const double Q11[4] = {2.0 / 3.0, -1.0, 0.0, 1.0 / 3.0};
+  const double lnh = log(h);
+  // log part: -(1/2pi) sum_m c_m h^{2m} sum_p Q_p (ln h / e - 1/e^2), e = 2m + p + 1
+  double L00 = 0, L10 = 0, L11 = 0;
+  double tm = 1.0;
+  const double z = 0.25 * G.k * G.k * h * h;
+  for (int m = 0; m < 60; ++m) {
+    double s00 = 0, s10 = 0, s11 = 0;
+    for (int p = 0; p < 4; ++p) {
+      const double e = 2.0 * m + p + 1.0;
+      const double f = lnh / e - 1.0 / (e * e);
+      if (p < 2) { s00 += Q00[p] * f; s10 += Q10[p] * f; }
+      s11 += Q11[p] * f;
+    }
+    L00 += tm * s00;
+    L10 += tm * s10;
+    L11 += tm * s11;
+    tm *= -z / ((m + 1.0) * (m + 1.0));
+    if (fabs(tm) < 1e-20) break;
+  }
+  double2 F00 = make_double2(0, 0), F10 = F00, F11 = F00;
+  for (int i = 0; i < 24; ++i) {
+    const double d = x24[i];
+    const double2 F = green_regular(h * d, G.k);
+    const double q00 = w24[i] * (2.0 - 2.0 * d);
+    const double q10 = w24[i] * (1.0 - d);
+    const double q11 = w24[i] * (2.0 / 3.0 - d + d * d * d / 3.0);
+    F00.x += q00 * F.x; F00.y += q00 * F.y;
+    F10.x += q10 * F.x; F10.y += q10 * F.y;
+    F11.x += q11 * F.x; F11.y += q11 * F.y;
+  }
+  const double hh = h * h;
+  M[0][0] = make_double2(hh * (-kInv2Pi * L00 + F00.x), hh * F00.y);
+  M[1][0] = make_double2(hh * (-kInv2Pi * L10 + F10.x), hh * F10.y);
+  M[0][1] = M[1][0];
+  M[1][1] = make_double2(hh * (-kInv2Pi * L11 + F11.x), hh * F11.y);
+}
+
+// segments a and b share a vertex; a_first: a ends where b starts
+__device__ void moments_adjacent(const NearGeo& G, int a, int b, bool a_first, double2 M[2][2]) {
+  const int N = G.N;
+  const int a1 = (a + 1) % N, b1 = (b + 1) % N;
+  double Vx, Vy, Pax, Pay, Pbx, Pby, t0, t1, s0, s1;
+  const double ha = G.h[a], hb = G.h[b];
+  if (a_first) {   // V = end of a = start of b
+    Vx = G.vx[a1]; Vy = G.vy[a1];
+    Pax = G.vx[a]; Pay = G.vy[a];
+    Pbx = G.vx[b1]; Pby = G.vy[b1];
+    t0 = 1.0; t1 = -1.0 / ha;      // tau = 1 - s/ha
+    s0 = 0.0; s1 = 1.0 / hb;       // sigma = s'/hb
+  } else {         // V = start of a = end of b
+    Vx = G.vx[a]; Vy = G.vy[a];
+    Pax = G.vx[a1]; Pay = G.vy[a1];
+    Pbx = G.vx[b]; Pby = G.vy[b];
+    t0 = 0.0; t1 = 1.0 / ha;
+    s0 = 1.0; s1 = -1.0 / hb;
+  }
+  const double eax = (Pax - Vx) / ha, eay = (Pay - Vy) / ha;
+  const double ebx = (Pbx - Vx) / hb, eby = (Pby - Vy) / hb;
+  const double cab = eax * ebx + eay * eby;
+  const double k = G.k;
+  // polar log part: B_ij = int int J0(kR) ln R s^i s'^j ds ds'
+  double B[2][2] = {{0, 0}, {0, 0}};
+  const double* x32 = G.gl + 80;
+  const double* w32 = G.gl + 112;
+  const double psid = atan2(hb, ha);
+  for (int half = 0; half < 2; ++half) {
+    const double lo = half ? psid : 0.0, hi = half ? 0.5 * kPi : psid;
+    const double len = hi - lo;
+    for (int q = 0; q < 32; ++q) {
+      const double ps = lo + len * x32[q];
+      const double wps = len * w32[q];
+      double sp, cp;
+      sincos(ps, &sp, &cp);
+      const double r2 = 1.0 - 2.0 * cp * sp * cab;
+      const double lnr = 0.5 * log(r2);
+      const double P = half ? hb / sp : ha / cp;
+      const double lnP = log(P);
+      const double zz = 0.25 * k * k * r2 * P * P;
+      // sum over m for total degree d = i + j in {0,1,2}
+      double Sd[3] = {0, 0, 0};
+      for (int d = 0; d < 3; ++d) {
+        double tm = 1.0;
+        double Pe = pow(P, (double)(d + 2));   // P^{e} with e = d + 2 at m = 0
+        double acc = 0.0;
+        for (int m = 0; m < 60; ++m) {
+          const double e = 2.0 * m + d + 2.0;
+          acc += tm * Pe * ((lnP + lnr) / e - 1.0 / (e * e));
+          tm *= -zz / ((m + 1.0) * (m + 1.0));
+          if (fabs(tm) < 1e-20) break;
+        }
+        Sd[d] = acc;   // tm carries (k P r / 2)^{2m}/(m!)^2, Pe the rest
+      }
+      B[0][0] += wps * Sd[0];
+      B[1][0] += wps * cp * Sd[1];
+      B[0][1] += wps * sp * Sd[1];
+      B[1][1] += wps * cp * sp * Sd[2];
+    }
+  }
+  // smooth part by 16 x 16 Gauss-Legendre in (s, s')
+  const double* x16 = G.gl;
+  const double* w16 = G.gl + 16;
+  double2 F[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) F[u][v] = make_double2(0, 0);
+  for (int i = 0; i < 16; ++i) {
+    const double S = x16[i] * ha;
+    const double tau = t0 + t1 * S;
+    for (int j = 0; j < 16; ++j) {
+      const double Sp = x16[j] * hb;
+      const double sig = s0 + s1 * Sp;
+      const double R = sqrt(fmax(S * S + Sp * Sp - 2.0 * S * Sp * cab, 0.0));
+      const double2 f = green_regular(R, k);
+      const double w = w16[i] * w16[j] * ha * hb;
+      const double c00 = w, c10 = w * tau, c01 = w * sig, c11 = w * tau * sig;
+      F[0][0].x += c00 * f.x; F[0][0].y += c00 * f.y;
+      F[1][0].x += c10 * f.x; F[1][0].y += c10 * f.y;
+      F[0][1].x += c01 * f.x; F[0][1].y += c01 * f.y;
+      F[1][1].x += c11 * f.x; F[1][1].y += c11 * f.y;
+    }
+  }
+  // tau^u sigma^v in powers of (s, s'): alpha^u_i, beta^v_j
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      const double al[2] = {u ? t0 : 1.0, u ? t1 : 0.0};
+      const double be[2] = {v ? s0 : 1.0, v ? s1 : 0.0};
+      double Lsum = 0.0;
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) Lsum += al[i] * be[j] * B[i][j];
+      M[u][v] = make_double2(-kInv2Pi * Lsum + F[u][v].x, F[u][v].y);
+    }
+}
+
+__device__ void moments_disjoint(const NearGeo& G, int a, int b, double2 M[2][2]) {
+  const int N = G.N;
+  const int a1 = (a + 1) % N, b1 = (b + 1) % N;
+  const double ax = G.vx[a], ay = G.vy[a], adx = G.vx[a1] - ax, ady = G.vy[a1] - ay;
+  const double bx = G.vx[b], by = G.vy[b], bdx = G.vx[b1] - bx, bdy = G.vy[b1] - by;
+  const double* x16 = G.gl;
+  const double* w16 = G.gl + 16;
+  double2 acc[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) acc[u][v] = make_double2(0, 0);
+  for (int i = 0; i < 16; ++i) {
+    const double ti = x16[i];
+    const double px = ax + adx * ti, py = ay + ady * ti;
+    double2 r0 = make_double2(0, 0), r1 = make_double2(0, 0);
+    for (int j = 0; j < 16; ++j) {
+      const double sj = x16[j];
+      const double dx = px - (bx + bdx * sj), dy = py - (by + bdy * sj);
+      const double2 g = green(sqrt(dx * dx + dy * dy), G.k);
+      const double w = w16[j];
+      r0.x += w * g.x; r0.y += w * g.y;
+      r1.x += w * sj * g.x; r1.y += w * sj * g.y;
+    }
+    const double wi = w16[i];
+    acc[0][0].x += wi * r0.x; acc[0][0].y += wi * r0.y;
+    acc[0][1].x += wi * r1.x; acc[0][1].y += wi * r1.y;
+    acc[1][0].x += wi * ti * r0.x; acc[1][0].y += wi * ti * r0.y;
+    acc[1][1].x += wi * ti * r1.x; acc[1][1].y += wi * ti * r1.y;
+  }
+  const double s = G.h[a] * G.h[b];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) M[u][v] = make_double2(s * acc[u][v].x, s * acc[u][v].y);
+}
+
+__device__ void segment_moments(const NearGeo& G, int a, int b, double2 M[2][2]) {
+  const int N = G.N;
+  if (a == b) moments_self(G, G.h[a], M);
+  else if ((a + 1) % N == b) moments_adjacent(G, a, b, true, M);
+  else if ((b + 1) % N == a) moments_adjacent(G, a, b, false, M);
+  else moments_disjoint(G, a, b, M);
+}
+
+// grid approximation (Lambda_i^T G_grid Lambda_j) of one channel pair
+__device__ double2 grid_pair(const double* Wi, const double* Wj, int dax, int day,
+                             const double2* ks, int KS) {
+  double2 acc = make_double2(0, 0);
+  for (int e = 0; e < 16; ++e) {
+    const int se = e & 3, te = e >> 2;
+    double2 inner = make_double2(0, 0);
+    for (int f = 0; f < 16; ++f) {
+      const int sf = f & 3, tf = f >> 2;
+      const int dx = abs(dax + se - sf), dy = abs(day + te - tf);
+      const double2 kv = ks[dy * KS + dx];
+      inner.x += Wj[f] * kv.x;
+      inner.y += Wj[f] * kv.y;
+    }
+    acc.x += Wi[e] * inner.x;
+    acc.y += Wi[e] * inner.y;
+  }
+  return acc;
+}
+
+__global__ void k_near_build(NearGeo G, int basis, int64_t nnz, const int32_t* __restrict__ rows,
+                             const int32_t* __restrict__ cols, const int32_t* __restrict__ anx,
+                             const int32_t* __restrict__ any, const double* W0, const double* W1,
+                             const double* W2, const double* W3, const double2* __restrict__ ks,
+                             int KS, double2* CS, double2* CN) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  const int i = rows[q], j = cols[q];
+  const int N = G.N;
+  const int dax = anx[i] - anx[j], day = any[i] - any[j];
+  double2 M[2][2];
+  if (basis == AIM_PULSE) {
+    segment_moments(G, i, j, M);
+    const double2 gp = grid_pair(W0 + (size_t)i * 16, W0 + (size_t)j * 16, dax, day, ks, KS);
+    CS[q] = make_double2(M[0][0].x - gp.x, M[0][0].y - gp.y);
+    return;
+  }
+  // hats: pieces (segment, c0, c1): rising on i-1, falling on i
+  const int sa[2] = {(i - 1 + N) % N, i}, sb[2] = {(j - 1 + N) % N, j};
+  const double c0[2] = {0.0, 1.0}, c1[2] = {1.0, -1.0};
+  double2 S = make_double2(0, 0), Nn = make_double2(0, 0);
+  const double k2 = G.k * G.k;
+  for (int pa = 0; pa < 2; ++pa)
+    for (int pb = 0; pb < 2; ++pb) {
+      const int a = sa[pa], b = sb[pb];
+      segment_moments(G, a, b, M);
+      // phi_i phi_j moment: sum_uv p_u q_v M_uv with p = (c0, c1)
+      const double pu[2] = {c0[pa], c1[pa]}, qv[2] = {c0[pb], c1[pb]};
+      double2 pp = make_double2(0, 0);
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          pp.x += pu[u] * qv[v] * M[u][v].x;
+          pp.y += pu[u] * qv[v] * M[u][v].y;
+        }
+      S.x += pp.x;
+      S.y += pp.y;
+      const double da = c1[pa] / G.h[a], db = c1[pb] / G.h[b];
+      const double tt = G.tx[a] * G.tx[b] + G.ty[a] * G.ty[b];
+      Nn.x += da * db * M[0][0].x - k2 * tt * pp.x;
+      Nn.y += da * db * M[0][0].y - k2 * tt * pp.y;
+    }
+  const size_t oi = (size_t)i * 16, oj = (size_t)j * 16;
+  const double2 gS = grid_pair(W0 + oi, W0 + oj, dax, day, ks, KS);
+  const double2 gq = grid_pair(W1 + oi, W1 + oj, dax, day, ks, KS);
+  const double2 gx = grid_pair(W2 + oi, W2 + oj, dax, day, ks, KS);
+  const double2 gy = grid_pair(W3 + oi, W3 + oj, dax, day, ks, KS);
+  CS[q] = make_double2(S.x - gS.x, S.y - gS.y);
+  CN[q] = make_double2(Nn.x - (gq.x - k2 * (gx.x + gy.x)), Nn.y - (gq.y - k2 * (gx.y + gy.y)));
+}
+
+// ---------------------------------------------------------------------------
+// anterpolation: U[ch*nrhs + r][a] = sum_e w_ch[e] x[r*ldx + basis_e]
+// ---------------------------------------------------------------------------
+template <typename T, typename TW>
+__global__ void k_anterp(int n_act, int nrhs, const int32_t* __restrict__ at_ptr,
+                         const int32_t* __restrict__ at_basis, const TW* __restrict__ w0,
+                         const TW* __restrict__ w1, const TW* __restrict__ w2,
+                         const double2* __restrict__ x, int64_t ldx, cplx<T>* __restrict__ U) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pair = blockIdx.y;              // ch * nrhs + r
+  if (a >= n_act) return;
+  const int ch = pair / nrhs, r = pair - ch * nrhs;
+  const TW* w = ch == 0 ? w0 : (ch == 1 ? w1 : w2);
+  const double2* xr = x + (size_t)r * ldx;
+  T sx = 0, sy = 0;
+  for (int e = at_ptr[a]; e < at_ptr[a + 1]; ++e) {
+    const double2 xv = xr[at_basis[e]];
+    const T ww = (T)w[e];
+    sx += ww * (T)xv.x;
+    sy += ww * (T)xv.y;
+  }
+  U[(size_t)pair * n_act + a] = mk<T>(sx, sy);
+}
+
+// ---------------------------------------------------------------------------
+// interpolation + near field: 16 lanes per basis row
+//   y = scale * ( sum_ch sgn_ch W_ch . V_ch + C_near x )
+// ---------------------------------------------------------------------------
+template <typename T, typename TW>
+__global__ __launch_bounds__(256) void k_interp_near(
+    int N, int nrhs, int nch, const TW* __restrict__ W0, const TW* __restrict__ W1,
+    const TW* __restrict__ W2, double sg, const int32_t* __restrict__ aidx,
+    const cplx<T>* __restrict__ V, int n_act, const int32_t* __restrict__ nptr,
+    const int32_t* __restrict__ ncol, const double2* __restrict__ C, const double2* __restrict__ x,
+    int64_t ldx, double2* __restrict__ y, int64_t ldy, double2 scale) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = gid >> 4, l = gid & 15;
+  if (row >= N) return;          // whole 16-lane groups exit together
+  const size_t o = (size_t)row * 16 + l;
+  const int a = aidx[o];
+  const double w0 = (double)W0[o];
+  const double w1 = nch > 1 ? (double)W1[o] : 0.0;
+  const double w2 = nch > 1 ? (double)W2[o] : 0.0;
+  const int q0 = C ? nptr[row] : 0, q1 = C ? nptr[row + 1] : 0;
+  for (int r = 0; r < nrhs; ++r) {
+    double ax, ay;
+    {
+      const cplx<T> v0 = V[(size_t)r * n_act + a];
+      ax = w0 * (double)v0.x;
+      ay = w0 * (double)v0.y;
+      if (nch > 1) {
+        const cplx<T> v1 = V[(size_t)(nrhs + r) * n_act + a];
+        const cplx<T> v2 = V[(size_t)(2 * nrhs + r) * n_act + a];
+        ax += sg * (w1 * (double)v1.x + w2 * (double)v2.x);
+        ay += sg * (w1 * (double)v1.y + w2 * (double)v2.y);
+      }
+    }
+    const double2* xr = x + (size_t)r * ldx;
+    for (int q = q0 + l; q < q1; q += 16) {
+      const double2 cv = C[q];
+      const double2 xv = xr[ncol[q]];
+      ax += cv.x * xv.x - cv.y * xv.y;
+      ay += cv.x * xv.y + cv.y * xv.x;
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+      ax += __shfl_xor(ax, off, 16);
+      ay += __shfl_xor(ay, off, 16);
+    }
+    if (l == 0) y[(size_t)r * ldy + row] = make_double2(scale.x * ax - scale.y * ay, scale.x * ay + scale.y * ax);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram solve
+// ---------------------------------------------------------------------------
+__global__ void k_gram_pulse(int N, int nrhs, const double* h, const double2* x, int64_t ldx, double2* y,
+                             int64_t ldy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const double2 v = x[(size_t)r * ldx + i];
+  y[(size_t)r * ldy + i] = make_double2(v.x / h[i], v.y / h[i]);
+}
+
+// Hats, N >= GB + 2 GH: block of GB outputs from a truncated tridiagonal system
+// extended by GH unknowns on each side.  The inverse of this Gram matrix
+// decays at least like 0.268^|i-j| (condition number <= 3), so the
+// truncation error is below 1e-18 relative.
+constexpr int GB = 64, GH = 32, GM = GB + 2 * GH;
+
+__global__ void k_gram_hat_blocks(int N, int nrhs, const double* h, const double2* x, int64_t ldx,
+                                  double2* y, int64_t ldy) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  const int nblk = (N + GB - 1) / GB;
+  if (blk >= nblk) return;
+  const int i0 = blk * GB - GH;    // first unknown of the local system (cyclic)
+  double cp[GM];
+  double2 dp[GM];
+  const double2* xr = x + (size_t)r * ldx;
+  // Thomas: a_i y_{i-1} + d_i y_i + c_i y_{i+1} = b_i, local indices 0..GM-1
+  double prev_c = 0.0;
+  double2 prev_d = make_double2(0, 0);
+  for (int l = 0; l < GM; ++l) {
+    const int gi = ((i0 + l) % N + N) % N;
+    const int gm = (gi - 1 + N) % N;
+    const double d = (h[gm] + h[gi]) / 3.0;
+    const double a = (l > 0) ? h[gm] / 6.0 : 0.0;
+    const double c = (l < GM - 1) ? h[gi] / 6.0 : 0.0;
+    const double den = d - a * prev_c;
+    const double2 b = xr[gi];
+    cp[l] = c / den;
+    dp[l] = make_double2((b.x - a * prev_d.x) / den, (b.y - a * prev_d.y) / den);
+    prev_c = cp[l];
+    prev_d = dp[l];
+  }
+  double2 nxt = dp[GM - 1];
+  double2* yr = y + (size_t)r * ldy;
+  for (int l = GM - 1; l >= 0; --l) {
+    double2 v = dp[l];
+    if (l < GM - 1) { v.x -= cp[l] * nxt.x; v.y -= cp[l] * nxt.y; }
+    nxt = v;
+    if (l >= GH && l < GH + GB) {
+      const int gi = i0 + l;
+      if (gi < N) yr[gi] = v;
+    }
+  }
+}
+
+// Hats, small N: cyclic Thomas with Sherman-Morrison, one thread per column.
+// scratch: 3N doubles per column.
+__global__ void k_gram_hat_small(int N, int nrhs, const double* h, const double2* x, int64_t ldx,
+                                 double2* y, int64_t ldy, double* scratch) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double* cp = scratch + (size_t)r * 5 * N;
+  double* dy_re = cp + N;
+  double* dy_im = dy_re + N;
+  double* zz = dy_im + N;
+  double* dd = zz + N;
+  const double2* xr = x + (size_t)r * ldx;
+  double2* yr = y + (size_t)r * ldy;
+  // G = T + u v^T: gam = -d_0, corner e = h_{N-1}/6
+  const double d0 = (h[N - 1] + h[0]) / 3.0;
+  const double gam = -d0;
+  const double ec = h[N - 1] / 6.0;
+  for (int i = 0; i < N; ++i) {
+    double d = (h[(i - 1 + N) % N] + h[i]) / 3.0;
+    if (i == 0) d -= gam;
+    if (i == N - 1) d -= ec * ec / gam;
+    dd[i] = d;
+  }
+  // forward sweep for two right-hand sides (b and u)
+  double pc = 0, pyr = 0, pyi = 0, pz = 0;
+  for (int i = 0; i < N; ++i) {
+    const double a = (i > 0) ? h[i - 1] / 6.0 : 0.0;
+    const double c = (i < N - 1) ? h[i] / 6.0 : 0.0;
+    const double den = dd[i] - a * pc;
+    const double u = (i == 0) ? gam : (i == N - 1 ? ec : 0.0);
+    cp[i] = c / den;
+    dy_re[i] = (xr[i].x - a * pyr) / den;
+    dy_im[i] = (xr[i].y - a * pyi) / den;
+    zz[i] = (u - a * pz) / den;
+    pc = cp[i]; pyr = dy_re[i]; pyi = dy_im[i]; pz = zz[i];
+  }
+  for (int i = N - 2; i >= 0; --i) {
+    dy_re[i] -= cp[i] * dy_re[i + 1];
+    dy_im[i] -= cp[i] * dy_im[i + 1];
+    zz[i] -= cp[i] * zz[i + 1];
+  }
+  // v = (1, 0, .., 0, ec/gam)
+  const double vz = zz[0] + ec / gam * zz[N - 1];
+  const double vyr = dy_re[0] + ec / gam * dy_re[N - 1];
+  const double vyi = dy_im[0] + ec / gam * dy_im[N - 1];
+  const double fr = vyr / (1.0 + vz), fi = vyi / (1.0 + vz);
+  for (int i = 0; i < N; ++i) yr[i] = make_double2(dy_re[i] - zz[i] * fr, dy_im[i] - zz[i] * fi);
+}
+
+// ---------------------------------------------------------------------------
+// plane-wave right-hand sides; rcs reduction
+// ---------------------------------------------------------------------------
+__global__ void k_rhs(int N, int nrhs, int basis, int p, const double* gx, const double* gw, const double* vx,
+                      const double* vy, const double* h, const double* tx, const double* ty,
+                      const double* phi, double k, double eta, double amp, double2* b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  double cph, sph;
+  sincos(phi[r], &sph, &cph);
+  double accx = 0, accy = 0;
+  const int npc = basis == AIM_PULSE ? 1 : 2;
+  for (int pc = 0; pc < npc; ++pc) {
+    int s;
+    double c0, c1;
+    if (basis == AIM_PULSE) { s = i; c0 = 1; c1 = 0; }
+    else if (pc == 0) { s = (i - 1 + N) % N; c0 = 0; c1 = 1; }
+    else { s = i; c0 = 1; c1 = -1; }
+    const int s1 = (s + 1) % N;
+    const double ax = vx[s], ay = vy[s], dx = vx[s1] - ax, dy = vy[s1] - ay;
+    // TE: (jk/eta) * eta * amp * t.(z x khat) = jk amp (t.(-khat_y, khat_x))
+    const double tdot = basis == AIM_PULSE ? 1.0 : (-tx[s] * sph + ty[s] * cph);
+    for (int q = 0; q < p; ++q) {
+      const double tau = gx[q];
+      const double px = ax + dx * tau, py = ay + dy * tau;
+      const double wk = h[s] * gw[q] * (c0 + c1 * tau) * tdot;
+      double sn, cs;
+      sincos(-k * (px * cph + py * sph), &sn, &cs);
+      accx += wk * cs;
+      accy += wk * sn;
+    }
+  }
+  double2 out;
+  if (basis == AIM_PULSE) out = make_double2(amp * accx, amp * accy);
+  else out = make_double2(-k * amp * accy, k * amp * accx);   // multiply by j k amp
+  b[(size_t)r * N + i] = out;
+}
+
+// partial dot products sum_i b_i J_i per column (no conjugate)
+__global__ void k_dotu_cols(int N, const double2* a, const double2* b, double* out) {
+  const int r = blockIdx.x;
+  __shared__ double sx[256], sy[256];
+  double ax = 0, ay = 0;
+  for (int i = threadIdx.x; i < N; i += 256) {
+    const double2 u = a[(size_t)r * N + i], v = b[(size_t)r * N + i];
+    ax += u.x * v.x - u.y * v.y;
+    ay += u.x * v.y + u.y * v.x;
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) { sx[threadIdx.x] += sx[threadIdx.x + s]; sy[threadIdx.x] += sy[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[2 * r] = sx[0]; out[2 * r + 1] = sy[0]; }
+}
+
+// ===========================================================================
+// host side
+// ===========================================================================
+aim_status dev_alloc(Ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return AIM_OK;
+  if (hipMalloc(p, bytes) != hipSuccess) { *p = nullptr; return AIM_E_OOM; }
+  c->allocs.push_back(*p);
+  c->dev_bytes += bytes;
+  return AIM_OK;
+}
+
+template <typename V>
+static aim_status upload(Ctx* c, V** dst, const void* src, size_t bytes) {
+  aim_status st = dev_alloc(c, (void**)dst, bytes);
+  if (st != AIM_OK) return st;
+  if (bytes) AIM_HIP_CHECK(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return AIM_OK;
+}
+
+#define TRY(x)                         \
+  do {                                 \
+    aim_status s_ = (x);               \
+    if (s_ != AIM_OK) return s_;       \
+  } while (0)
+
+aim_status setup_device(Ctx* c) {
+  HostTables& t = c->t;
+  const int N = t.N, n = t.n, m = t.m;
+  hipStream_t s = c->stream;
+  TRY(upload(c, &c->d_vx, t.vx.data(), N * 8));
+  TRY(upload(c, &c->d_vy, t.vy.data(), N * 8));
+  TRY(upload(c, &c->d_h, t.h.data(), N * 8));
+  TRY(upload(c, &c->d_tx, t.tx.data(), N * 8));
+  TRY(upload(c, &c->d_ty, t.ty.data(), N * 8));
+  TRY(upload(c, &c->d_glx, t.gl_x.data(), t.p * 8));
+  TRY(upload(c, &c->d_glw, t.gl_w.data(), t.p * 8));
+  std::vector<float> tmpf;
+  for (int ch = 0; ch < t.nch; ++ch) {
+    TRY(upload(c, &c->d_W[ch], t.W[ch].data(), t.W[ch].size() * 8));
+    TRY(upload(c, &c->d_at_w[ch], t.at_w[ch].data(), t.at_w[ch].size() * 8));
+    if (c->precision == AIM_MIXED) {
+      tmpf.assign(t.W[ch].begin(), t.W[ch].end());
+      TRY(upload(c, &c->d_Wf[ch], tmpf.data(), tmpf.size() * 4));
+      tmpf.assign(t.at_w[ch].begin(), t.at_w[ch].end());
+      TRY(upload(c, &c->d_at_wf[ch], tmpf.data(), tmpf.size() * 4));
+      AIM_HIP_CHECK(hipStreamSynchronize(s));
+    }
+  }
+  TRY(upload(c, &c->d_aidx, t.aidx.data(), t.aidx.size() * 4));
+  TRY(upload(c, &c->d_act_ix, t.act_ix.data(), t.act_ix.size() * 4));
+  TRY(upload(c, &c->d_row_ptr, t.row_ptr.data(), t.row_ptr.size() * 4));
+  TRY(upload(c, &c->d_at_ptr, t.at_ptr.data(), t.at_ptr.size() * 4));
+  TRY(upload(c, &c->d_at_basis, t.at_basis.data(), t.at_basis.size() * 4));
+  // twiddles
+  std::vector<double> tw;
+  twiddles(n, tw);
+  TRY(upload(c, &c->d_tw, tw.data(), tw.size() * 8));
+  if (c->precision == AIM_MIXED) {
+    tmpf.assign(tw.begin(), tw.end());
+    TRY(upload(c, &c->d_twf, tmpf.data(), tmpf.size() * 4));
+  }
+  AIM_HIP_CHECK(hipStreamSynchronize(s));
+
+  // kernel samples and spectrum (temporary n x n buffer)
+  double2* cfull = nullptr;
+  if (hipMalloc(&cfull, (size_t)n * n * sizeof(double2)) != hipSuccess) return AIM_E_OOM;
+  {
+    dim3 g((n + 255) / 256, n);
+    hipLaunchKernelGGL(k_sample_kernel, g, dim3(256), 0, s, m, n, t.eps, t.k, cfull);
+    c->ks = t.R + 4;
+    TRY(dev_alloc(c, (void**)&c->d_ksmall, (size_t)c->ks * c->ks * sizeof(double2)));
+    hipLaunchKernelGGL(k_small_table, dim3(c->ks), dim3(64 * ((c->ks + 63) / 64)), 0, s, m, n, c->ks, cfull,
+                       c->d_ksmall);
+    aim_status st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
+    if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
+    if (st != AIM_OK) { hipFree(cfull); return st; }
+    const int H = n / 2 + 1;
+    st = dev_alloc(c, (void**)&c->d_C, (size_t)H * H * sizeof(double2));
+    if (st == AIM_OK) st = dev_alloc(c, (void**)&c->d_Ca, (size_t)H * H * sizeof(double2));
+    if (st == AIM_OK && c->precision == AIM_MIXED) {
+      st = dev_alloc(c, (void**)&c->d_Cf, (size_t)H * H * sizeof(float2));
+      if (st == AIM_OK) st = dev_alloc(c, (void**)&c->d_Caf, (size_t)H * H * sizeof(float2));
+    }
+    if (st != AIM_OK) { hipFree(cfull); return st; }
+    hipLaunchKernelGGL(k_extract_quarter, dim3((H + 255) / 256, H), dim3(256), 0, s, n, cfull, c->d_C, c->d_Cf);
+    AIM_HIP_CHECK(hipStreamSynchronize(s));
+    hipFree(cfull);
+  }
+  TRY(apply_filter(c, INFINITY));
+
+  // near field
+  const int64_t nnz = (int64_t)t.nr_col.size();
+  c->nnz = nnz;
+  TRY(upload(c, &c->d_nr_ptr, t.nr_ptr.data(), t.nr_ptr.size() * 4));
+  TRY(upload(c, &c->d_nr_col, t.nr_col.data(), t.nr_col.size() * 4));
+  TRY(dev_alloc(c, (void**)&c->d_CS, nnz * sizeof(double2)));
+  if (t.basis == AIM_HAT) TRY(dev_alloc(c, (void**)&c->d_CN, nnz * sizeof(double2)));
+  {
+    std::vector<int32_t> rows(nnz);
+    for (int i = 0; i < N; ++i)
+      for (int q = t.nr_ptr[i]; q < t.nr_ptr[i + 1]; ++q) rows[q] = i;
+    std::vector<double> gl;
+    for (int pq : {16, 24, 32}) {
+      std::vector<double> x, w;
+      gauss_legendre01(pq, x, w);
+      gl.insert(gl.end(), x.begin(), x.end());
+      gl.insert(gl.end(), w.begin(), w.end());
+    }
+    int32_t *d_rows = nullptr, *d_anx = nullptr, *d_any = nullptr;
+    double* d_gl = nullptr;
+    bool ok = hipMalloc(&d_rows, std::max<int64_t>(nnz, 1) * 4) == hipSuccess;
+    ok = ok && hipMalloc(&d_anx, N * 4) == hipSuccess && hipMalloc(&d_any, N * 4) == hipSuccess;
+    ok = ok && hipMalloc(&d_gl, gl.size() * 8) == hipSuccess;
+    if (!ok) return AIM_E_OOM;
+    hipMemcpy(d_rows, rows.data(), nnz * 4, hipMemcpyHostToDevice);
+    hipMemcpy(d_anx, t.anc_x.data(), N * 4, hipMemcpyHostToDevice);
+    hipMemcpy(d_any, t.anc_y.data(), N * 4, hipMemcpyHostToDevice);
+    hipMemcpy(d_gl, gl.data(), gl.size() * 8, hipMemcpyHostToDevice);
+    NearGeo G{c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, N, t.k, d_gl};
+    if (nnz > 0) {
+      const int nb = 128;
+      hipLaunchKernelGGL(k_near_build, dim3((unsigned)((nnz + nb - 1) / nb)), dim3(nb), 0, s, G, t.basis, nnz,
+                         d_rows, c->d_nr_col, d_anx, d_any, c->d_W[0], c->d_W[1], c->d_W[2], c->d_W[3],
+                         c->d_ksmall, c->ks, c->d_CS, c->d_CN);
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    hipFree(d_rows);
+    hipFree(d_anx);
+    hipFree(d_any);
+    hipFree(d_gl);
+    if (e != hipSuccess) return AIM_E_HIP;
+  }
+
+  // matvec work buffers
+  c->nch_max = (t.basis == AIM_HAT) ? 3 : 1;
+  const size_t pairs = (size_t)c->nch_max * c->max_rhs;
+  const size_t be = 16;   // FP64 complex (FP32 uses the first half)
+  TRY(dev_alloc(c, &c->d_U, pairs * t.n_act * be));
+  TRY(dev_alloc(c, &c->d_V, pairs * t.n_act * be));
+  TRY(dev_alloc(c, &c->d_T, pairs * (size_t)t.nr * n * be));
+  TRY(dev_alloc(c, (void**)&c->d_tmp1, (size_t)N * c->max_rhs * 16));
+  TRY(dev_alloc(c, (void**)&c->d_tmp2, (size_t)N * c->max_rhs * 16));
+  TRY(dev_alloc(c, (void**)&c->d_rhs, (size_t)N * c->max_rhs * 16));
+  TRY(dev_alloc(c, (void**)&c->d_red, (size_t)std::max(5 * N, 64) * std::max(c->max_rhs, 1) * 8));
+  AIM_HIP_CHECK(hipStreamSynchronize(s));
+  return AIM_OK;
+}
+
+aim_status apply_filter(Ctx* c, double alpha) {
+  const int n = c->t.n, H = n / 2 + 1;
+  const bool all = !std::isfinite(alpha);
+  const double thr = all ? 0.0 : ((alpha * n) * c->t.eps / (2.0 * kPi)) * ((alpha * n) * c->t.eps / (2.0 * kPi));
+  hipLaunchKernelGGL(k_filter, dim3((H + 255) / 256, H), dim3(256), 0, c->stream, n, thr, all, c->d_C, c->d_Ca,
+                     c->d_Caf);
+  AIM_HIP_CHECK(hipGetLastError());
+  c->alpha = alpha;
+  c->filtered = !all;
+  return AIM_OK;
+}
+
+// grid part: V = [F^-1 (Chat . F(Lambda x))]_restr for nch channels
+template <typename T>
+static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int nrhs, const double2* x,
+                             int64_t ldx) {
+  HostTables& t = c->t;
+  hipStream_t s = c->stream;
+  const int pairs = nch * nrhs;
+  cplx<T>* U = (cplx<T>*)c->d_U;
+  cplx<T>* V = (cplx<T>*)c->d_V;
+  cplx<T>* Tb = (cplx<T>*)c->d_T;
+  const bool f32 = sizeof(T) == 4;
+  dim3 ga((t.n_act + 255) / 256, pairs);
+  if (f32) {
+    hipLaunchKernelGGL((k_anterp<T, float>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr, c->d_at_basis,
+                       c->d_at_wf[chans[0]], c->d_at_wf[chans[nch > 1 ? 1 : 0]], c->d_at_wf[chans[nch > 2 ? 2 : 0]],
+                       x, ldx, U);
+  } else {
+    hipLaunchKernelGGL((k_anterp<T, double>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr, c->d_at_basis,
+                       c->d_at_w[chans[0]], c->d_at_w[chans[nch > 1 ? 1 : 0]], c->d_at_w[chans[nch > 2 ? 2 : 0]],
+                       x, ldx, U);
+  }
+  AIM_HIP_CHECK(hipGetLastError());
+  const cplx<T>* tw = f32 ? (const cplx<T>*)c->d_twf : (const cplx<T>*)c->d_tw;
+  const cplx<T>* Cq = f32 ? (const cplx<T>*)(filt ? (void*)c->d_Caf : (void*)c->d_Cf)
+                          : (const cplx<T>*)(filt ? (void*)c->d_Ca : (void*)c->d_C);
+  TRY(launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, pairs, Tb, tw, s));
+  TRY(launch_cols<T>(t.n, 0, Tb, t.nr, pairs, Cq, tw, s));
+  TRY(launch_rows_inv<T>(t.n, Tb, t.nr, c->d_row_ptr, c->d_act_ix, pairs, V, t.n_act, tw, s));
+  return AIM_OK;
+}
+
+template <typename T>
+static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near, const double2* Cn, int nrhs,
+                         const double2* x, int64_t ldx, double2* y, int64_t ldy, double2 scale) {
+  HostTables& t = c->t;
+  const int threads = 256;
+  dim3 g((unsigned)(((size_t)t.N * 16 + threads - 1) / threads));
+  const cplx<T>* V = (const cplx<T>*)c->d_V;
+  const double2* C = near ? Cn : nullptr;
+  if (sizeof(T) == 4) {
+    hipLaunchKernelGGL((k_interp_near<T, float>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
+                       c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
+                       c->d_aidx, V, t.n_act, c->d_nr_ptr, c->d_nr_col, C, x, ldx, y, ldy, scale);
+  } else {
+    hipLaunchKernelGGL((k_interp_near<T, double>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
+                       c->d_W[chans[0]], c->d_W[chans[nch > 1 ? 1 : 0]], c->d_W[chans[nch > 2 ? 2 : 0]], sg,
+                       c->d_aidx, V, t.n_act, c->d_nr_ptr, c->d_nr_col, C, x, ldx, y, ldy, scale);
+  }
+  AIM_HIP_CHECK(hipGetLastError());
+  return AIM_OK;
+}
+
+template <typename T>
+static aim_status op_grid(Ctx* c, int base_op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy,
+                          double2 scale) {
+  static const int chS[1] = {0};
+  static const int chN[3] = {1, 2, 3};
+  const double k2 = c->t.k * c->t.k;
+  switch (base_op) {
+    case AIM_OP_S:
+      TRY(grid_apply<T>(c, chS, 1, false, nrhs, x, ldx));
+      return interp<T>(c, chS, 1, 0.0, true, c->d_CS, nrhs, x, ldx, y, ldy, scale);
+    case AIM_OP_S_ALPHA:
+      TRY(grid_apply<T>(c, chS, 1, true, nrhs, x, ldx));
+      return interp<T>(c, chS, 1, 0.0, false, nullptr, nrhs, x, ldx, y, ldy, scale);
+    case AIM_OP_N:
+      TRY(grid_apply<T>(c, chN, 3, false, nrhs, x, ldx));
+      return interp<T>(c, chN, 3, -k2, true, c->d_CN, nrhs, x, ldx, y, ldy, scale);
+  }
+  return AIM_E_ARG;
+}
+
+static aim_status gram_inv(Ctx* c, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy) {
+  HostTables& t = c->t;
+  const int N = t.N;
+  if (t.basis == AIM_PULSE) {
+    hipLaunchKernelGGL(k_gram_pulse, dim3((N + 255) / 256, nrhs), dim3(256), 0, c->stream, N, nrhs, c->d_h, x, ldx,
+                       y, ldy);
+  } else if (N >= GM) {
+    const int nblk = (N + GB - 1) / GB;
+    hipLaunchKernelGGL(k_gram_hat_blocks, dim3((nblk + 63) / 64, nrhs), dim3(64), 0, c->stream, N, nrhs, c->d_h, x,
+                       ldx, y, ldy);
+  } else {
+    hipLaunchKernelGGL(k_gram_hat_small, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, N, nrhs, c->d_h, x, ldx,
+                       y, ldy, c->d_red);
+  }
+  AIM_HIP_CHECK(hipGetLastError());
+  return AIM_OK;
+}
+
+aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy) {
+  const bool f32 = (op & AIM_OP_GRID_FP32) != 0;
+  const int base = op & 0xff;
+  if (nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
+  if (f32 && c->precision != AIM_MIXED) return AIM_E_ARG;
+  const bool hat = c->t.basis == AIM_HAT;
+  if ((base == AIM_OP_N || base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF) && !hat) return AIM_E_ARG;
+  const double2 one = make_double2(1.0, 0.0);
+  auto grid = [&](int b, const double2* xx, int64_t lx, double2* yy, int64_t ly, double2 sc) {
+    return f32 ? op_grid<float>(c, b, nrhs, xx, lx, yy, ly, sc) : op_grid<double>(c, b, nrhs, xx, lx, yy, ly, sc);
+  };
+  const int64_t N = c->t.N;
+  switch (base) {
+    case AIM_OP_S:
+    case AIM_OP_S_ALPHA:
+    case AIM_OP_N:
+      return grid(base, x, ldx, y, ldy, one);
+    case AIM_OP_TM:
+      return grid(AIM_OP_S, x, ldx, y, ldy, make_double2(0.0, c->t.k * c->t.eta));
+    case AIM_OP_GRAM_INV:
+      return gram_inv(c, nrhs, x, ldx, y, ldy);
+    case AIM_OP_TE_CP:
+    case AIM_OP_TE_CP_UNF:
+      TRY(grid(AIM_OP_N, x, ldx, c->d_tmp1, N, one));
+      TRY(gram_inv(c, nrhs, c->d_tmp1, N, c->d_tmp2, N));
+      TRY(grid(base == AIM_OP_TE_CP ? AIM_OP_S_ALPHA : AIM_OP_S, c->d_tmp2, N, c->d_tmp1, N, one));
+      return gram_inv(c, nrhs, c->d_tmp1, N, y, ldy);
+  }
+  return AIM_E_ARG;
+}
+
+aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b) {
+  HostTables& t = c->t;
+  if (nrhs < 1) return AIM_E_ARG;
+  double* d_phi = nullptr;
+  AIM_HIP_CHECK(hipMalloc(&d_phi, nrhs * 8));
+  hipMemcpyAsync(d_phi, phi_host, nrhs * 8, hipMemcpyHostToDevice, c->stream);
+  hipLaunchKernelGGL(k_rhs, dim3((t.N + 127) / 128, nrhs), dim3(128), 0, c->stream, t.N, nrhs, t.basis, t.p,
+                     c->d_glx, c->d_glw, c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, d_phi, t.k, t.eta, amp, b);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  hipFree(d_phi);
+  return e == hipSuccess ? AIM_OK : AIM_E_HIP;
+}
+
+aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma) {
+  HostTables& t = c->t;
+  if (t.basis != AIM_PULSE || nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
+  TRY(rhs_planewave(c, nrhs, phi_host, 1.0, c->d_rhs));
+  double* d_out = nullptr;
+  AIM_HIP_CHECK(hipMalloc(&d_out, nrhs * 16));
+  hipLaunchKernelGGL(k_dotu_cols, dim3(nrhs), dim3(256), 0, c->stream, t.N, c->d_rhs, J, d_out);
+  std::vector<double> h(2 * nrhs);
+  hipMemcpyAsync(h.data(), d_out, nrhs * 16, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  hipFree(d_out);
+  if (e != hipSuccess) return AIM_E_HIP;
+  for (int r = 0; r < nrhs; ++r) sigma[r] = t.k * t.eta * t.eta / 4.0 * (h[2 * r] * h[2 * r] + h[2 * r + 1] * h[2 * r + 1]);
+  return AIM_OK;
+}
+
+aim_status eval_green(Ctx* c, int n, const double* R, double2* out) {
+  if (n < 0) return AIM_E_ARG;
+  if (n == 0) return AIM_OK;
+  hipLaunchKernelGGL(k_eval_green, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, R, c->t.k, out);
+  AIM_HIP_CHECK(hipGetLastError());
+  return AIM_OK;
+}
+
+}  // namespace aim

@@ -1,0 +1,40 @@
+"""C-ABI library: loads and exports every function include/aim.h declares
+(no compute calls; runs without a GPU)."""
+import ctypes
+
+import pytest
+
+from paper_2606_10784_amd import aim
+from paper_2606_10784_amd import workloads as wl
+
+
+def test_library_exports_every_declared_function():
+    lib = aim._lib()
+    names = aim.header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(aim.EXPORTS)
+
+
+def test_strerror_and_footprint_are_host_only():
+    lib = aim._lib()
+    assert lib.aim_strerror(aim.AIM_E_GEOM) == b"stencil leaves the grid"
+    w = wl.cylinder_large()
+    fp = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=1)
+    # T intermediate alone: nr x n x 16 bytes, nr <= m
+    assert 1024 * 2048 * 16 < fp < 2e9
+    fp8 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=8)
+    assert fp8 > 4 * fp
+
+
+def test_setup_rejects_bad_arguments_without_device():
+    lib = aim._lib()
+    h = ctypes.c_void_p()
+    assert lib.aim_setup(None, ctypes.byref(h)) == aim.AIM_E_ARG
+    p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, 48, 0.1)   # m not a power of two
+    assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+    p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, 16, 0.1)   # contour leaves grid
+    assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_GEOM
+    assert lib.aim_filter(None, 1.0) == aim.AIM_E_ARG
+    assert lib.aim_matvec(None, 0, 1, None, None) == aim.AIM_E_ARG

@@ -1,0 +1,215 @@
+"""GPU parity of the AIM operators against the CPU FP64 oracle.
+
+All calls go through the C ABI (ctypes binding).  Element-wise bound for
+FP64 paths: |y_gpu - y_oracle| <= 1e-12 max|y_oracle|; the FP32-grid path:
+1e-5 (relative to the same scale)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import aim as oaim
+from oracle import excitation
+from paper_2606_10784_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2606_10784_amd import aim  # noqa: E402
+
+K = wl.K0
+ETA = wl.ETA0
+
+
+def _t(x):
+    x = np.asarray(x)
+    if x.ndim == 2:
+        x = x.T
+    return torch.from_numpy(np.ascontiguousarray(x.astype(np.complex128))).cuda()
+
+
+def _n(t):
+    a = t.cpu().numpy()
+    return a.T if a.ndim == 2 else a
+
+
+def _relmax(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+# --------------------------------------------------------------------------
+# pulse basis, circle: N = 500 (ragged w.r.t. 16-lane groups), m = 64
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cyl():
+    xy = wl.circle(1.0, 500)
+    m, eps = 64, 0.1
+    alpha = wl.alpha_half_bins(eps)
+    orc = oaim.AimOracle(xy, K, ETA, 0, m, eps, alpha=alpha)
+    ctx = aim.Context(xy, K, ETA, 0, m, eps, max_rhs=4, precision=aim.AIM_MIXED)
+    ctx.filter(alpha)
+    return xy, orc, ctx
+
+
+def test_green_function_device_vs_scipy(cyl):
+    from scipy import special
+    _, _, ctx = cyl
+    R = np.concatenate([np.geomspace(1e-6, 1.0, 300), np.linspace(1.0, 400.0, 300)])
+    g = _n(ctx.eval_green(torch.from_numpy(R).cuda()))
+    ref = -0.25j * special.hankel2(0, K * R)
+    err = np.abs(g - ref) / np.abs(ref)
+    print("green rel err max", err.max())
+    assert err.max() < 1e-13
+
+
+def test_near_field_entries_match_oracle(cyl):
+    xy, orc, ctx = cyl
+    pairs = orc.near_sel_pairs
+    C = orc.Cnear['S']
+    worst = 0.0
+    scale = np.max(np.abs(C))
+    for row in (0, 1, 137, 499):
+        cols, vals = ctx.near_row('S', row)
+        sel = pairs[:, 0] == row
+        assert np.array_equal(cols, pairs[sel, 1])
+        worst = max(worst, float(np.max(np.abs(vals - C[sel]))) / scale)
+    print("near S entries rel err", worst)
+    assert worst < 1e-13
+
+
+@pytest.mark.parametrize("op", ["S_ALPHA", "S", "TM"])
+def test_matvec_fp64_pulse(cyl, op):
+    xy, orc, ctx = cyl
+    x = wl.probe_vector(500, seed=11)
+    y = _n(ctx.matvec(op, _t(x)))
+    ref = orc.apply(op, x)
+    err = _relmax(y, ref)
+    print(op, "rel err", err)
+    assert err < 1e-12
+
+
+def test_matvec_multi_rhs_equals_columns(cyl):
+    xy, orc, ctx = cyl
+    X = wl.probe_vector(500, nrhs=3, seed=12)
+    Y = _n(ctx.matvec("S", _t(X)))
+    for r in range(3):
+        yr = _n(ctx.matvec("S", _t(X[:, r])))
+        assert np.array_equal(Y[:, r], yr)          # bitwise: columns are independent
+    ref = orc.apply("S", X)
+    assert _relmax(Y, ref) < 1e-12
+
+
+def test_matvec_deterministic(cyl):
+    _, _, ctx = cyl
+    x = _t(wl.probe_vector(500, seed=13))
+    a, b = ctx.matvec("S", x), ctx.matvec("S", x)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("op", ["S_ALPHA", "S"])
+def test_matvec_grid_fp32(cyl, op):
+    xy, orc, ctx = cyl
+    x = wl.probe_vector(500, seed=14)
+    y = _n(ctx.matvec(aim.OPS[op] | aim.AIM_OP_GRID_FP32, _t(x)))
+    ref = orc.apply(op, x)
+    err = _relmax(y, ref)
+    print(op, "fp32-grid rel err", err)
+    assert err < 1e-5
+
+
+def test_rhs_and_rcs_match_oracle(cyl):
+    xy, orc, ctx = cyl
+    ph = np.array([0.0, 0.4, 2.5])
+    b = _n(ctx.rhs_planewave(ph))
+    ref = excitation.rhs_tm(xy, 0, K, ph)
+    assert _relmax(b, ref) < 1e-13
+    J = wl.probe_vector(500, nrhs=3, seed=15)
+    sig = ctx.rcs(_t(J), ph)
+    sref = excitation.rcs_monostatic_tm(xy, 0, K, ETA, J, ph)
+    assert np.max(np.abs(sig - sref) / sref) < 1e-12
+
+
+def test_unfiltered_reset_and_info(cyl):
+    xy, orc, ctx = cyl
+    inf = ctx.info()
+    assert inf["n_unknowns"] == 500 and inf["n_pad"] == 128 and inf["n_active"] == orc.act.size
+    assert inf["near_nnz_s"] == orc.near_pairs.shape[0]
+    ctx.filter(math.inf)
+    x = wl.probe_vector(500, seed=16)
+    y = _n(ctx.matvec("S_ALPHA", _t(x)))
+    ref = orc.op_S(x, near=False)
+    assert _relmax(y, ref) < 1e-12
+    ctx.filter(orc.alpha)
+
+
+def test_invalid_calls_rejected(cyl):
+    _, _, ctx = cyl
+    x = _t(wl.probe_vector(500, seed=1))
+    with pytest.raises(aim.AimError):
+        ctx.matvec("N", x)                          # N needs the hat basis
+    with pytest.raises(aim.AimError):
+        ctx.matvec("S", _t(wl.probe_vector(500, nrhs=5, seed=1)))   # nrhs > max_rhs
+    with pytest.raises(aim.AimError):
+        ctx.filter(-1.0)
+
+
+# --------------------------------------------------------------------------
+# hat basis, star contour (TE operators)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def star():
+    xy = wl.star5(0.8, 300)
+    eps = 0.05
+    m = wl.grid_side_for(xy, eps)
+    alpha = wl.alpha_half_bins(eps)
+    orc = oaim.AimOracle(xy, K, ETA, 1, m, eps, alpha=alpha)
+    ctx = aim.Context(xy, K, ETA, 1, m, eps, max_rhs=2, precision=aim.AIM_MIXED)
+    ctx.filter(alpha)
+    return xy, orc, ctx
+
+
+@pytest.mark.parametrize("op", ["S_ALPHA", "S", "N", "GRAM_INV", "TE_CP", "TE_CP_UNF"])
+def test_matvec_fp64_hat(star, op):
+    xy, orc, ctx = star
+    x = wl.probe_vector(300, seed=21)
+    y = _n(ctx.matvec(op, _t(x)))
+    ref = orc.apply(op, x)
+    err = _relmax(y, ref)
+    print(op, "hat rel err", err)
+    assert err < 1e-12
+
+
+def test_near_field_hat_entries(star):
+    xy, orc, ctx = star
+    pairs = orc.near_sel_pairs
+    for op in ("S", "N"):
+        C = orc.Cnear[op]
+        scale = np.max(np.abs(C))
+        for row in (0, 150, 299):
+            cols, vals = ctx.near_row(op, row)
+            sel = pairs[:, 0] == row
+            assert np.array_equal(cols, pairs[sel, 1])
+            assert np.max(np.abs(vals - C[sel])) < 1e-13 * scale
+
+
+def test_te_rhs(star):
+    xy, orc, ctx = star
+    ph = np.array([0.3, 1.9])
+    b = _n(ctx.rhs_planewave(ph))
+    ref = excitation.rhs_te(xy, 1, K, ETA, ph)
+    assert _relmax(b, ref) < 1e-13
+
+
+def test_hat_gram_small_n_path():
+    # N < 128 uses the single-thread cyclic solver
+    xy = wl.star5(0.5, 90)
+    eps = 0.05
+    m = wl.grid_side_for(xy, eps)
+    ctx = aim.Context(xy, K, ETA, 1, m, eps)
+    from oracle import galerkin
+    x = wl.probe_vector(90, seed=3)
+    y = _n(ctx.matvec("GRAM_INV", _t(x)))
+    assert _relmax(y, galerkin.gram_solve(xy, 1, x)) < 1e-13
