@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the filtered-AIM EFIE hot path on one MI355X.
+
+One step = one full TM-EFIE restarted-GMRES solve (plain FP64, restart 100)
+to a 1e-6 relative residual on the PEC cylinder with ka = 200
+(N = 16384 pulse segments, AIM grid 1024 x 1024 at lambda/15 padded to
+2048 x 2048, half of the spectrum kept by the filter), plane wave at 0 deg.
+Inputs (geometry, right-hand side, spectra, near field) are resident in HBM
+before the timed region.  `value` is AIM matvecs/s over the timed solves;
+solves/s, solve latency percentiles, matvec-only throughput and the
+mixed-precision (FP32 grid + FP64 refinement) solve are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cylinder_ka200",
+                    choices=["cylinder_ka200", "cylinder_ka2pi"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
+    return ap.parse_args()
+
+
+def kernel_bytes(kid, inf, nch=1, nrhs=1, b=16):
+    """Algorithmic HBM bytes of one launch of pipeline kernel `kid`."""
+    N, n, nr, nact = inf["n_unknowns"], inf["n_pad"], inf["active_rows"], inf["n_active"]
+    H = n // 2 + 1
+    nnz = inf["near_nnz_s"]
+    p = nch * nrhs
+    if kid == 0:   # anterpolation: x, transposed stencils, U
+        return N * 16 * nrhs + N * 16 * (4 + 8) + (nact + 1) * 4 + p * nact * b
+    if kid == 1:   # row FFTs: U in, T out
+        return p * nact * b + nact * 4 + p * nr * n * b
+    if kid == 2:   # column FFT . spectrum . inverse: T in and out, quarter spectrum once
+        return 2 * p * nr * n * b + H * H * b
+    if kid == 3:   # inverse row FFTs: T in, V out
+        return p * nr * n * b + p * nact * b + nact * 4
+    if kid == 4:   # interpolation + near field: stencils, V, near CSR, x, y
+        return N * 16 * (8 + 4) + p * nact * b + nnz * (16 + 4) + (N + 1) * 4 + 2 * N * 16 * nrhs
+    raise ValueError(kid)
+
+
+def kernel_flops(kid, inf):
+    n, nr = inf["n_pad"], inf["active_rows"]
+    lg = math.log2(n)
+    if kid == 1 or kid == 3:
+        return nr * 5 * n * lg
+    if kid == 2:
+        return n * (2 * 5 * n * lg + 6 * n)
+    return 0.0
+
+
+def cpu_baseline(w, sample_every=64, reps=2):
+    """Oracle AIM matvec on the host: full direct-Toeplitz grid product plus
+    the near-field product of every `sample_every`-th row (scaled)."""
+    import numpy as np
+    from oracle import aim as oaim
+    from paper_2606_10784_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    A = oaim.AimOracle(w.xy, w.k, w.eta, w.basis, w.m, w.eps, alpha=w.alpha, near=False)
+    rows = np.arange(0, w.n_unknowns, sample_every)
+    A.near_pairs = A._near_pairs()
+    A._build_near(("S",), rows)
+    x = wl.probe_vector(w.n_unknowns, seed=1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A.op_S(x, near=False)
+    t_grid = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        A.near_apply("S", x)
+    t_near = (time.perf_counter() - t0) / reps * (w.n_unknowns / rows.size)
+    per = t_grid + t_near
+    return {"value": 1.0 / per, "unit": "AIM matvecs/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"{reps} oracle S_AIM matvecs at {w.name}: direct Toeplitz sum over all "
+                       f"{A.act.size} active grid points (measured) + near-field product of "
+                       f"{rows.size} of {w.n_unknowns} rows scaled to all rows; {per:.2f} s per matvec")}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2606_10784_amd import aim
+    from paper_2606_10784_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    w = wl.cylinder_large() if args.workload == "cylinder_ka200" else wl.cylinder_small()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    t_setup = time.perf_counter()
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, quad=w.quad, near_radius=w.near_radius,
+                      precision=aim.AIM_MIXED, max_rhs=1, stream=stream)
+    ctx.filter(w.alpha)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    inf = ctx.info()
+    b = ctx.rhs_planewave(0.0)
+    print(f"[bench] setup {t_setup:.2f} s  N={inf['n_unknowns']} n={inf['n_pad']} active={inf['n_active']} "
+          f"rows={inf['active_rows']} near={inf['near_nnz_s']}", file=sys.stderr, flush=True)
+
+    # warm-up solves
+    for i in range(args.warmup):
+        x, info = ctx.solve("TM", b, tol=args.tol, restart=args.restart)
+        print(f"[bench] warmup {i} iters={info[0]['iterations']} resid={info[0]['resid_true']:.2e}",
+              file=sys.stderr, flush=True)
+
+    # rank the pipeline kernels on a short matvec loop (event-timed)
+    xprobe = torch.from_numpy(wl.probe_vector(w.n_unknowns, seed=3)).to(dev)
+    yprobe = torch.empty_like(xprobe)
+    ktimes = {}
+    for kid in range(5):
+        aim.aim_profile_start(ctx, kid, 1, 64)
+        for _ in range(10):
+            ctx.matvec("TM", xprobe, yprobe)
+        ms, ns, nl = aim.aim_profile_stop(ctx)
+        ktimes[kid] = ms
+    dom = max(ktimes, key=ktimes.get)
+    names = ["anterp", "rows_fwd", "cols_conv", "rows_inv", "interp_near"]
+
+    # ---------------- timed region: K FP64 solves ----------------
+    aim.aim_profile_start(ctx, dom, 1, 100000)
+    torch.cuda.synchronize()
+    lat, mv, its, res = [], 0, [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        x, info = ctx.solve("TM", b, tol=args.tol, restart=args.restart)
+        lat.append(time.perf_counter() - ts)
+        mv += info[0]["matvecs"]
+        its.append(info[0]["iterations"])
+        res.append(info[0]["resid_true"])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    dom_ms, dom_samples, dom_launches = aim.aim_profile_stop(ctx)
+    # -------------------------------------------------------------
+    print(f"[bench] timed {args.steps} solves in {t_total:.3f} s", file=sys.stderr, flush=True)
+
+    # matvec-only throughput (events around a back-to-back loop)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(5):
+        ctx.matvec("TM", xprobe, yprobe)
+    e0.record()
+    for _ in range(args.matvecs):
+        ctx.matvec("TM", xprobe, yprobe)
+    e1.record()
+    torch.cuda.synchronize()
+    mv_ms = e0.elapsed_time(e1) / args.matvecs
+    e0.record()
+    for _ in range(args.matvecs):
+        ctx.matvec(aim.AIM_OP_TM | aim.AIM_OP_GRID_FP32, xprobe, yprobe)
+    e1.record()
+    torch.cuda.synchronize()
+    mv32_ms = e0.elapsed_time(e1) / args.matvecs
+
+    # mixed-precision solve at the same accuracy (reported beside value)
+    tm0 = time.perf_counter()
+    xm, infm = ctx.solve("TM", b, tol=args.tol, restart=args.restart, precision=aim.AIM_MIXED)
+    t_mixed = time.perf_counter() - tm0
+    dx = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    alg_b = kernel_bytes(dom, inf)
+    achieved = alg_b / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    value = mv / t_total
+    lat_ms = sorted(1e3 * v for v in lat)
+
+    def pct(p):
+        return lat_ms[min(len(lat_ms) - 1, int(math.ceil(p / 100.0 * len(lat_ms))) - 1)]
+
+    out = {
+        "metric": "AIM matvecs/s + solves/s at 1e-6 residual vs FP64 plain; p50/p99 latency",
+        "value": value,
+        "unit": "AIM matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": w.name, "form": "TM-EFIE", "solver": f"GMRES({args.restart}) FP64",
+                   "tol": args.tol, "N": inf["n_unknowns"], "grid": f"{w.m}x{w.m} pad {inf['n_pad']}",
+                   "eps_over_lambda": w.eps, "filter_alpha": w.alpha},
+        "solves_per_s": args.steps / t_total,
+        "latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "iterations": its,
+        "resid_true": max(res),
+        "matvec_only": {"fp64_ms": mv_ms, "fp64_per_s": 1e3 / mv_ms, "fp32_grid_ms": mv32_ms,
+                        "fp32_grid_per_s": 1e3 / mv32_ms},
+        "mixed_solve": {"seconds": t_mixed, "iterations": infm[0]["iterations"], "outer": infm[0]["outer"],
+                        "resid_true": infm[0]["resid_true"], "rel_diff_vs_fp64": dx,
+                        "speedup_vs_fp64": (t_total / args.steps) / t_mixed},
+        "kernel_ms": {names[k]: v for k, v in ktimes.items()},
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_b, "avg_ms": dom_ms, "samples": dom_samples,
+                     "flops_per_launch": kernel_flops(dom, inf)},
+        "setup_s": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,18 @@ aim_status aim_eval_green(aim_ctx ctx, int32_t n, const void* R_dev, void* out_d
 aim_status aim_near_row(aim_ctx ctx, int32_t op, int32_t row, int32_t cap,
                         int32_t* cols_host, double* vals_host, int32_t* len);
 
+/* Kernel timing with HIP events recorded on the context's stream around the
+   launches of one kernel of the matvec pipeline (for benchmarking).  From
+   aim_profile_start on, every `every`-th launch of `kernel` (up to
+   max_samples) is bracketed by a pair of events; aim_profile_stop
+   synchronises the stream, returns the mean duration in ms of the sampled
+   launches, the number sampled and the number of launches seen, and stops
+   recording.  Errors: AIM_E_ARG (kernel id, every < 1), AIM_E_STATE (stop
+   without start), AIM_E_HIP.                                                  */
+enum { AIM_K_ANTERP = 0, AIM_K_ROWS_FWD = 1, AIM_K_COLS = 2, AIM_K_ROWS_INV = 3, AIM_K_INTERP = 4 };
+aim_status aim_profile_start(aim_ctx ctx, int32_t kernel, int32_t every, int32_t max_samples);
+aim_status aim_profile_stop(aim_ctx ctx, double* avg_ms, int64_t* samples, int64_t* launches);
+
 void aim_destroy(aim_ctx ctx);
 const char* aim_strerror(aim_status s);
 

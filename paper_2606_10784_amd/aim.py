@@ -25,6 +25,7 @@ AIM_OP_S, AIM_OP_S_ALPHA, AIM_OP_N, AIM_OP_GRAM_INV, AIM_OP_TM, AIM_OP_TE_CP, AI
 AIM_OP_GRID_FP32 = 0x100
 AIM_TM_EFIE, AIM_TE_CALDERON, AIM_TE_CALDERON_UNFILTERED = range(3)
 AIM_FP64, AIM_MIXED = 0, 1
+AIM_K_ANTERP, AIM_K_ROWS_FWD, AIM_K_COLS, AIM_K_ROWS_INV, AIM_K_INTERP = range(5)
 
 OPS = {'S': AIM_OP_S, 'S_ALPHA': AIM_OP_S_ALPHA, 'N': AIM_OP_N, 'GRAM_INV': AIM_OP_GRAM_INV,
        'TM': AIM_OP_TM, 'TE_CP': AIM_OP_TE_CP, 'TE_CP_UNF': AIM_OP_TE_CP_UNF}
@@ -80,6 +81,9 @@ EXPORTS = {
     "aim_near_row": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int32)]),
+    "aim_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "aim_profile_stop": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "aim_destroy": (None, [ctypes.c_void_p]),
     "aim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -289,6 +293,20 @@ def aim_near_row(ctx, op, row):
                                vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)),
            "aim_near_row")
     return cols, vals[0::2] + 1j * vals[1::2]
+
+
+def aim_profile_start(ctx, kernel, every=1, max_samples=4096):
+    _check(_lib().aim_profile_start(ctx.handle, int(kernel), int(every), int(max_samples)), "aim_profile_start")
+
+
+def aim_profile_stop(ctx):
+    """(mean ms of the sampled launches, samples, launches seen)"""
+    ms = ctypes.c_double()
+    ns = ctypes.c_int64()
+    nl = ctypes.c_int64()
+    _check(_lib().aim_profile_stop(ctx.handle, ctypes.byref(ms), ctypes.byref(ns), ctypes.byref(nl)),
+           "aim_profile_stop")
+    return ms.value, ns.value, nl.value
 
 
 def header_functions(path=None):

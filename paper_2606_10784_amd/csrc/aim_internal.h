@@ -126,6 +126,28 @@ struct Ctx {
   size_t dev_bytes = 0;
   GmresWork gw;
   std::vector<void*> allocs;
+  // event timing of one pipeline kernel (aim_profile_start / stop)
+  int prof_kernel = -1, prof_every = 1, prof_max = 0;
+  int64_t prof_launches = 0;
+  std::vector<hipEvent_t> ev0, ev1;
+  int ev_used = 0;
+};
+
+// brackets one launch of pipeline kernel `kid` with events when profiling
+struct ProfScope {
+  Ctx* c;
+  bool on = false;
+  int slot = -1;
+  ProfScope(Ctx* cc, int kid) : c(cc) {
+    if (c->prof_kernel != kid) return;
+    const int64_t n = c->prof_launches++;
+    if (n % c->prof_every != 0 || c->ev_used >= c->prof_max) return;
+    slot = c->ev_used++;
+    on = hipEventRecord(c->ev0[slot], c->stream) == hipSuccess;
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(c->ev1[slot], c->stream);
+  }
 };
 
 // kernels / launchers (aim_kernels.hip)

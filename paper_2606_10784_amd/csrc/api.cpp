@@ -170,8 +170,47 @@ aim_status aim_near_row(aim_ctx ctx, int32_t op, int32_t row, int32_t cap, int32
   return AIM_OK;
 }
 
+aim_status aim_profile_start(aim_ctx ctx, int32_t kernel, int32_t every, int32_t max_samples) {
+  if (!ctx || kernel < AIM_K_ANTERP || kernel > AIM_K_INTERP || every < 1 || max_samples < 1) return AIM_E_ARG;
+  Ctx& c = ctx->c;
+  while ((int)c.ev0.size() < max_samples) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return AIM_E_HIP;
+    if (hipEventCreate(&b) != hipSuccess) return AIM_E_HIP;
+    c.ev0.push_back(a);
+    c.ev1.push_back(b);
+  }
+  c.prof_kernel = kernel;
+  c.prof_every = every;
+  c.prof_max = max_samples;
+  c.prof_launches = 0;
+  c.ev_used = 0;
+  return AIM_OK;
+}
+
+aim_status aim_profile_stop(aim_ctx ctx, double* avg_ms, int64_t* samples, int64_t* launches) {
+  if (!ctx) return AIM_E_ARG;
+  Ctx& c = ctx->c;
+  if (c.prof_kernel < 0) return AIM_E_STATE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return AIM_E_HIP;
+  double tot = 0.0;
+  for (int i = 0; i < c.ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c.ev0[i], c.ev1[i]) != hipSuccess) return AIM_E_HIP;
+    tot += ms;
+  }
+  if (avg_ms) *avg_ms = c.ev_used ? tot / c.ev_used : 0.0;
+  if (samples) *samples = c.ev_used;
+  if (launches) *launches = c.prof_launches;
+  c.prof_kernel = -1;
+  c.ev_used = 0;
+  return AIM_OK;
+}
+
 void aim_destroy(aim_ctx ctx) {
   if (!ctx) return;
+  for (hipEvent_t e : ctx->c.ev0) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->c.ev1) (void)hipEventDestroy(e);
   free_ctx(&ctx->c);
   delete ctx;
 }

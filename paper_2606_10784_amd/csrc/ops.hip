@@ -788,6 +788,8 @@ static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int n
   cplx<T>* Tb = (cplx<T>*)c->d_T;
   const bool f32 = sizeof(T) == 4;
   dim3 ga((t.n_act + 255) / 256, pairs);
+  {
+  ProfScope ps(c, AIM_K_ANTERP);
   if (f32) {
     hipLaunchKernelGGL((k_anterp<T, float>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr, c->d_at_basis,
                        c->d_at_wf[chans[0]], c->d_at_wf[chans[nch > 1 ? 1 : 0]], c->d_at_wf[chans[nch > 2 ? 2 : 0]],
@@ -797,13 +799,23 @@ static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int n
                        c->d_at_w[chans[0]], c->d_at_w[chans[nch > 1 ? 1 : 0]], c->d_at_w[chans[nch > 2 ? 2 : 0]],
                        x, ldx, U);
   }
+  }
   AIM_HIP_CHECK(hipGetLastError());
   const cplx<T>* tw = f32 ? (const cplx<T>*)c->d_twf : (const cplx<T>*)c->d_tw;
   const cplx<T>* Cq = f32 ? (const cplx<T>*)(filt ? (void*)c->d_Caf : (void*)c->d_Cf)
                           : (const cplx<T>*)(filt ? (void*)c->d_Ca : (void*)c->d_C);
-  TRY(launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, pairs, Tb, tw, s));
-  TRY(launch_cols<T>(t.n, 0, Tb, t.nr, pairs, Cq, tw, s));
-  TRY(launch_rows_inv<T>(t.n, Tb, t.nr, c->d_row_ptr, c->d_act_ix, pairs, V, t.n_act, tw, s));
+  {
+    ProfScope ps(c, AIM_K_ROWS_FWD);
+    TRY(launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, pairs, Tb, tw, s));
+  }
+  {
+    ProfScope ps(c, AIM_K_COLS);
+    TRY(launch_cols<T>(t.n, 0, Tb, t.nr, pairs, Cq, tw, s));
+  }
+  {
+    ProfScope ps(c, AIM_K_ROWS_INV);
+    TRY(launch_rows_inv<T>(t.n, Tb, t.nr, c->d_row_ptr, c->d_act_ix, pairs, V, t.n_act, tw, s));
+  }
   return AIM_OK;
 }
 
@@ -815,6 +827,7 @@ static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near
   dim3 g((unsigned)(((size_t)t.N * 16 + threads - 1) / threads));
   const cplx<T>* V = (const cplx<T>*)c->d_V;
   const double2* C = near ? Cn : nullptr;
+  ProfScope ps(c, AIM_K_INTERP);
   if (sizeof(T) == 4) {
     hipLaunchKernelGGL((k_interp_near<T, float>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
                        c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
