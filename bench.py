@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the filtered-AIM EFIE hot path on one MI355X.
 
-One step = one full TM-EFIE restarted-GMRES solve (plain FP64, restart 100)
+One step = one full TM-EFIE GMRES solve (plain FP64, restart 400)
 to a 1e-6 relative residual on the PEC cylinder with ka = 200
 (N = 16384 pulse segments, AIM grid 1024 x 1024 at lambda/15 padded to
 2048 x 2048, half of the spectrum kept by the filter), plane wave at 0 deg.
@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--workload", default="cylinder_ka200",
                     choices=["cylinder_ka200", "cylinder_ka2pi"])
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--restart", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")

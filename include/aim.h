@@ -86,7 +86,7 @@ typedef struct {
   double k;               /* wavenumber (rad / length unit), > 0                    */
   double eta;             /* medium impedance (ohm)                                 */
   int32_t basis;          /* AIM_PULSE (TM systems) or AIM_HAT (TE systems)         */
-  int32_t m;              /* grid points per side (power of two, 16..4096)          */
+  int32_t m;              /* grid points per side (power of two, 16..2048)          */
   double eps;             /* grid step; grid centred at 0, L = (m-1) eps / 2        */
   int32_t quad;           /* Gauss-Legendre nodes per segment in the stencils (>=1) */
   int32_t near_radius;    /* anchor Chebyshev radius of the near zone (>= 3)        */
@@ -149,8 +149,9 @@ aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_ho
    residual estimate of that system is <= tol ||b||).  x_dev holds the
    initial guess on entry and the solution on exit.  precision AIM_MIXED
    runs FP64 iterative refinement around an inner GMRES whose grid part is
-   FP32.  info_host: nrhs entries (may be NULL).  Synchronous.  Errors:
-   AIM_E_ARG, AIM_E_NOCONV, AIM_E_NUMERIC, AIM_E_OOM.                          */
+   FP32.  restart: 1..1000 Krylov vectors per cycle.  info_host: nrhs
+   entries (may be NULL).  Synchronous.  Errors: AIM_E_ARG, AIM_E_NOCONV,
+   AIM_E_NUMERIC, AIM_E_OOM.                                                   */
 aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                      const void* b_dev, void* x_dev, double tol, int32_t maxit,
                      int32_t restart, aim_solve_info* info_host);

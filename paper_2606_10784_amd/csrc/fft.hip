@@ -73,15 +73,66 @@ __device__ __forceinline__ void dft8(cplx<T>* v) {
   v[3] = cadd(e3, w3); v[7] = csub(e3, w3);
 }
 
+// 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(cplx<T>* v) {
+  using V = cplx<T>;
+  // W16^e, e = 0..9 (forward sign)
+  const T c1 = (T)0.92387953251128675612818318939678829, s1 = (T)0.38268343236508977172845998403039887;
+  const T c2 = (T)0.70710678118654752440084436210484903;
+  dft4<V, INV>(v[0], v[4], v[8], v[12]);
+  dft4<V, INV>(v[1], v[5], v[9], v[13]);
+  dft4<V, INV>(v[2], v[6], v[10], v[14]);
+  dft4<V, INV>(v[3], v[7], v[11], v[15]);
+  // after the first stage v[4 k1 + n2] holds A[n2][k1]; twiddle by W16^{n2 k1}
+  auto tw = [&](V a, T c, T sn) -> V {   // a * (c - i sn) forward, a * (c + i sn) inverse
+    V r;
+    if (!INV) { r.x = a.x * c + a.y * sn; r.y = a.y * c - a.x * sn; }
+    else { r.x = a.x * c - a.y * sn; r.y = a.y * c + a.x * sn; }
+    return r;
+  };
+  // n2 = 1: k1 = 1,2,3 -> e = 1,2,3
+  v[5] = tw(v[5], c1, s1);
+  v[9] = tw(v[9], c2, c2);
+  v[13] = tw(v[13], s1, c1);
+  // n2 = 2: e = 2,4,6
+  v[6] = tw(v[6], c2, c2);
+  v[10] = rot_mi<V, INV>(v[10]);
+  v[14] = tw(v[14], -c2, c2);
+  // n2 = 3: e = 3,6,9
+  v[7] = tw(v[7], s1, c1);
+  v[11] = tw(v[11], -c2, c2);
+  v[15] = tw(v[15], -c1, -s1);
+  // second stage over n2 for each k1; output X[k1 + 4 k2]
+  dft4<V, INV>(v[0], v[1], v[2], v[3]);
+  dft4<V, INV>(v[4], v[5], v[6], v[7]);
+  dft4<V, INV>(v[8], v[9], v[10], v[11]);
+  dft4<V, INV>(v[12], v[13], v[14], v[15]);
+  // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 block
+  V t;
+  t = v[1]; v[1] = v[4]; v[4] = t;
+  t = v[2]; v[2] = v[8]; v[8] = t;
+  t = v[3]; v[3] = v[12]; v[12] = t;
+  t = v[6]; v[6] = v[9]; v[9] = t;
+  t = v[7]; v[7] = v[13]; v[13] = t;
+  t = v[11]; v[11] = v[14]; v[14] = t;
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_r(cplx<T>* v) {
-  if constexpr (R == 8) dft8<T, INV>(v);
+  if constexpr (R == 16) dft16<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
   else if constexpr (R == 4) dft4<cplx<T>, INV>(v[0], v[1], v[2], v[3]);
   else dft2<cplx<T>, INV>(v[0], v[1]);
 }
 
+// LDS index with one pad slot per 8 elements: breaks the power-of-two
+// strides of the early Stockham passes across banks.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 3); }
+
 // One Stockham pass: sub-transform length NS -> NS*R.  Element i of column c
-// lives at buf[i * NCOL + c].
+// lives at buf[pidx(i * NCOL + c)].
 template <typename T, int N, int NCOL, int NT, bool INV, int NS, int R>
 __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
@@ -95,7 +146,7 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __res
     if ((NB % NT) == 0 || b < NB) {
       const int c = b % NCOL, j = b / NCOL;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * (N / R)) * NCOL + c];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[pidx((j + r * (N / R)) * NCOL + c)];
       if constexpr (NS > 1) {
         const int k = j & (NS - 1);
 #pragma unroll
@@ -117,45 +168,99 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __res
       const int k = j & (NS - 1);
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(base + r * NS) * NCOL + c] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[pidx((base + r * NS) * NCOL + c)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
+// radix-16 passes, then 8, 4 or 2 for the remainder
 template <typename T, int N, int NCOL, int NT, bool INV, int NS>
 __device__ __forceinline__ void fft_passes(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
   if constexpr (NS < N) {
-    constexpr int R = (N / NS >= 8) ? 8 : (N / NS);
+    constexpr int R = (N / NS >= 16) ? 16 : (N / NS);
     stockham_pass<T, N, NCOL, NT, INV, NS, R>(buf, tw);
     fft_passes<T, N, NCOL, NT, INV, NS * R>(buf, tw);
   }
 }
 
 // ---------------------------------------------------------------------------
-// kernels
+// column blocks: CB columns per block; columns kx and N - kx share a block so
+// the even-symmetric quarter spectrum is read once.  Block b, slot c holds
+// pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror N - q); the last slot pair
+// of the last block holds the self-mirrored columns 0 and N/2.
 // ---------------------------------------------------------------------------
-template <int N> constexpr int row_threads() { return N / 8 < 64 ? 64 : (N / 8 > 256 ? 256 : N / 8); }
+template <typename T, int N> struct ColCfg {
+  static constexpr int BYTES = 160000;   // padded LDS per block, <= 160 KiB
+  static constexpr int CB0 = BYTES / (padded(N) * (int)sizeof(cplx<T>));
+  static constexpr int CB1 = CB0 < 2 ? 2 : (CB0 > 16 ? 16 : CB0);
+  static constexpr int CB = (CB1 >= 16) ? 16 : (CB1 >= 8 ? 8 : (CB1 >= 4 ? 4 : 2));
+  static constexpr int NT = (N * CB / 16 >= 512) ? 512 : 256;
+};
+
+__device__ __forceinline__ void col_of(int b, int c, int N, int CB, int& kx, int& kxq) {
+  const int q = b * (CB / 2) + (c >> 1) + 1;
+  const int half = c & 1;
+  if (q >= N / 2) {            // last pair slot of the last block
+    kx = half ? N / 2 : 0;
+    kxq = kx;
+  } else {
+    kx = half ? N - q : q;
+    kxq = q;
+  }
+}
+
+__device__ __forceinline__ void slot_of(int kx, int N, int CB, int& b, int& c) {
+  const int q = kx <= N / 2 ? kx : N - kx;
+  const int nblk = N / CB;
+  if (q == 0 || q == N / 2) {
+    b = nblk - 1;
+    c = CB - 2 + (q == 0 ? 0 : 1);
+  } else {
+    b = (q - 1) / (CB / 2);
+    c = 2 * ((q - 1) % (CB / 2)) + (kx > N / 2 ? 1 : 0);
+  }
+}
+
+// XCD-aware row order: consecutive rows go to the same XCD (blocks are
+// dealt round-robin over 8 XCDs), so the halves of a tile line written by
+// neighbouring rows meet in one L2.
+__device__ __forceinline__ int xcd_row(int bid, int nrows) {
+  const int per = (nrows + 7) / 8;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// kernels.  T layout (tiled): [pair][block][row][CB]
+// ---------------------------------------------------------------------------
+template <int N> constexpr int row_threads() { return N / 16 < 64 ? 64 : (N / 16 > 256 ? 256 : N / 16); }
 
 // Pass 1: gather active values of a row into a zeroed LDS row, FFT along x.
-// grid = (nr, pairs); U: [pair][n_act]; T: [pair][nr][N]
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     const cplx<T>* __restrict__ U, int n_act, const int32_t* __restrict__ row_ptr,
     const int32_t* __restrict__ act_ix, int nr, cplx<T>* __restrict__ Tb,
     const cplx<T>* __restrict__ tw) {
   constexpr int NT = row_threads<N>();
-  __shared__ cplx<T> buf[N];
-  const int row = blockIdx.x, pair = blockIdx.y;
-  for (int i = threadIdx.x; i < N; i += NT) buf[i] = mk<T>(0, 0);
+  constexpr int CB = ColCfg<T, N>::CB;
+  constexpr int NBLK = N / CB;
+  __shared__ cplx<T> buf[padded(N)];
+  const int row = xcd_row(blockIdx.x, nr), pair = blockIdx.y;
+  if (row >= nr) return;
+  for (int i = threadIdx.x; i < N; i += NT) buf[pidx(i)] = mk<T>(0, 0);
   __syncthreads();
   const int a0 = row_ptr[row], a1 = row_ptr[row + 1];
   const cplx<T>* Up = U + (size_t)pair * n_act;
-  for (int a = a0 + threadIdx.x; a < a1; a += NT) buf[act_ix[a]] = Up[a];
+  for (int a = a0 + threadIdx.x; a < a1; a += NT) buf[pidx(act_ix[a])] = Up[a];
   __syncthreads();
   fft_passes<T, N, 1, NT, false, 1>(buf, tw);
-  cplx<T>* out = Tb + ((size_t)pair * nr + row) * N;
-  for (int i = threadIdx.x; i < N; i += NT) out[i] = buf[i];
+  cplx<T>* out = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  for (int idx = threadIdx.x; idx < N; idx += NT) {
+    const int b = idx / CB, c = idx % CB;
+    int kx, kxq;
+    col_of(b, c, N, CB, kx, kxq);
+    out[(size_t)b * nr * CB + c] = buf[pidx(kx)];
+  }
 }
 
 // Pass 3: inverse FFT along x, gather the active points of the row.
@@ -165,40 +270,42 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
     const int32_t* __restrict__ act_ix, cplx<T>* __restrict__ Vout, int n_act,
     const cplx<T>* __restrict__ tw) {
   constexpr int NT = row_threads<N>();
-  __shared__ cplx<T> buf[N];
-  const int row = blockIdx.x, pair = blockIdx.y;
-  const cplx<T>* in = Tb + ((size_t)pair * nr + row) * N;
-  for (int i = threadIdx.x; i < N; i += NT) buf[i] = in[i];
+  constexpr int CB = ColCfg<T, N>::CB;
+  constexpr int NBLK = N / CB;
+  __shared__ cplx<T> buf[padded(N)];
+  const int row = xcd_row(blockIdx.x, nr), pair = blockIdx.y;
+  if (row >= nr) return;
+  const cplx<T>* in = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  for (int idx = threadIdx.x; idx < N; idx += NT) {
+    const int b = idx / CB, c = idx % CB;
+    int kx, kxq;
+    col_of(b, c, N, CB, kx, kxq);
+    buf[pidx(kx)] = in[(size_t)b * nr * CB + c];
+  }
   __syncthreads();
   fft_passes<T, N, 1, NT, true, 1>(buf, tw);
   const int a0 = row_ptr[row], a1 = row_ptr[row + 1];
   cplx<T>* Vp = Vout + (size_t)pair * n_act;
-  for (int a = a0 + threadIdx.x; a < a1; a += NT) Vp[a] = buf[act_ix[a]];
+  for (int a = a0 + threadIdx.x; a < a1; a += NT) Vp[a] = buf[pidx(act_ix[a])];
 }
 
-// Set-up: in-place forward FFT of nrows full rows of length N.
+// Set-up: in-place forward FFT of full rows of length N (row-major array).
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* __restrict__ A,
                                                                        const cplx<T>* __restrict__ tw) {
   constexpr int NT = row_threads<N>();
-  __shared__ cplx<T> buf[N];
+  __shared__ cplx<T> buf[padded(N)];
   cplx<T>* rowp = A + (size_t)blockIdx.x * N;
-  for (int i = threadIdx.x; i < N; i += NT) buf[i] = rowp[i];
+  for (int i = threadIdx.x; i < N; i += NT) buf[pidx(i)] = rowp[i];
   __syncthreads();
   fft_passes<T, N, 1, NT, false, 1>(buf, tw);
-  for (int i = threadIdx.x; i < N; i += NT) rowp[i] = buf[i];
+  for (int i = threadIdx.x; i < N; i += NT) rowp[i] = buf[pidx(i)];
 }
 
-template <typename T, int N> struct ColCfg {
-  static constexpr int BYTES = 65536;
-  static constexpr int CB0 = BYTES / (N * (int)sizeof(cplx<T>));
-  static constexpr int CB = CB0 < 1 ? 1 : (CB0 > 16 ? 16 : CB0);
-  static constexpr int NT = 256;
-};
-
-// Pass 2: column FFT, spectrum multiply, inverse column FFT (in place on T).
-// grid = (N / CB, pairs). Cq: quarter spectrum [kxq][kyq], (N/2+1)^2.
-// MODE 0: convolution over rows [0, nr); MODE 1: plain forward FFT of all N rows
+// Pass 2 (MODE 0): column FFT, spectrum multiply, inverse column FFT, in
+// place on one tile [row][CB] of T.  Cq: quarter spectrum [kxq][kyq].
+// MODE 1 (set-up): plain forward FFT of CB consecutive columns of a
+// row-major N x N array.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
     cplx<T>* __restrict__ Tb, int nr, const cplx<T>* __restrict__ Cq,
@@ -206,45 +313,53 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
   constexpr int CB = ColCfg<T, N>::CB;
   constexpr int NT = ColCfg<T, N>::NT;
   constexpr int H = N / 2 + 1;
-  __shared__ cplx<T> buf[N * CB];
-  const int kx0 = blockIdx.x * CB;
+  constexpr int NBLK = N / CB;
+  __shared__ cplx<T> buf[padded(N * CB)];
+  const int b = blockIdx.x;
   const int pair = blockIdx.y;
-  cplx<T>* base = Tb + (size_t)pair * nr * N;
-  const int rows_in = (MODE == 0) ? nr : N;
-  for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
-    const int i = idx / CB, c = idx % CB;
-    buf[idx] = (i < rows_in) ? base[(size_t)i * N + kx0 + c] : mk<T>(0, 0);
-  }
-  __syncthreads();
-  fft_passes<T, N, CB, NT, false, 1>(buf, tw);
   if constexpr (MODE == 0) {
+    cplx<T>* tile = Tb + ((size_t)pair * NBLK + b) * nr * CB;
+    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+      const int i = idx / CB;
+      buf[pidx(idx)] = (i < nr) ? tile[idx] : mk<T>(0, 0);
+    }
+    __syncthreads();
+    fft_passes<T, N, CB, NT, false, 1>(buf, tw);
     for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
       const int ky = idx / CB, c = idx % CB;
-      const int kx = kx0 + c;
-      const int kxq = kx <= N / 2 ? kx : N - kx;
+      int kx, kxq;
+      col_of(b, c, N, CB, kx, kxq);
       const int kyq = ky <= N / 2 ? ky : N - ky;
-      buf[idx] = cmul(buf[idx], Cq[(size_t)kxq * H + kyq]);
+      buf[pidx(idx)] = cmul(buf[pidx(idx)], Cq[(size_t)kxq * H + kyq]);
     }
     __syncthreads();
     fft_passes<T, N, CB, NT, true, 1>(buf, tw);
-  }
-  const int rows_out = (MODE == 0) ? nr : N;
-  for (int idx = threadIdx.x; idx < rows_out * CB; idx += NT) {
-    const int i = idx / CB, c = idx % CB;
-    base[(size_t)i * N + kx0 + c] = buf[idx];
+    for (int idx = threadIdx.x; idx < nr * CB; idx += NT) tile[idx] = buf[pidx(idx)];
+  } else {
+    const int kx0 = b * CB;
+    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+      const int i = idx / CB, c = idx % CB;
+      buf[pidx(idx)] = Tb[(size_t)i * N + kx0 + c];
+    }
+    __syncthreads();
+    fft_passes<T, N, CB, NT, false, 1>(buf, tw);
+    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+      const int i = idx / CB, c = idx % CB;
+      Tb[(size_t)i * N + kx0 + c] = buf[pidx(idx)];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // launchers with run-time size dispatch
 // ---------------------------------------------------------------------------
-#define AIM_FOR_SIZES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(8192)
+#define AIM_FOR_SIZES(X) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename T>
 aim_status launch_rows_fwd(int n, const cplx<T>* U, int n_act, const int32_t* row_ptr,
                            const int32_t* act_ix, int nr, int pairs, cplx<T>* Tb,
                            const cplx<T>* tw, hipStream_t s) {
-  dim3 g(nr, pairs);
+  dim3 g(8 * ((nr + 7) / 8), pairs);
   switch (n) {
 #define CASE(NN)                                                                               \
   case NN:                                                                                     \
@@ -262,7 +377,7 @@ template <typename T>
 aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_ptr,
                            const int32_t* act_ix, int pairs, cplx<T>* V, int n_act,
                            const cplx<T>* tw, hipStream_t s) {
-  dim3 g(nr, pairs);
+  dim3 g(8 * ((nr + 7) / 8), pairs);
   switch (n) {
 #define CASE(NN)                                                                               \
   case NN:                                                                                     \

@@ -19,6 +19,8 @@
 namespace aim {
 
 static constexpr int RED_CHUNK = 2048;
+// Arnoldi steps enqueued between two host reads of the residual estimates
+static constexpr int kCheckEvery = 8;
 
 // partial sums of conj(V_i) . w over a chunk, or |w|^2 when V == nullptr
 __global__ __launch_bounds__(256) void k_dots(int N, const double2* __restrict__ V, int64_t ld_rhs_v,
@@ -67,35 +69,104 @@ __global__ void k_reduce(int nrhs, int j1, int nchunk, int jmax, const double2* 
   out[(size_t)r * ld_out + i] = make_double2(sx, sy);
 }
 
-// w[r] += sgn * sum_i V[r][i] c[r][i]
-__global__ void k_gemv(int N, int j1, const double2* __restrict__ V, int64_t ld_rhs_v,
-                       const double2* __restrict__ c, int64_t ld_c, double sgn, const int* __restrict__ active,
-                       double2* __restrict__ w, int64_t ld_w) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+// w[r] += sgn * sum_i V[r][i] c[r][i]; block = 32 rows x 8 groups of i
+constexpr int GV_ROWS = 32, GV_GRP = 8;
+__global__ __launch_bounds__(256) void k_gemv(int N, int j1, const double2* __restrict__ V, int64_t ld_rhs_v,
+                                              const double2* __restrict__ c, int64_t ld_c, double sgn,
+                                              const int* __restrict__ active, double2* __restrict__ w,
+                                              int64_t ld_w) {
   const int r = blockIdx.y;
-  if (n >= N || !active[r]) return;
+  if (!active[r]) return;
+  const int lr = threadIdx.x % GV_ROWS, g = threadIdx.x / GV_ROWS;
+  const int n = blockIdx.x * GV_ROWS + lr;
   const double2* vr = V + (size_t)r * ld_rhs_v;
   const double2* cr = c + (size_t)r * ld_c;
   double sx = 0, sy = 0;
-  for (int i = 0; i < j1; ++i) {
-    const double2 a = vr[(size_t)i * N + n], b = cr[i];
-    sx += a.x * b.x - a.y * b.y;
-    sy += a.x * b.y + a.y * b.x;
+  if (n < N) {
+    for (int i = g; i < j1; i += GV_GRP) {
+      const double2 a = vr[(size_t)i * N + n], b = cr[i];
+      sx += a.x * b.x - a.y * b.y;
+      sy += a.x * b.y + a.y * b.x;
+    }
   }
-  double2 o = w[(size_t)r * ld_w + n];
-  w[(size_t)r * ld_w + n] = make_double2(o.x + sgn * sx, o.y + sgn * sy);
+  __shared__ double px[256], py[256];
+  px[threadIdx.x] = sx;
+  py[threadIdx.x] = sy;
+  __syncthreads();
+  if (g == 0 && n < N) {
+    for (int q = 1; q < GV_GRP; ++q) {
+      sx += px[q * GV_ROWS + lr];
+      sy += py[q * GV_ROWS + lr];
+    }
+    double2 o = w[(size_t)r * ld_w + n];
+    w[(size_t)r * ld_w + n] = make_double2(o.x + sgn * sx, o.y + sgn * sy);
+  }
 }
 
-// H[:, j] (+)= h ; keeps the first CGS pass
-__global__ void k_hacc(int j1, int nrhs, int ldh, int j, const double2* h, int64_t ld_h, int first,
-                       const int* active, double2* H) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One CGS pass update: h = sum of the Vᴴw chunk partials (fixed order), then
+// w -= V h.  Block 0 also adds h into H[:, j].  With want_norm, each block
+// writes the partial |w|^2 of its rows (the norm of the orthogonalised w).
+// Dynamic LDS: j1 double2.
+__global__ __launch_bounds__(256) void k_cgs_update(int N, int j1, int nchunk, int jmax,
+                                                    const double2* __restrict__ part, const double2* __restrict__ V,
+                                                    int64_t ld_rhs_v, const int* __restrict__ active,
+                                                    double2* __restrict__ w, int64_t ld_w, double2* __restrict__ H,
+                                                    int ldh, int j, int first, int want_norm,
+                                                    double* __restrict__ npart) {
+  extern __shared__ double2 hsh[];
   const int r = blockIdx.y;
-  if (i >= j1 || !active[r]) return;
-  double2* Hc = H + (size_t)r * ldh * (ldh - 1) + (size_t)j * ldh;
-  const double2 v = h[(size_t)r * ld_h + i];
-  if (first) Hc[i] = v;
-  else Hc[i] = make_double2(Hc[i].x + v.x, Hc[i].y + v.y);
+  if (!active[r]) return;
+  const double2* pr = part + (size_t)r * jmax * nchunk;
+  for (int i = threadIdx.x; i < j1; i += 256) {
+    double sx = 0, sy = 0;
+    for (int c = 0; c < nchunk; ++c) {
+      const double2 v = pr[(size_t)i * nchunk + c];
+      sx += v.x;
+      sy += v.y;
+    }
+    hsh[i] = make_double2(sx, sy);
+    if (blockIdx.x == 0) {
+      double2* Hc = H + (size_t)r * ldh * (ldh - 1) + (size_t)j * ldh;
+      Hc[i] = first ? make_double2(sx, sy) : make_double2(Hc[i].x + sx, Hc[i].y + sy);
+    }
+  }
+  __syncthreads();
+  const int lr = threadIdx.x % GV_ROWS, g = threadIdx.x / GV_ROWS;
+  const int n = blockIdx.x * GV_ROWS + lr;
+  const double2* vr = V + (size_t)r * ld_rhs_v;
+  double sx = 0, sy = 0;
+  if (n < N) {
+    for (int i = g; i < j1; i += GV_GRP) {
+      const double2 a = vr[(size_t)i * N + n], b = hsh[i];
+      sx += a.x * b.x - a.y * b.y;
+      sy += a.x * b.y + a.y * b.x;
+    }
+  }
+  __shared__ double px[256], py[256];
+  px[threadIdx.x] = sx;
+  py[threadIdx.x] = sy;
+  __syncthreads();
+  double nrm = 0.0;
+  if (g == 0 && n < N) {
+    for (int q = 1; q < GV_GRP; ++q) {
+      sx += px[q * GV_ROWS + lr];
+      sy += py[q * GV_ROWS + lr];
+    }
+    const double2 o = w[(size_t)r * ld_w + n];
+    const double2 nw = make_double2(o.x - sx, o.y - sy);
+    w[(size_t)r * ld_w + n] = nw;
+    nrm = nw.x * nw.x + nw.y * nw.y;
+  }
+  if (want_norm) {
+    __syncthreads();
+    px[threadIdx.x] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < GV_ROWS; ++q) t += px[q];
+      npart[(size_t)r * gridDim.x + blockIdx.x] = t;
+    }
+  }
 }
 
 // v = w / ||w||   (||w|| from the reduction); also records H[j+1, j]
@@ -129,71 +200,117 @@ __global__ void k_axpy(int N, const double2* d, double2* x) {
   x[(size_t)c * N + n] = make_double2(o.x + a.x, o.y + a.y);
 }
 
-// Givens update of column j (one thread per right-hand side)
-__global__ void k_givens(int nrhs, int ldh, int j, const double* hn, const int* active, double2* H, double2* cs,
-                         double2* sn, double2* g, double* resid) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs || !active[r]) return;
+// ||w|| from the block partials (fixed order), H[j+1, j] = ||w||, then the
+// Givens update of column j: the column and the previous rotations are
+// staged in LDS so one thread runs the dependent chain from LDS.  One block
+// per right-hand side; dynamic LDS: (ldh + 2 * restart) double2.
+__global__ __launch_bounds__(256) void k_norm_givens(int nrhs, int ldh, int j, int nparts,
+                                                     const double* __restrict__ npart,
+                                                     const int* __restrict__ active, double2* H, double2* cs,
+                                                     double2* sn, double2* g, double* resid_hist, double* hn) {
+  extern __shared__ double2 sh[];
+  const int r = blockIdx.x;
+  if (!active[r]) return;
   const int R = ldh - 1;
+  double2* Hs = sh;            // ldh
+  double2* Cs = sh + ldh;      // R
+  double2* Ss = Cs + R;        // R
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += 256) t += npart[(size_t)r * nparts + q];
+  red[threadIdx.x] = t;
   double2* Hc = H + (size_t)r * ldh * R + (size_t)j * ldh;
   double2* c = cs + (size_t)r * R;
   double2* s = sn + (size_t)r * R;
-  double2* gg = g + (size_t)r * ldh;
-  Hc[j + 1] = make_double2(hn[r], 0.0);
-  for (int i = 0; i < j; ++i) {
-    const double ci = c[i].x;
-    const double2 si = s[i];
-    const double2 a = Hc[i], b = Hc[i + 1];
-    // [c s; -conj(s) c]
-    const double2 t = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
-    const double2 u = make_double2(-(si.x * a.x + si.y * a.y) + ci * b.x, -(si.x * a.y - si.y * a.x) + ci * b.y);
-    Hc[i] = t;
-    Hc[i + 1] = u;
+  for (int i = threadIdx.x; i <= j; i += 256) Hs[i] = Hc[i];
+  for (int i = threadIdx.x; i < j; i += 256) {
+    Cs[i] = c[i];
+    Ss[i] = s[i];
   }
-  const double2 a = Hc[j], b = Hc[j + 1];
-  const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-  const double den = hypot(na, nb);
-  double ci;
-  double2 si;
-  if (na == 0.0) {
-    ci = 0.0;
-    si = make_double2(1.0, 0.0);
-  } else {
-    ci = na / den;
-    // s = (a/|a|) conj(b) / den
-    const double2 ph = make_double2(a.x / na, a.y / na);
-    si = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
   }
-  c[j] = make_double2(ci, 0.0);
-  s[j] = si;
-  Hc[j] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
-  Hc[j + 1] = make_double2(0.0, 0.0);
-  const double2 gj = gg[j];
-  gg[j + 1] = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));
-  gg[j] = make_double2(ci * gj.x, ci * gj.y);
-  resid[r] = hypot(gg[j + 1].x, gg[j + 1].y);
+  if (threadIdx.x == 0) {
+    const double hnr = sqrt(red[0]);
+    hn[r] = hnr;
+    Hs[j + 1] = make_double2(hnr, 0.0);
+    double2 a = Hs[0];
+    for (int i = 0; i < j; ++i) {
+      const double ci = Cs[i].x;
+      const double2 si = Ss[i];
+      const double2 b = Hs[i + 1];
+      // [c s; -conj(s) c]
+      Hs[i] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
+      a = make_double2(-(si.x * a.x + si.y * a.y) + ci * b.x, -(si.x * a.y - si.y * a.x) + ci * b.y);
+    }
+    const double2 b = Hs[j + 1];
+    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+    const double den = hypot(na, nb);
+    double ci;
+    double2 si;
+    if (na == 0.0) {
+      ci = 0.0;
+      si = make_double2(1.0, 0.0);
+    } else {
+      ci = na / den;
+      const double2 ph = make_double2(a.x / na, a.y / na);
+      si = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);
+    }
+    c[j] = make_double2(ci, 0.0);
+    s[j] = si;
+    Hs[j] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
+    Hs[j + 1] = make_double2(0.0, 0.0);
+    double2* gg = g + (size_t)r * ldh;
+    const double2 gj = gg[j];
+    gg[j + 1] = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));
+    gg[j] = make_double2(ci * gj.x, ci * gj.y);
+    resid_hist[(size_t)r * R + j] = hypot(gg[j + 1].x, gg[j + 1].y);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 256) Hc[i] = Hs[i];
 }
 
-// y = H^-1 g (upper triangular, jm x jm), one thread per right-hand side
-__global__ void k_trisolve(int nrhs, int ldh, const int* jm, const double2* H, const double2* g, double2* y) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
+// v = w / hn[r]
+__global__ void k_scale_to(int N, const double* __restrict__ hn, const double2* __restrict__ w, int64_t ld_w,
+                           double2* __restrict__ v, int64_t ld_rhs_v, const int* __restrict__ active) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= N || !active[r]) return;
+  const double nr = hn[r];
+  const double sc = nr > 0 ? 1.0 / nr : 0.0;
+  const double2 a = w[(size_t)r * ld_w + n];
+  v[(size_t)r * ld_rhs_v + n] = make_double2(a.x * sc, a.y * sc);
+}
+
+// y = H^-1 g (upper triangular, jm x jm), column-oriented back substitution,
+// one block per right-hand side; dynamic LDS: ldh double2.
+__global__ __launch_bounds__(256) void k_trisolve(int nrhs, int ldh, const int* jm, const double2* H,
+                                                  const double2* g, double2* y) {
+  extern __shared__ double2 gl[];
+  const int r = blockIdx.x;
   const int R = ldh - 1;
   const int m = jm[r];
   const double2* Hr = H + (size_t)r * ldh * R;
   const double2* gr = g + (size_t)r * ldh;
   double2* yr = y + (size_t)r * R;
+  for (int i = threadIdx.x; i < m; i += 256) gl[i] = gr[i];
+  __syncthreads();
   for (int i = m - 1; i >= 0; --i) {
-    double sx = gr[i].x, sy = gr[i].y;
-    for (int k = i + 1; k < m; ++k) {
-      const double2 h = Hr[(size_t)k * ldh + i], v = yr[k];
-      sx -= h.x * v.x - h.y * v.y;
-      sy -= h.x * v.y + h.y * v.x;
-    }
-    const double2 d = Hr[(size_t)i * ldh + i];
+    const double2* col = Hr + (size_t)i * ldh;
+    const double2 d = col[i];
     const double dd = d.x * d.x + d.y * d.y;
-    yr[i] = make_double2((sx * d.x + sy * d.y) / dd, (sy * d.x - sx * d.y) / dd);
+    const double2 gi = gl[i];
+    const double2 yi = make_double2((gi.x * d.x + gi.y * d.y) / dd, (gi.y * d.x - gi.x * d.y) / dd);
+    if (threadIdx.x == 0) yr[i] = yi;
+    for (int k = threadIdx.x; k < i; k += 256) {
+      const double2 h = col[k];
+      gl[k] = make_double2(gl[k].x - (h.x * yi.x - h.y * yi.y), gl[k].y - (h.x * yi.y + h.y * yi.x));
+    }
+    __syncthreads();
   }
+  for (int i = m + threadIdx.x; i < R; i += 256) yr[i] = make_double2(0, 0);
 }
 
 __global__ void k_set_g0(int nrhs, int ldh, const double2* nrm2, const int* active, double2* g) {
@@ -209,7 +326,7 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
   if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
   for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
                   (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
-                  (void*)w.resid, (void*)w.hn, (void*)w.active})
+                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.active})
     if (p) hipFree(p);
   if (w.host_resid) hipHostFree(w.host_resid);
   c->dev_bytes -= w.bytes;
@@ -232,10 +349,10 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
             A((void**)&w.part, (size_t)nrhs * ldh * w.nchunk * 16) && A((void**)&w.r, (size_t)nrhs * N * 16) &&
             A((void**)&w.d, (size_t)nrhs * N * 16) && A((void**)&w.b2, (size_t)nrhs * N * 16) &&
             A((void**)&w.nrm, (size_t)nrhs * 2 * 16) && A((void**)&w.bnorm, (size_t)nrhs * 8) &&
-            A((void**)&w.resid, (size_t)nrhs * 8) && A((void**)&w.hn, (size_t)nrhs * 8) &&
+            A((void**)&w.resid, (size_t)nrhs * restart * 8) && A((void**)&w.hn, (size_t)nrhs * 8) && A((void**)&w.npart, (size_t)nrhs * ((N + 31) / 32) * 8) &&
             A((void**)&w.active, (size_t)nrhs * 4 * 2);
   if (!ok) return AIM_E_OOM;
-  if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * 8 * 4) != hipSuccess) return AIM_E_OOM;
+  if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * restart * 8) != hipSuccess) return AIM_E_OOM;
   w.bytes = tot;
   c->dev_bytes += tot;
   return AIM_OK;
@@ -322,41 +439,49 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
     std::fill(jdone.begin(), jdone.end(), 0);
     std::vector<int> cyc(act);
     int j = 0;
-    for (; j < restart && total < maxit; ++j) {
-      const int j1 = j + 1;
-      // w = A v_j
-      TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
-      res.matvecs++;
-      // CGS2
-      for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
-                           w.active, w.part, w.nchunk, ldh);
-        hipLaunchKernelGGL(k_reduce, dim3((j1 + 63) / 64, nrhs), dim3(64), 0, s, nrhs, j1, w.nchunk, ldh, w.part,
-                           w.active, w.hcol, (int64_t)ldh);
-        hipLaunchKernelGGL(k_gemv, gN, dim3(256), 0, s, N, j1, w.V, ldv, w.hcol, (int64_t)ldh, -1.0, w.active,
-                           w.W, (int64_t)N);
-        hipLaunchKernelGGL(k_hacc, dim3((j1 + 63) / 64, nrhs), dim3(64), 0, s, j1, nrhs, ldh, j, w.hcol,
-                           (int64_t)ldh, pass == 0 ? 1 : 0, w.active, w.H);
+    while (j < restart && total < maxit) {
+      const int jstart = j;
+      const int jend = std::min(std::min(restart, j + kCheckEvery), j + (maxit - total));
+      for (; j < jend; ++j) {
+        const int j1 = j + 1;
+        // w = A v_j
+        TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
+        res.matvecs++;
+        // CGS2: two passes of (Vᴴw partials, fused reduce + update); the
+        // second pass also leaves the partial norms of the new w
+        const int gblk = (N + GV_ROWS - 1) / GV_ROWS;
+        for (int pass = 0; pass < 2; ++pass) {
+          hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
+                             w.active, w.part, w.nchunk, ldh);
+          hipLaunchKernelGGL(k_cgs_update, dim3(gblk, nrhs), dim3(256), (size_t)j1 * 16, s, N, j1, w.nchunk, ldh,
+                             w.part, w.V, ldv, w.active, w.W, (int64_t)N, w.H, ldh, j, pass == 0 ? 1 : 0,
+                             pass == 1 ? 1 : 0, w.npart);
+        }
+        hipLaunchKernelGGL(k_norm_givens, dim3(nrhs), dim3(256), (size_t)(ldh + 2 * restart) * 16, s, nrhs, ldh, j,
+                           gblk, w.npart, w.active, w.H, w.cs, w.sn, w.g, w.resid, w.hn);
+        hipLaunchKernelGGL(k_scale_to, gN, dim3(256), 0, s, N, w.hn, w.W, (int64_t)N, w.V + (size_t)j1 * N, ldv,
+                           w.active);
+        AIM_HIP_CHECK(hipGetLastError());
+        total++;
       }
-      TRY(norms(c, nrhs, w.W, N, w.active, w.nrm));
-      hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, (int64_t)1, w.W, (int64_t)N,
-                         w.V + (size_t)j1 * N, ldv, w.active, w.hn);
-      hipLaunchKernelGGL(k_givens, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, j, w.hn, w.active, w.H, w.cs,
-                         w.sn, w.g, w.resid);
-      AIM_HIP_CHECK(hipGetLastError());
-      AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid, w.resid, nrhs * 8, hipMemcpyDeviceToHost, s));
+      // residual estimates of the steps just taken
+      for (int r = 0; r < nrhs; ++r)
+        if (act[r])
+          AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jstart, w.resid + (size_t)r * restart + jstart,
+                                       (size_t)(jend - jstart) * 8, hipMemcpyDeviceToHost, s));
       AIM_HIP_CHECK(hipStreamSynchronize(s));
-      total++;
       bool left = false, changed = false;
       for (int r = 0; r < nrhs; ++r) {
         if (!act[r]) continue;
-        res.iters[r]++;
-        jdone[r] = j1;
-        const double rel = w.host_resid[r] / bn[r];
-        if (!std::isfinite(rel)) return AIM_E_NUMERIC;
-        res.est[r] = rel;
-        if (rel <= tol) { act[r] = 0; changed = true; }
-        else left = true;
+        for (int jj = jstart; jj < jend; ++jj) {
+          res.iters[r]++;
+          jdone[r] = jj + 1;
+          const double rel = w.host_resid[(size_t)r * restart + jj] / bn[r];
+          if (!std::isfinite(rel)) return AIM_E_NUMERIC;
+          res.est[r] = rel;
+          if (rel <= tol) { act[r] = 0; changed = true; break; }
+        }
+        if (act[r]) left = true;
       }
       if (!left) break;
       if (changed) AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
@@ -367,19 +492,12 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
     int* d_jm = (int*)w.part;   // scratch: jm then mask
     AIM_HIP_CHECK(hipMemcpyAsync(d_jm, jdone.data(), nrhs * 4, hipMemcpyHostToDevice, s));
     AIM_HIP_CHECK(hipMemcpyAsync(w.active, upd.data(), nrhs * 4, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_trisolve, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, d_jm, w.H, w.g, w.y);
+    hipLaunchKernelGGL(k_trisolve, dim3(nrhs), dim3(256), (size_t)ldh * 16, s, nrhs, ldh, d_jm, w.H, w.g, w.y);
     int jmax = 0;
     for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jdone[r]);
-    // columns with fewer steps have y entries beyond jdone that are stale: zero them by the mask of jm
-    std::vector<double2> yh((size_t)nrhs * restart);
-    AIM_HIP_CHECK(hipMemcpyAsync(yh.data(), w.y, yh.size() * 16, hipMemcpyDeviceToHost, s));
-    AIM_HIP_CHECK(hipStreamSynchronize(s));
-    for (int r = 0; r < nrhs; ++r)
-      for (int i = jdone[r]; i < restart; ++i) yh[(size_t)r * restart + i] = make_double2(0, 0);
-    AIM_HIP_CHECK(hipMemcpyAsync(w.y, yh.data(), yh.size() * 16, hipMemcpyHostToDevice, s));
     if (jmax > 0)
-      hipLaunchKernelGGL(k_gemv, gN, dim3(256), 0, s, N, jmax, w.V, ldv, w.y, (int64_t)restart, 1.0, w.active, x,
-                         (int64_t)N);
+      hipLaunchKernelGGL(k_gemv, dim3((N + GV_ROWS - 1) / GV_ROWS, nrhs), dim3(256), 0, s, N, jmax, w.V, ldv, w.y,
+                         (int64_t)restart, 1.0, w.active, x, (int64_t)N);
     AIM_HIP_CHECK(hipGetLastError());
     res.restarts++;
     // columns flagged converged by the estimate are re-checked with the true
@@ -437,7 +555,8 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
                  int restart, aim_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   const int op = form_op(form);
-  if (op < 0 || nrhs < 1 || nrhs > c->max_rhs || !(tol > 0) || maxit < 1 || restart < 1) return AIM_E_ARG;
+  if (op < 0 || nrhs < 1 || nrhs > c->max_rhs || !(tol > 0) || maxit < 1 || restart < 1 || restart > 1000)
+    return AIM_E_ARG;
   if (precision == AIM_MIXED && c->precision != AIM_MIXED) return AIM_E_ARG;
   if (form != AIM_TM_EFIE && c->t.basis != AIM_HAT) return AIM_E_ARG;
   if (form == AIM_TM_EFIE && c->t.basis != AIM_PULSE) return AIM_E_ARG;

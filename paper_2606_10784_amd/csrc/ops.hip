@@ -381,31 +381,40 @@ __global__ void k_near_build(NearGeo G, int basis, int64_t nnz, const int32_t* _
 // anterpolation: U[ch*nrhs + r][a] = sum_e w_ch[e] x[r*ldx + basis_e]
 // ---------------------------------------------------------------------------
 template <typename T, typename TW>
-__global__ void k_anterp(int n_act, int nrhs, const int32_t* __restrict__ at_ptr,
-                         const int32_t* __restrict__ at_basis, const TW* __restrict__ w0,
-                         const TW* __restrict__ w1, const TW* __restrict__ w2,
-                         const double2* __restrict__ x, int64_t ldx, cplx<T>* __restrict__ U) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_anterp(int n_act, int nrhs, const int32_t* __restrict__ at_ptr,
+                                                const int32_t* __restrict__ at_basis, const TW* __restrict__ w0,
+                                                const TW* __restrict__ w1, const TW* __restrict__ w2,
+                                                const double2* __restrict__ x, int64_t ldx,
+                                                cplx<T>* __restrict__ U) {
+  // 16 lanes per active grid point, shuffle reduction
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = gid >> 4, l = gid & 15;
   const int pair = blockIdx.y;              // ch * nrhs + r
-  if (a >= n_act) return;
+  if (a >= n_act) return;                   // whole 16-lane groups exit together
   const int ch = pair / nrhs, r = pair - ch * nrhs;
   const TW* w = ch == 0 ? w0 : (ch == 1 ? w1 : w2);
   const double2* xr = x + (size_t)r * ldx;
   T sx = 0, sy = 0;
-  for (int e = at_ptr[a]; e < at_ptr[a + 1]; ++e) {
+  const int e1 = at_ptr[a + 1];
+  for (int e = at_ptr[a] + l; e < e1; e += 16) {
     const double2 xv = xr[at_basis[e]];
     const T ww = (T)w[e];
     sx += ww * (T)xv.x;
     sy += ww * (T)xv.y;
   }
-  U[(size_t)pair * n_act + a] = mk<T>(sx, sy);
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) {
+    sx += __shfl_xor(sx, off, 16);
+    sy += __shfl_xor(sy, off, 16);
+  }
+  if (l == 0) U[(size_t)pair * n_act + a] = mk<T>(sx, sy);
 }
 
 // ---------------------------------------------------------------------------
 // interpolation + near field: 16 lanes per basis row
 //   y = scale * ( sum_ch sgn_ch W_ch . V_ch + C_near x )
 // ---------------------------------------------------------------------------
-template <typename T, typename TW>
+template <typename T, typename TW, int LANES>
 __global__ __launch_bounds__(256) void k_interp_near(
     int N, int nrhs, int nch, const TW* __restrict__ W0, const TW* __restrict__ W1,
     const TW* __restrict__ W2, double sg, const int32_t* __restrict__ aidx,
@@ -413,17 +422,18 @@ __global__ __launch_bounds__(256) void k_interp_near(
     const int32_t* __restrict__ ncol, const double2* __restrict__ C, const double2* __restrict__ x,
     int64_t ldx, double2* __restrict__ y, int64_t ldy, double2 scale) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = gid >> 4, l = gid & 15;
-  if (row >= N) return;          // whole 16-lane groups exit together
-  const size_t o = (size_t)row * 16 + l;
-  const int a = aidx[o];
-  const double w0 = (double)W0[o];
-  const double w1 = nch > 1 ? (double)W1[o] : 0.0;
-  const double w2 = nch > 1 ? (double)W2[o] : 0.0;
+  const int row = gid / LANES, l = gid % LANES;
+  if (row >= N) return;          // whole lane groups exit together
+  const bool st = l < 16;        // lanes 0..15 hold the 16 stencil entries
+  const size_t o = (size_t)row * 16 + (st ? l : 0);
+  const int a = st ? aidx[o] : 0;
+  const double w0 = st ? (double)W0[o] : 0.0;
+  const double w1 = (st && nch > 1) ? (double)W1[o] : 0.0;
+  const double w2 = (st && nch > 1) ? (double)W2[o] : 0.0;
   const int q0 = C ? nptr[row] : 0, q1 = C ? nptr[row + 1] : 0;
   for (int r = 0; r < nrhs; ++r) {
-    double ax, ay;
-    {
+    double ax = 0.0, ay = 0.0;
+    if (st) {
       const cplx<T> v0 = V[(size_t)r * n_act + a];
       ax = w0 * (double)v0.x;
       ay = w0 * (double)v0.y;
@@ -435,16 +445,16 @@ __global__ __launch_bounds__(256) void k_interp_near(
       }
     }
     const double2* xr = x + (size_t)r * ldx;
-    for (int q = q0 + l; q < q1; q += 16) {
+    for (int q = q0 + l; q < q1; q += LANES) {
       const double2 cv = C[q];
       const double2 xv = xr[ncol[q]];
       ax += cv.x * xv.x - cv.y * xv.y;
       ay += cv.x * xv.y + cv.y * xv.x;
     }
 #pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-      ax += __shfl_xor(ax, off, 16);
-      ay += __shfl_xor(ay, off, 16);
+    for (int off = LANES / 2; off >= 1; off >>= 1) {
+      ax += __shfl_xor(ax, off, LANES);
+      ay += __shfl_xor(ay, off, LANES);
     }
     if (l == 0) y[(size_t)r * ldy + row] = make_double2(scale.x * ax - scale.y * ay, scale.x * ay + scale.y * ax);
   }
@@ -787,7 +797,7 @@ static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int n
   cplx<T>* V = (cplx<T>*)c->d_V;
   cplx<T>* Tb = (cplx<T>*)c->d_T;
   const bool f32 = sizeof(T) == 4;
-  dim3 ga((t.n_act + 255) / 256, pairs);
+  dim3 ga((unsigned)(((size_t)t.n_act * 16 + 255) / 256), pairs);
   {
   ProfScope ps(c, AIM_K_ANTERP);
   if (f32) {
@@ -819,24 +829,33 @@ static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int n
   return AIM_OK;
 }
 
-template <typename T>
-static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near, const double2* Cn, int nrhs,
-                         const double2* x, int64_t ldx, double2* y, int64_t ldy, double2 scale) {
+template <typename T, int LANES>
+static void launch_interp(Ctx* c, const int* chans, int nch, double sg, const double2* C, int nrhs,
+                          const double2* x, int64_t ldx, double2* y, int64_t ldy, double2 scale) {
   HostTables& t = c->t;
   const int threads = 256;
-  dim3 g((unsigned)(((size_t)t.N * 16 + threads - 1) / threads));
+  dim3 g((unsigned)(((size_t)t.N * LANES + threads - 1) / threads));
   const cplx<T>* V = (const cplx<T>*)c->d_V;
-  const double2* C = near ? Cn : nullptr;
-  ProfScope ps(c, AIM_K_INTERP);
   if (sizeof(T) == 4) {
-    hipLaunchKernelGGL((k_interp_near<T, float>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
+    hipLaunchKernelGGL((k_interp_near<T, float, LANES>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
                        c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
                        c->d_aidx, V, t.n_act, c->d_nr_ptr, c->d_nr_col, C, x, ldx, y, ldy, scale);
   } else {
-    hipLaunchKernelGGL((k_interp_near<T, double>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
+    hipLaunchKernelGGL((k_interp_near<T, double, LANES>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
                        c->d_W[chans[0]], c->d_W[chans[nch > 1 ? 1 : 0]], c->d_W[chans[nch > 2 ? 2 : 0]], sg,
                        c->d_aidx, V, t.n_act, c->d_nr_ptr, c->d_nr_col, C, x, ldx, y, ldy, scale);
   }
+}
+
+template <typename T>
+static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near, const double2* Cn, int nrhs,
+                         const double2* x, int64_t ldx, double2* y, int64_t ldy, double2 scale) {
+  const double2* C = near ? Cn : nullptr;
+  ProfScope ps(c, AIM_K_INTERP);
+  // wide lane groups when the near-field rows are long
+  const bool wide = near && c->nnz >= (int64_t)40 * c->t.N;
+  if (wide) launch_interp<T, 64>(c, chans, nch, sg, C, nrhs, x, ldx, y, ldy, scale);
+  else launch_interp<T, 16>(c, chans, nch, sg, C, nrhs, x, ldx, y, ldy, scale);
   AIM_HIP_CHECK(hipGetLastError());
   return AIM_OK;
 }
