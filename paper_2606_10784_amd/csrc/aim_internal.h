@@ -80,8 +80,8 @@ struct GmresWork {
   double2 *V = nullptr, *W = nullptr, *H = nullptr, *g = nullptr, *cs = nullptr, *sn = nullptr,
           *y = nullptr, *hcol = nullptr, *part = nullptr, *r = nullptr, *x64 = nullptr, *d = nullptr,
           *b2 = nullptr, *nrm = nullptr;
-  double *bnorm = nullptr, *resid = nullptr, *hn = nullptr, *npart = nullptr;
-  int *active = nullptr;
+  double *bnorm = nullptr, *resid = nullptr, *hn = nullptr, *npart = nullptr, *w0part = nullptr;
+  int *active = nullptr, *reorth = nullptr;
   double* host_resid = nullptr;   // pinned
   int nchunk = 0;
   size_t bytes = 0;

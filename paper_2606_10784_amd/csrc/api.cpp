@@ -21,7 +21,7 @@ void free_ctx(Ctx* c) {
   GmresWork& w = c->gw;
   for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
                   (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
-                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.active})
+                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.w0part, (void*)w.reorth, (void*)w.active})
     if (p) hipFree(p);
   if (w.host_resid) hipHostFree(w.host_resid);
   w = GmresWork();

@@ -126,10 +126,38 @@ __device__ __forceinline__ void dft_r(cplx<T>* v) {
   else dft2<cplx<T>, INV>(v[0], v[1]);
 }
 
-// LDS index with one pad slot per 8 elements: breaks the power-of-two
-// strides of the early Stockham passes across banks.
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 3); }
-__host__ __device__ constexpr int padded(int n) { return n + (n >> 3); }
+#ifndef AIM_PAD_SHIFT
+#define AIM_PAD_SHIFT 4
+#endif
+#ifndef AIM_TW_RECUR
+#define AIM_TW_RECUR 1
+#endif
+// LDS index with one pad slot per 16 elements: the radix-16 first pass
+// stores with a stride of 16 elements, which the pad turns into 17 so the
+// lanes of a wave spread over all banks.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> AIM_PAD_SHIFT); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> AIM_PAD_SHIFT); }
+
+// w^r for r = 1..R-1 from w = w^1 by a product tree of depth <= 4
+template <typename V, int R>
+__device__ __forceinline__ void tw_powers(V w1, V* wp) {
+  wp[1] = w1;
+  if constexpr (R > 2) {
+    wp[2] = cmul(w1, w1);
+    wp[3] = cmul(wp[2], w1);
+  }
+  if constexpr (R > 4) {
+    wp[4] = cmul(wp[2], wp[2]);
+    wp[5] = cmul(wp[4], w1);
+    wp[6] = cmul(wp[4], wp[2]);
+    wp[7] = cmul(wp[4], wp[3]);
+  }
+  if constexpr (R > 8) {
+    wp[8] = cmul(wp[4], wp[4]);
+#pragma unroll
+    for (int r = 9; r < 16; ++r) wp[r] = cmul(wp[8], wp[r - 8]);
+  }
+}
 
 // One Stockham pass: sub-transform length NS -> NS*R.  Element i of column c
 // lives at buf[pidx(i * NCOL + c)].
@@ -149,12 +177,21 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __res
       for (int r = 0; r < R; ++r) v[q][r] = buf[pidx((j + r * (N / R)) * NCOL + c)];
       if constexpr (NS > 1) {
         const int k = j & (NS - 1);
+#if AIM_TW_RECUR
+        V w1 = tw[k * (N / (NS * R))];
+        if (INV) w1.y = -w1.y;
+        V wp[R];
+        tw_powers<V, R>(w1, wp);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wp[r]);
+#else
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           V w = tw[k * r * (N / (NS * R))];
           if (INV) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
         }
+#endif
       }
       dft_r<T, R, INV>(v[q]);
     }
@@ -190,8 +227,11 @@ __device__ __forceinline__ void fft_passes(cplx<T>* buf, const cplx<T>* __restri
 // pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror N - q); the last slot pair
 // of the last block holds the self-mirrored columns 0 and N/2.
 // ---------------------------------------------------------------------------
+#ifndef AIM_COL_LDS_BYTES
+#define AIM_COL_LDS_BYTES 80000   // padded LDS per column block: two blocks per CU
+#endif
 template <typename T, int N> struct ColCfg {
-  static constexpr int BYTES = 160000;   // padded LDS per block, <= 160 KiB
+  static constexpr int BYTES = AIM_COL_LDS_BYTES;
   static constexpr int CB0 = BYTES / (padded(N) * (int)sizeof(cplx<T>));
   static constexpr int CB1 = CB0 < 2 ? 2 : (CB0 > 16 ? 16 : CB0);
   static constexpr int CB = (CB1 >= 16) ? 16 : (CB1 >= 8 ? 8 : (CB1 >= 4 ? 4 : 2));

@@ -22,16 +22,20 @@ static constexpr int RED_CHUNK = 2048;
 // Arnoldi steps enqueued between two host reads of the residual estimates
 static constexpr int kCheckEvery = 8;
 
-// partial sums of conj(V_i) . w over a chunk, or |w|^2 when V == nullptr
+// partial sums of conj(V_i) . w over a chunk, or |w|^2 when V == nullptr.
+// skip (optional): right-hand sides whose flag is 0 do nothing.  w0part
+// (optional): blocks with i == 0 also leave the partial |w|^2 of the chunk.
 __global__ __launch_bounds__(256) void k_dots(int N, const double2* __restrict__ V, int64_t ld_rhs_v,
                                               const double2* __restrict__ w, int64_t ld_w,
                                               const int* __restrict__ active, double2* __restrict__ part,
-                                              int nchunk, int jmax) {
+                                              int nchunk, int jmax, const int* __restrict__ skip = nullptr,
+                                              double* __restrict__ w0part = nullptr) {
   const int chunk = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
-  if (!active[r]) return;
+  if (!active[r] || (skip && !skip[r])) return;
   const double2* vi = V ? V + (size_t)r * ld_rhs_v + (size_t)i * N : nullptr;
   const double2* wr = w + (size_t)r * ld_w;
-  double sx = 0, sy = 0;
+  const bool wn = w0part && i == 0;
+  double sx = 0, sy = 0, sw = 0;
   const int n0 = chunk * RED_CHUNK, n1 = min(N, n0 + RED_CHUNK);
   for (int n = n0 + threadIdx.x; n < n1; n += 256) {
     const double2 b = wr[n];
@@ -39,22 +43,28 @@ __global__ __launch_bounds__(256) void k_dots(int N, const double2* __restrict__
       const double2 a = vi[n];
       sx += a.x * b.x + a.y * b.y;
       sy += a.x * b.y - a.y * b.x;
+      if (wn) sw += b.x * b.x + b.y * b.y;
     } else {
       sx += b.x * b.x + b.y * b.y;
     }
   }
-  __shared__ double rx[256], ry[256];
+  __shared__ double rx[256], ry[256], rw[256];
   rx[threadIdx.x] = sx;
   ry[threadIdx.x] = sy;
+  rw[threadIdx.x] = sw;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       rx[threadIdx.x] += rx[threadIdx.x + s];
       ry[threadIdx.x] += ry[threadIdx.x + s];
+      rw[threadIdx.x] += rw[threadIdx.x + s];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[((size_t)r * jmax + i) * nchunk + chunk] = make_double2(rx[0], ry[0]);
+  if (threadIdx.x == 0) {
+    part[((size_t)r * jmax + i) * nchunk + chunk] = make_double2(rx[0], ry[0]);
+    if (wn) w0part[(size_t)r * nchunk + chunk] = rw[0];
+  }
 }
 
 // out[r][i] = sum_chunk part (fixed order); mode 1: accumulate into H column
@@ -112,10 +122,10 @@ __global__ __launch_bounds__(256) void k_cgs_update(int N, int j1, int nchunk, i
                                                     int64_t ld_rhs_v, const int* __restrict__ active,
                                                     double2* __restrict__ w, int64_t ld_w, double2* __restrict__ H,
                                                     int ldh, int j, int first, int want_norm,
-                                                    double* __restrict__ npart) {
+                                                    double* __restrict__ npart, const int* __restrict__ skip) {
   extern __shared__ double2 hsh[];
   const int r = blockIdx.y;
-  if (!active[r]) return;
+  if (!active[r] || (skip && !skip[r])) return;
   const double2* pr = part + (size_t)r * jmax * nchunk;
   for (int i = threadIdx.x; i < j1; i += 256) {
     double sx = 0, sy = 0;
@@ -200,88 +210,141 @@ __global__ void k_axpy(int N, const double2* d, double2* x) {
   x[(size_t)c * N + n] = make_double2(o.x + a.x, o.y + a.y);
 }
 
-// ||w|| from the block partials (fixed order), H[j+1, j] = ||w||, then the
-// Givens update of column j: the column and the previous rotations are
-// staged in LDS so one thread runs the dependent chain from LDS.  One block
-// per right-hand side; dynamic LDS: (ldh + 2 * restart) double2.
-__global__ __launch_bounds__(256) void k_norm_givens(int nrhs, int ldh, int j, int nparts,
-                                                     const double* __restrict__ npart,
-                                                     const int* __restrict__ active, double2* H, double2* cs,
-                                                     double2* sn, double2* g, double* resid_hist, double* hn) {
-  extern __shared__ double2 sh[];
+// Selective re-orthogonalisation (Daniel-Gragg-Kaufman-Stewart): a second
+// Gram-Schmidt pass is needed only when the first one removed more than
+// half of |w|^2, i.e. ||w1|| < ||w0|| / sqrt(2).  One block per rhs.
+__global__ void k_reorth_flag(int nchunk, int nparts, const double* __restrict__ w0part,
+                              const double* __restrict__ npart, const int* __restrict__ active, int* reorth) {
   const int r = blockIdx.x;
   if (!active[r]) return;
-  const int R = ldh - 1;
-  double2* Hs = sh;            // ldh
-  double2* Cs = sh + ldh;      // R
-  double2* Ss = Cs + R;        // R
+  __shared__ double a[256], b[256];
+  double s0 = 0, s1 = 0;
+  for (int q = threadIdx.x; q < nchunk; q += 256) s0 += w0part[(size_t)r * nchunk + q];
+  for (int q = threadIdx.x; q < nparts; q += 256) s1 += npart[(size_t)r * nparts + q];
+  a[threadIdx.x] = s0;
+  b[threadIdx.x] = s1;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      a[threadIdx.x] += a[threadIdx.x + st];
+      b[threadIdx.x] += b[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) reorth[r] = (b[0] < 0.5 * a[0]) ? 1 : 0;
+}
+
+// hn = ||w|| from the block partials (fixed order); v_{j+1} = w / hn; block 0
+// records H[j+1, j] = hn (before rotation).
+__global__ __launch_bounds__(256) void k_scale_norm(int N, int nparts, const double* __restrict__ npart,
+                                                    const double2* __restrict__ w, int64_t ld_w,
+                                                    double2* __restrict__ v, int64_t ld_rhs_v,
+                                                    const int* __restrict__ active, double2* H, int ldh, int j) {
+  const int r = blockIdx.y;
+  if (!active[r]) return;
   __shared__ double red[256];
   double t = 0.0;
   for (int q = threadIdx.x; q < nparts; q += 256) t += npart[(size_t)r * nparts + q];
   red[threadIdx.x] = t;
-  double2* Hc = H + (size_t)r * ldh * R + (size_t)j * ldh;
-  double2* c = cs + (size_t)r * R;
-  double2* s = sn + (size_t)r * R;
-  for (int i = threadIdx.x; i <= j; i += 256) Hs[i] = Hc[i];
-  for (int i = threadIdx.x; i < j; i += 256) {
-    Cs[i] = c[i];
-    Ss[i] = s[i];
-  }
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double hnr = sqrt(red[0]);
-    hn[r] = hnr;
-    Hs[j + 1] = make_double2(hnr, 0.0);
-    double2 a = Hs[0];
-    for (int i = 0; i < j; ++i) {
-      const double ci = Cs[i].x;
-      const double2 si = Ss[i];
-      const double2 b = Hs[i + 1];
-      // [c s; -conj(s) c]
-      Hs[i] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
-      a = make_double2(-(si.x * a.x + si.y * a.y) + ci * b.x, -(si.x * a.y - si.y * a.x) + ci * b.y);
-    }
-    const double2 b = Hs[j + 1];
-    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-    const double den = hypot(na, nb);
-    double ci;
-    double2 si;
-    if (na == 0.0) {
-      ci = 0.0;
-      si = make_double2(1.0, 0.0);
-    } else {
-      ci = na / den;
-      const double2 ph = make_double2(a.x / na, a.y / na);
-      si = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);
-    }
-    c[j] = make_double2(ci, 0.0);
-    s[j] = si;
-    Hs[j] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
-    Hs[j + 1] = make_double2(0.0, 0.0);
-    double2* gg = g + (size_t)r * ldh;
-    const double2 gj = gg[j];
-    gg[j + 1] = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));
-    gg[j] = make_double2(ci * gj.x, ci * gj.y);
-    resid_hist[(size_t)r * R + j] = hypot(gg[j + 1].x, gg[j + 1].y);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j + 1; i += 256) Hc[i] = Hs[i];
-}
-
-// v = w / hn[r]
-__global__ void k_scale_to(int N, const double* __restrict__ hn, const double2* __restrict__ w, int64_t ld_w,
-                           double2* __restrict__ v, int64_t ld_rhs_v, const int* __restrict__ active) {
+  const double hnr = sqrt(red[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    H[(size_t)r * ldh * (ldh - 1) + (size_t)j * ldh + j + 1] = make_double2(hnr, 0.0);
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (n >= N || !active[r]) return;
-  const double nr = hn[r];
-  const double sc = nr > 0 ? 1.0 / nr : 0.0;
+  if (n >= N) return;
+  const double sc = hnr > 0 ? 1.0 / hnr : 0.0;
   const double2 a = w[(size_t)r * ld_w + n];
   v[(size_t)r * ld_rhs_v + n] = make_double2(a.x * sc, a.y * sc);
+}
+
+__device__ __forceinline__ void rot_apply(double ci, double2 si, double2& a, double2 b, double2& out_top) {
+  // [c s; -conj(s) c] (a, b) -> (out_top, a)
+  out_top = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
+  a = make_double2(-(si.x * a.x + si.y * a.y) + ci * b.x, -(si.x * a.y - si.y * a.x) + ci * b.y);
+}
+
+// Givens rotations for the Hessenberg columns j0..j1-1 of each rhs: the
+// rotations 0..j0-1 are applied to the new columns in parallel (one thread
+// per column, chains read from LDS), then the new rotations are formed in
+// order.  Writes the residual estimates |g_{j+1}| of those steps.  One block
+// per rhs; dynamic LDS: (j1 - j0) * ldh + 2 * j1 double2.
+__global__ __launch_bounds__(64) void k_givens_batch(int ldh, int j0, int j1, const int* __restrict__ active,
+                                                     double2* H, double2* cs, double2* sn, double2* g,
+                                                     double* resid_hist) {
+  extern __shared__ double2 sh[];
+  const int r = blockIdx.x;
+  if (!active[r]) return;
+  const int R = ldh - 1;
+  const int nc = j1 - j0;
+  double2* Hs = sh;                        // nc columns of ldh
+  double2* Cs = sh + (size_t)nc * ldh;     // j1
+  double2* Ss = Cs + j1;                   // j1
+  double2* Hr = H + (size_t)r * ldh * R;
+  double2* c = cs + (size_t)r * R;
+  double2* s = sn + (size_t)r * R;
+  for (int t = 0; t < nc; ++t)
+    for (int i = threadIdx.x; i <= j0 + t + 1; i += 64) Hs[(size_t)t * ldh + i] = Hr[(size_t)(j0 + t) * ldh + i];
+  for (int i = threadIdx.x; i < j0; i += 64) {
+    Cs[i] = c[i];
+    Ss[i] = s[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    double2* col = Hs + (size_t)threadIdx.x * ldh;
+    double2 a = col[0];
+    for (int i = 0; i < j0; ++i) {
+      double2 top;
+      rot_apply(Cs[i].x, Ss[i], a, col[i + 1], top);
+      col[i] = top;
+    }
+    col[j0] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2* gg = g + (size_t)r * ldh;
+    for (int t = 0; t < nc; ++t) {
+      const int jj = j0 + t;
+      double2* col = Hs + (size_t)t * ldh;
+      double2 a = col[j0];
+      for (int i = j0; i < jj; ++i) {
+        double2 top;
+        rot_apply(Cs[i].x, Ss[i], a, col[i + 1], top);
+        col[i] = top;
+      }
+      const double2 b = col[jj + 1];
+      const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+      const double den = hypot(na, nb);
+      double ci;
+      double2 si;
+      if (na == 0.0) {
+        ci = 0.0;
+        si = make_double2(1.0, 0.0);
+      } else {
+        ci = na / den;
+        const double2 ph = make_double2(a.x / na, a.y / na);
+        si = make_double2((ph.x * b.x + ph.y * b.y) / den, (ph.y * b.x - ph.x * b.y) / den);
+      }
+      Cs[jj] = make_double2(ci, 0.0);
+      Ss[jj] = si;
+      col[jj] = make_double2(ci * a.x + si.x * b.x - si.y * b.y, ci * a.y + si.x * b.y + si.y * b.x);
+      col[jj + 1] = make_double2(0.0, 0.0);
+      const double2 gj = gg[jj];
+      gg[jj + 1] = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));
+      gg[jj] = make_double2(ci * gj.x, ci * gj.y);
+      resid_hist[(size_t)r * R + jj] = hypot(gg[jj + 1].x, gg[jj + 1].y);
+    }
+  }
+  __syncthreads();
+  for (int t = 0; t < nc; ++t)
+    for (int i = threadIdx.x; i <= j0 + t + 1; i += 64) Hr[(size_t)(j0 + t) * ldh + i] = Hs[(size_t)t * ldh + i];
+  for (int i = j0 + threadIdx.x; i < j1; i += 64) {
+    c[i] = Cs[i];
+    s[i] = Ss[i];
+  }
 }
 
 // y = H^-1 g (upper triangular, jm x jm), column-oriented back substitution,
@@ -326,7 +389,7 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
   if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
   for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
                   (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
-                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.active})
+                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.w0part, (void*)w.reorth, (void*)w.active})
     if (p) hipFree(p);
   if (w.host_resid) hipHostFree(w.host_resid);
   c->dev_bytes -= w.bytes;
@@ -349,11 +412,19 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
             A((void**)&w.part, (size_t)nrhs * ldh * w.nchunk * 16) && A((void**)&w.r, (size_t)nrhs * N * 16) &&
             A((void**)&w.d, (size_t)nrhs * N * 16) && A((void**)&w.b2, (size_t)nrhs * N * 16) &&
             A((void**)&w.nrm, (size_t)nrhs * 2 * 16) && A((void**)&w.bnorm, (size_t)nrhs * 8) &&
-            A((void**)&w.resid, (size_t)nrhs * restart * 8) && A((void**)&w.hn, (size_t)nrhs * 8) && A((void**)&w.npart, (size_t)nrhs * ((N + 31) / 32) * 8) &&
+            A((void**)&w.resid, (size_t)nrhs * restart * 8) && A((void**)&w.hn, (size_t)nrhs * 8) && A((void**)&w.npart, (size_t)nrhs * ((N + 31) / 32) * 8) && A((void**)&w.w0part, (size_t)nrhs * w.nchunk * 8) &&
+            A((void**)&w.reorth, (size_t)nrhs * 4) &&
             A((void**)&w.active, (size_t)nrhs * 4 * 2);
   if (!ok) return AIM_E_OOM;
   if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * restart * 8) != hipSuccess) return AIM_E_OOM;
   w.bytes = tot;
+  {
+    const size_t gb = ((size_t)kCheckEvery * ldh + 2 * (size_t)restart) * 16;
+    if (gb > 65536 &&
+        hipFuncSetAttribute((const void*)k_givens_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gb) !=
+            hipSuccess)
+      return AIM_E_HIP;
+  }
   c->dev_bytes += tot;
   return AIM_OK;
 }
@@ -447,24 +518,31 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
         // w = A v_j
         TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
         res.matvecs++;
-        // CGS2: two passes of (Vᴴw partials, fused reduce + update); the
-        // second pass also leaves the partial norms of the new w
+        // CGS with selective re-orthogonalisation: pass 1 always; pass 2 only
+        // where the flag kernel asks for it (decided on the device)
         const int gblk = (N + GV_ROWS - 1) / GV_ROWS;
-        for (int pass = 0; pass < 2; ++pass) {
-          hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
-                             w.active, w.part, w.nchunk, ldh);
-          hipLaunchKernelGGL(k_cgs_update, dim3(gblk, nrhs), dim3(256), (size_t)j1 * 16, s, N, j1, w.nchunk, ldh,
-                             w.part, w.V, ldv, w.active, w.W, (int64_t)N, w.H, ldh, j, pass == 0 ? 1 : 0,
-                             pass == 1 ? 1 : 0, w.npart);
-        }
-        hipLaunchKernelGGL(k_norm_givens, dim3(nrhs), dim3(256), (size_t)(ldh + 2 * restart) * 16, s, nrhs, ldh, j,
-                           gblk, w.npart, w.active, w.H, w.cs, w.sn, w.g, w.resid, w.hn);
-        hipLaunchKernelGGL(k_scale_to, gN, dim3(256), 0, s, N, w.hn, w.W, (int64_t)N, w.V + (size_t)j1 * N, ldv,
-                           w.active);
+        hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
+                           w.active, w.part, w.nchunk, ldh, (const int*)nullptr, w.w0part);
+        hipLaunchKernelGGL(k_cgs_update, dim3(gblk, nrhs), dim3(256), (size_t)j1 * 16, s, N, j1, w.nchunk, ldh,
+                           w.part, w.V, ldv, w.active, w.W, (int64_t)N, w.H, ldh, j, 1, 1, w.npart,
+                           (const int*)nullptr);
+        hipLaunchKernelGGL(k_reorth_flag, dim3(nrhs), dim3(256), 0, s, w.nchunk, gblk, w.w0part, w.npart, w.active,
+                           w.reorth);
+        hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
+                           w.active, w.part, w.nchunk, ldh, (const int*)w.reorth, (double*)nullptr);
+        hipLaunchKernelGGL(k_cgs_update, dim3(gblk, nrhs), dim3(256), (size_t)j1 * 16, s, N, j1, w.nchunk, ldh,
+                           w.part, w.V, ldv, w.active, w.W, (int64_t)N, w.H, ldh, j, 0, 1, w.npart,
+                           (const int*)w.reorth);
+        hipLaunchKernelGGL(k_scale_norm, gN, dim3(256), 0, s, N, gblk, w.npart, w.W, (int64_t)N,
+                           w.V + (size_t)j1 * N, ldv, w.active, w.H, ldh, j);
         AIM_HIP_CHECK(hipGetLastError());
         total++;
       }
-      // residual estimates of the steps just taken
+      // rotations for the steps just taken, then their residual estimates
+      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(64),
+                         ((size_t)(jend - jstart) * ldh + 2 * (size_t)jend) * 16, s, ldh, jstart, jend, w.active, w.H,
+                         w.cs, w.sn, w.g, w.resid);
+      AIM_HIP_CHECK(hipGetLastError());
       for (int r = 0; r < nrhs; ++r)
         if (act[r])
           AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jstart, w.resid + (size_t)r * restart + jstart,
