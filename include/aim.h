@@ -189,6 +189,13 @@ enum { AIM_K_ANTERP = 0, AIM_K_ROWS_FWD = 1, AIM_K_COLS = 2, AIM_K_ROWS_INV = 3,
 aim_status aim_profile_start(aim_ctx ctx, int32_t kernel, int32_t every, int32_t max_samples);
 aim_status aim_profile_stop(aim_ctx ctx, double* avg_ms, int64_t* samples, int64_t* launches);
 
+/* Grid-kernel spectra F(c_grid) are shared by all contexts of a process on
+   one device with the same m, k*eps and precision (the samples depend on
+   k*eps only); a spectrum stays resident after its last context is
+   destroyed, up to 8 GiB of cached spectra.  aim_cache_clear frees the
+   unreferenced ones and returns the bytes freed.  Thread-safe.               */
+size_t aim_cache_clear(void);
+
 void aim_destroy(aim_ctx ctx);
 const char* aim_strerror(aim_status s);
 

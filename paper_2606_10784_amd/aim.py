@@ -84,6 +84,7 @@ EXPORTS = {
     "aim_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "aim_profile_stop": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "aim_cache_clear": (ctypes.c_size_t, []),
     "aim_destroy": (None, [ctypes.c_void_p]),
     "aim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -307,6 +308,10 @@ def aim_profile_stop(ctx):
     _check(_lib().aim_profile_stop(ctx.handle, ctypes.byref(ms), ctypes.byref(ns), ctypes.byref(nl)),
            "aim_profile_stop")
     return ms.value, ns.value, nl.value
+
+
+def aim_cache_clear():
+    return int(_lib().aim_cache_clear())
 
 
 def header_functions(path=None):

@@ -83,6 +83,7 @@ struct GmresWork {
   double *bnorm = nullptr, *resid = nullptr, *hn = nullptr, *npart = nullptr, *w0part = nullptr;
   int *active = nullptr, *reorth = nullptr;
   double* host_resid = nullptr;   // pinned
+  int* pin = nullptr;             // pinned mask staging
   int nchunk = 0;
   size_t bytes = 0;
 };
@@ -108,8 +109,9 @@ struct Ctx {
   double* d_at_w[4] = {nullptr, nullptr, nullptr, nullptr};
   float* d_at_wf[4] = {nullptr, nullptr, nullptr, nullptr};
   // spectra (quarter, [kxq][kyq], pre-scaled by 1/n^2)
-  double2 *d_C = nullptr, *d_Ca = nullptr;
-  float2 *d_Cf = nullptr, *d_Caf = nullptr;
+  double2 *d_C = nullptr, *d_Ca = nullptr, *own_Ca = nullptr;
+  float2 *d_Cf = nullptr, *d_Caf = nullptr, *own_Caf = nullptr;
+  void* spec = nullptr;          // shared spectrum cache entry
   double2* d_tw = nullptr;
   float2* d_twf = nullptr;
   double2* d_ksmall = nullptr;   // kernel at offsets |d| <= R+3 (rows dy, cols dx)
@@ -154,6 +156,9 @@ struct ProfScope {
 aim_status dev_alloc(Ctx* c, void** p, size_t bytes);
 aim_status setup_device(Ctx* c);                        // tables, spectrum, near field
 aim_status apply_filter(Ctx* c, double alpha);
+aim_status acquire_spectrum(Ctx* c, double keps);
+void release_spectrum(Ctx* c);
+size_t cache_clear();
 // y(:, r) = op x(:, r), column strides ldx / ldy (elements), FP64 vectors
 aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy);
 aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b);

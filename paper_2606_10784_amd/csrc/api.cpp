@@ -16,6 +16,7 @@ namespace aim {
 void free_ctx(Ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  release_spectrum(c);
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
   GmresWork& w = c->gw;
@@ -24,6 +25,7 @@ void free_ctx(Ctx* c) {
                   (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.w0part, (void*)w.reorth, (void*)w.active})
     if (p) hipFree(p);
   if (w.host_resid) hipHostFree(w.host_resid);
+  if (w.pin) hipHostFree(w.pin);
   w = GmresWork();
 }
 
@@ -206,6 +208,8 @@ aim_status aim_profile_stop(aim_ctx ctx, double* avg_ms, int64_t* samples, int64
   c.ev_used = 0;
   return AIM_OK;
 }
+
+size_t aim_cache_clear(void) { return cache_clear(); }
 
 void aim_destroy(aim_ctx ctx) {
   if (!ctx) return;

@@ -392,6 +392,7 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
                   (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.w0part, (void*)w.reorth, (void*)w.active})
     if (p) hipFree(p);
   if (w.host_resid) hipHostFree(w.host_resid);
+  if (w.pin) hipHostFree(w.pin);
   c->dev_bytes -= w.bytes;
   w = GmresWork();
   const int N = c->t.N;
@@ -417,6 +418,12 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
             A((void**)&w.active, (size_t)nrhs * 4 * 2);
   if (!ok) return AIM_E_OOM;
   if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * restart * 8) != hipSuccess) return AIM_E_OOM;
+  // pinned staging for the host-to-device mask copies (one region per use,
+  // each rewritten only after the stream has been synchronised)
+  if (hipHostMalloc((void**)&w.pin, (size_t)nrhs * 4 * sizeof(int)) != hipSuccess) return AIM_E_OOM;
+  for (int r = 0; r < 4 * nrhs; ++r) w.pin[r] = 1;
+  // all-ones mask used by the residual checks
+  if (hipMemcpy(w.active + nrhs, w.pin, (size_t)nrhs * 4, hipMemcpyHostToDevice) != hipSuccess) return AIM_E_HIP;
   w.bytes = tot;
   {
     const size_t gb = ((size_t)kCheckEvery * ldh + 2 * (size_t)restart) * 16;
@@ -463,9 +470,15 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
   const int ldh = restart + 1;
   const int64_t ldv = (int64_t)ldh * N;
   const dim3 gN((N + 255) / 256, nrhs);
-  int* d_all = w.active + nrhs;   // all-ones mask
-  std::vector<int> ones(nrhs, 1), act(nrhs, 1), jdone(nrhs, 0);
-  AIM_HIP_CHECK(hipMemcpyAsync(d_all, ones.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+  int* d_all = w.active + w.nrhs;   // all-ones mask (set at allocation)
+  std::vector<int> act(nrhs, 1), jdone(nrhs, 0);
+  int* pin_act = w.pin;
+  int* pin_upd = w.pin + nrhs;
+  int* pin_jm = w.pin + 2 * nrhs;
+  auto put_mask = [&](int* dst, int* stage, const std::vector<int>& v) {
+    std::copy(v.begin(), v.end(), stage);
+    return hipMemcpyAsync(dst, stage, nrhs * 4, hipMemcpyHostToDevice, s);
+  };
   // ||b||
   TRY(norms(c, nrhs, b, N, d_all, w.nrm));
   std::vector<double2> hb(nrhs);
@@ -488,7 +501,7 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
     TRY(matvec(c, op, nrhs, x, N, w.W, N));
     res.matvecs++;
     hipLaunchKernelGGL(k_bminus, gN, dim3(256), 0, s, N, b, w.W);
-    AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
     TRY(norms(c, nrhs, w.W, N, w.active, w.nrm));
     std::vector<double2> h0(nrhs);
     AIM_HIP_CHECK(hipMemcpyAsync(h0.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
@@ -503,7 +516,7 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
       else any = true;
     }
     if (!any || total >= maxit) break;
-    AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
     hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, (int64_t)1, w.W, (int64_t)N, w.V, ldv, w.active,
                        w.hn);
     hipLaunchKernelGGL(k_set_g0, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, w.nrm, w.active, w.g);
@@ -562,14 +575,14 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
         if (act[r]) left = true;
       }
       if (!left) break;
-      if (changed) AIM_HIP_CHECK(hipMemcpyAsync(w.active, act.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+      if (changed) AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
     }
     // x += V y for every column that took steps in this cycle
     std::vector<int> upd(nrhs, 0);
     for (int r = 0; r < nrhs; ++r) upd[r] = (cyc[r] && jdone[r] > 0) ? 1 : 0;
     int* d_jm = (int*)w.part;   // scratch: jm then mask
-    AIM_HIP_CHECK(hipMemcpyAsync(d_jm, jdone.data(), nrhs * 4, hipMemcpyHostToDevice, s));
-    AIM_HIP_CHECK(hipMemcpyAsync(w.active, upd.data(), nrhs * 4, hipMemcpyHostToDevice, s));
+    AIM_HIP_CHECK(put_mask(d_jm, pin_jm, jdone));
+    AIM_HIP_CHECK(put_mask(w.active, pin_upd, upd));
     hipLaunchKernelGGL(k_trisolve, dim3(nrhs), dim3(256), (size_t)ldh * 16, s, nrhs, ldh, d_jm, w.H, w.g, w.y);
     int jmax = 0;
     for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jdone[r]);
@@ -616,7 +629,7 @@ static int form_op(int form) {
 static aim_status true_resid(Ctx* c, int op, int nrhs, const double2* b, const double2* x, std::vector<double>& out) {
   GmresWork& w = c->gw;
   const int N = c->t.N;
-  int* d_all = w.active + nrhs;
+  int* d_all = w.active + w.nrhs;
   TRY(matvec(c, op, nrhs, x, N, w.W, N));
   hipLaunchKernelGGL(k_bminus, dim3((N + 255) / 256, nrhs), dim3(256), 0, c->stream, N, b, w.W);
   TRY(norms(c, nrhs, w.W, N, d_all, w.nrm));

@@ -9,8 +9,10 @@
 //  * anterpolation (transposed stencils, gather per active grid point) and
 //    interpolation fused with the near-field product (16 lanes per row)
 //  * Gram solve G^-1 (Sec. II): pulses diagonal, hats cyclic tridiagonal
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 
 #include "aim_internal.h"
 
@@ -71,17 +73,20 @@ __global__ void k_eval_green(int n, const double* R, double k, double2* out) {
 // ---------------------------------------------------------------------------
 // grid kernel sampling (wrap-around layout of the n x n circulant)
 // ---------------------------------------------------------------------------
-__global__ void k_sample_kernel(int m, int n, double eps, double k, double2* c) {
+// g at grid offsets depends on k eps only: g = -(j/4) H0^(2)(k eps |d|)
+__device__ __forceinline__ double2 green_grid(double keps, int dx, int dy) {
+  const double x = keps * sqrt((double)dx * dx + (double)dy * dy);
+  return make_double2(-0.25 * y0(x), -0.25 * j0(x));
+}
+
+__global__ void k_sample_kernel(int m, int n, double keps, double2* c) {
   const int qx = blockIdx.x * blockDim.x + threadIdx.x;
   const int qy = blockIdx.y;
   if (qx >= n) return;
   const int dx = qx < m ? qx : qx - n;   // qx == m: ring, |d| = m -> 0
   const int dy = qy < m ? qy : qy - n;
   double2 v = make_double2(0.0, 0.0);
-  if (qx != m && qy != m && (dx != 0 || dy != 0)) {
-    const double R = eps * sqrt((double)dx * dx + (double)dy * dy);
-    v = green(R, k);
-  }
+  if (qx != m && qy != m && (dx != 0 || dy != 0)) v = green_grid(keps, dx, dy);
   c[(size_t)qy * n + qx] = v;
 }
 
@@ -99,9 +104,11 @@ __global__ void k_extract_quarter(int n, const double2* C, double2* Q, float2* Q
   if (Qf) Qf[(size_t)kx * H + ky] = make_float2((float)v.x, (float)v.y);
 }
 
-__global__ void k_small_table(int m, int n, int ks, const double2* c, double2* out) {
+// the same grid kernel at the small offsets the near-field correction needs
+__global__ void k_small_table(int ks, double keps, double2* out) {
   const int dx = threadIdx.x, dy = blockIdx.x;
-  if (dx < ks && dy < ks) out[dy * ks + dx] = c[(size_t)dy * n + dx];
+  if (dx >= ks || dy >= ks) return;
+  out[dy * ks + dx] = (dx == 0 && dy == 0) ? make_double2(0.0, 0.0) : green_grid(keps, dx, dy);
 }
 
 // numerical filter on the quarter: keep qx^2 + qy^2 <= thr
@@ -651,6 +658,122 @@ static aim_status upload(Ctx* c, V** dst, const void* src, size_t bytes) {
     if (s_ != AIM_OK) return s_;       \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// process-wide cache of grid-kernel spectra, keyed by (device, m, k eps, FP32
+// copy).  The samples depend on k eps only, so a cached spectrum is the one
+// a fresh context would compute.  Entries without users stay resident until
+// aim_cache_clear or until the cache exceeds kSpecCacheBytes.
+// ---------------------------------------------------------------------------
+struct SpecEntry {
+  int device = 0, m = 0;
+  double keps = 0;
+  bool f32 = false;
+  double2* C = nullptr;
+  float2* Cf = nullptr;
+  int refs = 0;
+  size_t bytes = 0;
+  uint64_t last_use = 0;
+};
+static std::mutex g_spec_mu;
+static std::vector<SpecEntry*> g_spec;
+static uint64_t g_spec_clock = 0;
+static constexpr size_t kSpecCacheBytes = (size_t)8 << 30;
+
+static void spec_free(SpecEntry* e) {
+  if (e->C) (void)hipFree(e->C);
+  if (e->Cf) (void)hipFree(e->Cf);
+  delete e;
+}
+
+static void spec_evict_locked(size_t budget) {
+  size_t tot = 0;
+  for (SpecEntry* e : g_spec) tot += e->bytes;
+  while (tot > budget) {
+    SpecEntry* victim = nullptr;
+    for (SpecEntry* e : g_spec)
+      if (e->refs == 0 && (!victim || e->last_use < victim->last_use)) victim = e;
+    if (!victim) break;
+    tot -= victim->bytes;
+    g_spec.erase(std::find(g_spec.begin(), g_spec.end(), victim));
+    spec_free(victim);
+  }
+}
+
+aim_status acquire_spectrum(Ctx* c, double keps) {
+  const int m = c->t.m, n = c->t.n, H = n / 2 + 1;
+  const bool f32 = c->precision == AIM_MIXED;
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  for (SpecEntry* e : g_spec)
+    if (e->device == c->device && e->m == m && e->keps == keps && (e->f32 || !f32)) {
+      e->refs++;
+      e->last_use = ++g_spec_clock;
+      c->spec = e;
+      c->d_C = e->C;
+      c->d_Cf = e->Cf;
+      return AIM_OK;
+    }
+  SpecEntry* e = new SpecEntry();
+  e->device = c->device;
+  e->m = m;
+  e->keps = keps;
+  e->f32 = f32;
+  e->bytes = (size_t)H * H * (sizeof(double2) + (f32 ? sizeof(float2) : 0));
+  spec_evict_locked(kSpecCacheBytes > e->bytes ? kSpecCacheBytes - e->bytes : 0);
+  hipStream_t s = c->stream;
+  double2* cfull = nullptr;
+  bool ok = hipMalloc(&cfull, (size_t)n * n * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc(&e->C, (size_t)H * H * sizeof(double2)) == hipSuccess;
+  if (ok && f32) ok = hipMalloc(&e->Cf, (size_t)H * H * sizeof(float2)) == hipSuccess;
+  if (!ok) {
+    if (cfull) (void)hipFree(cfull);
+    spec_free(e);
+    return AIM_E_OOM;
+  }
+  hipLaunchKernelGGL(k_sample_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, m, n, keps, cfull);
+  aim_status st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
+  if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
+  if (st == AIM_OK) {
+    hipLaunchKernelGGL(k_extract_quarter, dim3((H + 255) / 256, H), dim3(256), 0, s, n, cfull, e->C, e->Cf);
+    if (hipStreamSynchronize(s) != hipSuccess) st = AIM_E_HIP;
+  }
+  (void)hipFree(cfull);
+  if (st != AIM_OK) {
+    spec_free(e);
+    return st;
+  }
+  e->refs = 1;
+  e->last_use = ++g_spec_clock;
+  g_spec.push_back(e);
+  c->spec = e;
+  c->d_C = e->C;
+  c->d_Cf = e->Cf;
+  return AIM_OK;
+}
+
+void release_spectrum(Ctx* c) {
+  if (!c->spec) return;
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  ((SpecEntry*)c->spec)->refs--;
+  c->spec = nullptr;
+  c->d_C = nullptr;
+  c->d_Cf = nullptr;
+}
+
+size_t cache_clear() {
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  size_t freed = 0;
+  for (auto it = g_spec.begin(); it != g_spec.end();) {
+    if ((*it)->refs == 0) {
+      freed += (*it)->bytes;
+      spec_free(*it);
+      it = g_spec.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return freed;
+}
+
 aim_status setup_device(Ctx* c) {
   HostTables& t = c->t;
   const int N = t.N, n = t.n, m = t.m;
@@ -689,31 +812,13 @@ aim_status setup_device(Ctx* c) {
   }
   AIM_HIP_CHECK(hipStreamSynchronize(s));
 
-  // kernel samples and spectrum (temporary n x n buffer)
-  double2* cfull = nullptr;
-  if (hipMalloc(&cfull, (size_t)n * n * sizeof(double2)) != hipSuccess) return AIM_E_OOM;
-  {
-    dim3 g((n + 255) / 256, n);
-    hipLaunchKernelGGL(k_sample_kernel, g, dim3(256), 0, s, m, n, t.eps, t.k, cfull);
-    c->ks = t.R + 4;
-    TRY(dev_alloc(c, (void**)&c->d_ksmall, (size_t)c->ks * c->ks * sizeof(double2)));
-    hipLaunchKernelGGL(k_small_table, dim3(c->ks), dim3(64 * ((c->ks + 63) / 64)), 0, s, m, n, c->ks, cfull,
-                       c->d_ksmall);
-    aim_status st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
-    if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
-    if (st != AIM_OK) { hipFree(cfull); return st; }
-    const int H = n / 2 + 1;
-    st = dev_alloc(c, (void**)&c->d_C, (size_t)H * H * sizeof(double2));
-    if (st == AIM_OK) st = dev_alloc(c, (void**)&c->d_Ca, (size_t)H * H * sizeof(double2));
-    if (st == AIM_OK && c->precision == AIM_MIXED) {
-      st = dev_alloc(c, (void**)&c->d_Cf, (size_t)H * H * sizeof(float2));
-      if (st == AIM_OK) st = dev_alloc(c, (void**)&c->d_Caf, (size_t)H * H * sizeof(float2));
-    }
-    if (st != AIM_OK) { hipFree(cfull); return st; }
-    hipLaunchKernelGGL(k_extract_quarter, dim3((H + 255) / 256, H), dim3(256), 0, s, n, cfull, c->d_C, c->d_Cf);
-    AIM_HIP_CHECK(hipStreamSynchronize(s));
-    hipFree(cfull);
-  }
+  // grid kernel at small offsets (near-field correction)
+  const double keps = t.k * t.eps;
+  c->ks = t.R + 4;
+  TRY(dev_alloc(c, (void**)&c->d_ksmall, (size_t)c->ks * c->ks * sizeof(double2)));
+  hipLaunchKernelGGL(k_small_table, dim3(c->ks), dim3(64 * ((c->ks + 63) / 64)), 0, s, c->ks, keps, c->d_ksmall);
+  // spectrum F(c_grid): shared through the process-wide cache
+  TRY(acquire_spectrum(c, keps));
   TRY(apply_filter(c, INFINITY));
 
   // near field
@@ -777,10 +882,21 @@ aim_status setup_device(Ctx* c) {
 aim_status apply_filter(Ctx* c, double alpha) {
   const int n = c->t.n, H = n / 2 + 1;
   const bool all = !std::isfinite(alpha);
-  const double thr = all ? 0.0 : ((alpha * n) * c->t.eps / (2.0 * kPi)) * ((alpha * n) * c->t.eps / (2.0 * kPi));
-  hipLaunchKernelGGL(k_filter, dim3((H + 255) / 256, H), dim3(256), 0, c->stream, n, thr, all, c->d_C, c->d_Ca,
-                     c->d_Caf);
-  AIM_HIP_CHECK(hipGetLastError());
+  if (all) {   // no truncation: the filtered operator uses the shared spectrum
+    c->d_Ca = c->d_C;
+    c->d_Caf = c->d_Cf;
+  } else {
+    if (!c->own_Ca) {
+      TRY(dev_alloc(c, (void**)&c->own_Ca, (size_t)H * H * sizeof(double2)));
+      if (c->precision == AIM_MIXED) TRY(dev_alloc(c, (void**)&c->own_Caf, (size_t)H * H * sizeof(float2)));
+    }
+    const double thr = ((alpha * n) * c->t.eps / (2.0 * kPi)) * ((alpha * n) * c->t.eps / (2.0 * kPi));
+    hipLaunchKernelGGL(k_filter, dim3((H + 255) / 256, H), dim3(256), 0, c->stream, n, thr, false, c->d_C,
+                       c->own_Ca, c->own_Caf);
+    AIM_HIP_CHECK(hipGetLastError());
+    c->d_Ca = c->own_Ca;
+    c->d_Caf = c->own_Caf;
+  }
   c->alpha = alpha;
   c->filtered = !all;
   return AIM_OK;

@@ -181,3 +181,54 @@ def grid_side_for(xy: np.ndarray, eps: float, margin_cells: int = 4) -> int:
     while m < need:
         m *= 2
     return m
+
+
+# --------------------------------------------------------------------------
+# serving stream: random star contours at random frequencies
+# --------------------------------------------------------------------------
+@dataclass
+class ServeRequest:
+    rid: int
+    arrival: float            # seconds after the stream starts
+    xy: np.ndarray
+    k: float
+    eta: float
+    m: int
+    eps: float
+    phis: np.ndarray          # incidence angles (one right-hand side each)
+    precision: int            # 0 FP64, 1 mixed
+    tol: float = 1e-6
+    basis: int = PULSE
+
+
+def serving_stream(n_req: int, rate: float, seed: int = 20261203, ka_range=(10.0, 400.0),
+                   pts_per_lambda: float = 20.0, eps_lambda: float = 0.1, max_rhs: int = 16):
+    """Poisson arrivals at `rate` per second of TM requests on seeded random
+    stars r = a(1 + sum_{m<=8} c_m cos(m theta + phi_m)), a = 1,
+    c_m ~ U(0, 0.05), ka ~ logU(ka_range), eps = eps_lambda * lambda (so
+    k eps is the same for every request), N = pts_per_lambda points per
+    wavelength of perimeter rounded up to a multiple of 256 (at least 1024),
+    1..max_rhs incidence angles ~ U[0, 2 pi), precision FP64 or mixed with
+    probability 1/2."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n_req):
+        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        ka = float(np.exp(rng.uniform(np.log(ka_range[0]), np.log(ka_range[1]))))
+        k = ka                      # a = 1
+        lam = 2.0 * np.pi / k
+        c = rng.uniform(0.0, 0.05, size=8)
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=8)
+        r, dr = _fourier_curve(1.0, c, ph)
+        tg = 2.0 * np.pi * np.arange(4096) / 4096
+        perim = float(np.mean(np.sqrt(r(tg) ** 2 + dr(tg) ** 2)) * 2.0 * np.pi)
+        n = int(max(1024, 256 * int(np.ceil(pts_per_lambda * perim / lam / 256.0))))
+        xy = equal_arc_polygon(r, dr, n)
+        eps = eps_lambda * lam
+        m = grid_side_for(xy, eps)
+        nr = int(rng.integers(1, max_rhs + 1))
+        phis = rng.uniform(0.0, 2.0 * np.pi, size=nr)
+        prec = int(rng.integers(0, 2))
+        out.append(ServeRequest(i, t, xy, k, ETA0, m, eps, phis, prec))
+    return out

@@ -1,0 +1,110 @@
+"""Continuous-batching server: admission logic on the CPU with a stand-in
+executor (never a product path), and on the GPU that each request's result
+is identical alone and inside a concurrent mix."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2606_10784_amd import serve
+from paper_2606_10784_amd import workloads as wl
+
+
+class FakeExecutor:
+    """Sleeps for a request-dependent time and tracks concurrency."""
+
+    def __init__(self, fps, durations):
+        self.fps = fps
+        self.dur = durations
+        self.lock = threading.Lock()
+        self.running = 0
+        self.peak = 0
+        self.log = []
+
+    def footprint(self, req):
+        return self.fps[req.rid]
+
+    def __call__(self, req, res):
+        with self.lock:
+            self.running += 1
+            self.peak = max(self.peak, self.running)
+            self.log.append(("start", req.rid, time.perf_counter()))
+        time.sleep(self.dur[req.rid])
+        with self.lock:
+            self.running -= 1
+        res.status = "ok"
+        res.nrhs = len(req.phis)
+        res.matvecs = 10
+
+
+def _reqs(arrivals):
+    return [wl.ServeRequest(i, a, np.zeros((8, 2)), 1.0, 1.0, 16, 0.1, np.zeros(2), 0)
+            for i, a in enumerate(arrivals)]
+
+
+def test_admission_respects_budget_slots_and_fifo():
+    reqs = _reqs([0.0, 0.001, 0.002, 0.003, 0.004, 0.005, 0.006])
+    fps = {0: 40, 1: 40, 2: 40, 3: 10, 4: 90, 5: 10, 6: 200}
+    dur = {i: 0.03 for i in fps}
+    exe = FakeExecutor(fps, dur)
+    srv = serve.Server(exe, hbm_budget=100, slots=3)
+    res = srv.run(reqs)
+    st = {r.rid: r.status for r in res}
+    assert st[6] == "rejected"                     # larger than the whole budget
+    assert all(st[i] == "ok" for i in range(6))
+    assert srv.max_reserved <= 100
+    assert exe.peak <= 3 and srv.max_active <= 3
+    # first come, first served: admission order follows arrival order
+    admits = [r.admit for r in res if r.status == "ok"]
+    assert admits == sorted(admits)
+    # request 2 (40) had to wait for 0 or 1 to release memory (budget 100)
+    r = {x.rid: x for x in res}
+    assert r[2].admit >= min(r[0].finish, r[1].finish) - 1e-3
+    s = serve.summarize(res, srv.wall)
+    assert s["completed"] == 6 and s["rejected"] == 1
+    assert s["latency_s"]["p50"] <= s["latency_s"]["p99"]
+
+
+def test_requests_arriving_while_busy_overlap():
+    reqs = _reqs([0.0, 0.01, 0.02, 0.03])
+    exe = FakeExecutor({i: 1 for i in range(4)}, {i: 0.1 for i in range(4)})
+    srv = serve.Server(exe, hbm_budget=10, slots=4)
+    res = srv.run(reqs)
+    assert exe.peak == 4                           # later arrivals joined running work
+    assert srv.wall < 0.35
+
+
+def test_failure_in_one_request_does_not_stop_the_loop():
+    class Boom(FakeExecutor):
+        def __call__(self, req, res):
+            if req.rid == 1:
+                raise RuntimeError("boom")
+            super().__call__(req, res)
+    reqs = _reqs([0.0, 0.0, 0.0])
+    exe = Boom({i: 1 for i in range(3)}, {i: 0.01 for i in range(3)})
+    res = serve.Server(exe, hbm_budget=10, slots=2).run(reqs)
+    assert [r.status.startswith("error") for r in res] == [False, True, False]
+
+
+@pytest.mark.gpu
+def test_result_identical_alone_and_in_mix():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    reqs = wl.serving_stream(4, rate=0.0, seed=7, ka_range=(10.0, 40.0), max_rhs=3)
+    exe = serve.GpuExecutor(restart=200, keep_solution=True)
+    alone = {}
+    for r in reqs:
+        out = serve.Server(exe, hbm_budget=64 << 30, slots=1).run([r])[0]
+        assert out.status == "ok", out.status
+        alone[r.rid] = out
+    srv = serve.Server(exe, hbm_budget=64 << 30, slots=4)
+    mix = srv.run(reqs)
+    assert srv.max_active >= 2
+    for out in mix:
+        assert out.status == "ok"
+        a = alone[out.rid]
+        assert np.array_equal(out.x, a.x), out.rid
+        assert np.array_equal(out.sigma, a.sigma)
+        assert out.resid <= 1.0000001 * reqs[out.rid].tol
