@@ -37,7 +37,47 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
+    ap.add_argument("--mode", default="solve", choices=["solve", "matvec"],
+                    help="matvec: set-up plus --matvecs FP64 matvecs only (short runs for counters)")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the serving stream (0: skip the serving measurement)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_cols_conv.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current source of the FFT kernels."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = os.path.join(os.path.dirname(TRAFFIC_FILE), "..", "paper_2606_10784_amd", "csrc", "fft.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except Exception:
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def serving(n_req, slots=4, budget=96 << 30):
+    """Closed-loop capacity of the continuous-batching server on the serving
+    stream, then Poisson arrivals at 0.7 of that capacity."""
+    from paper_2606_10784_amd import serve
+    from paper_2606_10784_amd import workloads as wl
+    exe = serve.GpuExecutor(restart=300)
+    reqs = wl.serving_stream(n_req, rate=0.0)
+    srv = serve.Server(exe, hbm_budget=budget, slots=slots)
+    cap = serve.summarize(srv.run(reqs, realtime=False), srv.wall)
+    rate = 0.7 * cap["requests_per_s"]
+    reqs = wl.serving_stream(n_req, rate=rate)
+    srv = serve.Server(exe, hbm_budget=budget, slots=slots)
+    out = serve.summarize(srv.run(reqs, realtime=True), srv.wall)
+    return {"stream": f"{n_req} TM requests, random stars ka~logU[10,400], 1-16 rhs, FP64/mixed, "
+                      f"{slots} slots, HBM budget {budget >> 30} GiB",
+            "closed_loop": cap, "poisson_rate_per_s": rate, "poisson": out}
 
 
 def kernel_bytes(kid, inf, nch=1, nrhs=1, b=16):
@@ -129,6 +169,21 @@ def main():
     b = ctx.rhs_planewave(0.0)
     print(f"[bench] setup {t_setup:.2f} s  N={inf['n_unknowns']} n={inf['n_pad']} active={inf['n_active']} "
           f"rows={inf['active_rows']} near={inf['near_nnz_s']}", file=sys.stderr, flush=True)
+    if args.mode == "matvec":
+        xprobe = torch.from_numpy(wl.probe_vector(w.n_unknowns, seed=3)).to(dev)
+        yprobe = torch.empty_like(xprobe)
+        for _ in range(args.matvecs):
+            ctx.matvec("TM", xprobe, yprobe)
+        if args.copy_calibration:
+            src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+            dst = torch.empty_like(src)
+            src.fill_(1.0)
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "matvec", "matvecs": args.matvecs, "workload": w.name,
+                          "alg_bytes_cols_conv": kernel_bytes(2, inf)}), flush=True)
+        ctx.close()
+        return
 
     # warm-up solves
     for i in range(args.warmup):
@@ -232,16 +287,19 @@ def main():
                         "speedup_vs_fp64": (t_total / args.steps) / t_mixed},
         "kernel_ms": {names[k]: v for k, v in ktimes.items()},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(names[dom]),
                      "alg_bytes_per_launch": alg_b, "avg_ms": dom_ms, "samples": dom_samples,
                      "flops_per_launch": kernel_flops(dom, inf)},
         "setup_s": t_setup,
     }
+    ctx.close()
+    if args.serve_requests > 0:
+        print("[bench] serving stream ...", file=sys.stderr, flush=True)
+        out["serving"] = serving(args.serve_requests)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

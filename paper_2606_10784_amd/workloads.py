@@ -211,10 +211,11 @@ def serving_stream(n_req: int, rate: float, seed: int = 20261203, ka_range=(10.0
     1..max_rhs incidence angles ~ U[0, 2 pi), precision FP64 or mixed with
     probability 1/2."""
     rng = np.random.default_rng(seed)
+    rng_arr = np.random.default_rng([seed, 1])    # arrivals drawn apart: same requests at any rate
     t = 0.0
     out = []
     for i in range(n_req):
-        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        t += rng_arr.exponential(1.0 / rate) if rate > 0 else 0.0
         ka = float(np.exp(rng.uniform(np.log(ka_range[0]), np.log(ka_range[1]))))
         k = ka                      # a = 1
         lam = 2.0 * np.pi / k
