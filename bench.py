@@ -30,7 +30,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cylinder_ka200",
-                    choices=["cylinder_ka200", "cylinder_ka2pi"])
+                    choices=["cylinder_ka200", "cylinder_ka2pi", "star_te", "cylinder_ka200_360rhs"],
+                    help="cylinder_ka200: the benchmark line; the others are separate measurements")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -140,6 +141,82 @@ def cpu_baseline(w, sample_every=64, reps=2):
                        f"{rows.size} of {w.n_unknowns} rows scaled to all rows; {per:.2f} s per matvec")}
 
 
+def star_te(args):
+    """Star N = 65536 hats, grid 2048 -> 4096: Calderon-preconditioned TE
+    solves with the filtered S^alpha and with the accurate S, FP64 and mixed."""
+    import torch
+    from paper_2606_10784_amd import aim
+    from paper_2606_10784_amd import workloads as wl
+    w = wl.star_large()
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1)
+    ctx.filter(w.alpha)
+    inf = ctx.info()
+    b = ctx.rhs_planewave(0.0)
+    out = {"workload": w.name, "N": inf["n_unknowns"], "grid": f"{w.m}x{w.m} pad {inf['n_pad']}",
+           "near_nnz": inf["near_nnz_s"], "alpha": w.alpha, "solves": {}}
+    x = torch.zeros_like(b)
+    for lab, op in (("N", "N"), ("S_ALPHA", "S_ALPHA"), ("TE_CP", "TE_CP"), ("TE_CP_UNF", "TE_CP_UNF")):
+        for prec in (0, aim.AIM_OP_GRID_FP32):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            y = ctx.matvec(aim.OPS[op] | prec, b)
+            e0.record()
+            for _ in range(10):
+                ctx.matvec(aim.OPS[op] | prec, b, y)
+            e1.record()
+            torch.cuda.synchronize()
+            out.setdefault("matvec_ms", {})[lab + ("_fp32grid" if prec else "")] = e0.elapsed_time(e1) / 10
+    for form in ("TE_CP", "TE_CP_UNF"):
+        for prec in (aim.AIM_FP64, aim.AIM_MIXED):
+            t0 = time.perf_counter()
+            x, info = ctx.solve(form, b, tol=args.tol, restart=300, maxit=3000, precision=prec)
+            dt = time.perf_counter() - t0
+            out["solves"][f"{form}_{'fp64' if prec == 0 else 'mixed'}"] = {
+                "seconds": dt, "iterations": info[0]["iterations"], "outer": info[0]["outer"],
+                "converged": info[0]["converged"], "resid_true": info[0]["resid_true"]}
+            print(f"[bench] {form} prec={prec} its={info[0]['iterations']} {dt:.2f}s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def batched_360(args):
+    """Cylinder ka = 200 with 360 plane waves (1 degree steps) in one batched
+    solve: FP64 and FP32-grid + FP64 refinement, monostatic RCS."""
+    import numpy as np
+    import torch
+    from oracle import mie
+    from paper_2606_10784_amd import aim
+    from paper_2606_10784_amd import workloads as wl
+    w = wl.cylinder_large()
+    R = 360
+    phis = np.deg2rad(np.arange(R))
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=R)
+    B = ctx.rhs_planewave(phis)
+    out = {"workload": w.name + "_360rhs", "nrhs": R, "solves": {}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for prec, lab in ((0, "fp64"), (aim.AIM_OP_GRID_FP32, "fp32grid")):
+        Y = ctx.matvec(aim.AIM_OP_TM | prec, B)
+        e0.record()
+        for _ in range(3):
+            ctx.matvec(aim.AIM_OP_TM | prec, B, Y)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"batched_matvec_ms_{lab}"] = e0.elapsed_time(e1) / 3
+    for prec, lab in ((aim.AIM_FP64, "fp64"), (aim.AIM_MIXED, "mixed")):
+        t0 = time.perf_counter()
+        X, infos = ctx.solve("TM", B, tol=args.tol, restart=args.restart, precision=prec)
+        dt = time.perf_counter() - t0
+        sig = ctx.rcs(X, phis)
+        ex = mie.mie_tm_backscatter(w.k, 200.0 / w.k)
+        out["solves"][lab] = {"seconds": dt, "rhs_solves_per_s": R / dt,
+                              "iterations_max": max(d["iterations"] for d in infos),
+                              "converged": sum(d["converged"] for d in infos),
+                              "resid_true_max": max(d["resid_true"] for d in infos),
+                              "rcs_min": float(sig.min()), "rcs_max": float(sig.max()), "rcs_mie": ex}
+        print(f"[bench] 360 rhs {lab}: {dt:.2f}s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -155,6 +232,10 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "star_te":
+        return star_te(args)
+    if args.workload == "cylinder_ka200_360rhs":
+        return batched_360(args)
     w = wl.cylinder_large() if args.workload == "cylinder_ka200" else wl.cylinder_small()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -1,0 +1,117 @@
+"""Parity at the full workload sizes, on sampled output rows the oracle
+evaluates one by one (direct Toeplitz sums over all active grid points plus
+the near-field rows built for the sample), and size-independent properties
+of the solves.
+
+  * cylinder ka = 200, N = 16384 pulses, grid 1024 -> 2048 at lambda/15
+    (the benchmark's configuration and launch path)
+  * star r = 20 (1 + 0.3 cos 5 theta), N = 65536 hats, grid 2048 -> 4096 at
+    lambda/30 (S, S^alpha and the three-channel N)
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import aim as oaim
+from oracle import mie
+from paper_2606_10784_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2606_10784_amd import aim  # noqa: E402
+
+
+def _rows(N, count, seed):
+    rng = np.random.default_rng(seed)
+    # both ends, a ragged stride and random rows
+    base = [0, 1, N // 2, N - 2, N - 1]
+    base += list(range(7, N, N // 11))
+    base += list(rng.integers(0, N, size=count))
+    return np.unique(np.array(base))
+
+
+@pytest.fixture(scope="module")
+def cyl200():
+    w = wl.cylinder_large()
+    rows = _rows(w.n_unknowns, 24, 5)
+    orc = oaim.AimOracle(w.xy, w.k, w.eta, 0, w.m, w.eps, alpha=w.alpha, near_rows=rows)
+    ctx = aim.Context(w.xy, w.k, w.eta, 0, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=8)
+    ctx.filter(w.alpha)
+    return w, rows, orc, ctx
+
+
+@pytest.mark.parametrize("op", ["S", "S_ALPHA"])
+def test_cylinder_ka200_matvec_rows(cyl200, op):
+    w, rows, orc, ctx = cyl200
+    x = wl.probe_vector(w.n_unknowns, seed=31)
+    y = ctx.matvec(op, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = orc.rows_apply(op, x, rows)
+    err = np.max(np.abs(y[rows] - ref)) / np.max(np.abs(ref))
+    print(op, "ka=200 sampled rows", rows.size, "rel err", err)
+    assert err < 1e-12
+    yf = ctx.matvec(aim.OPS[op] | aim.AIM_OP_GRID_FP32, torch.from_numpy(x).cuda()).cpu().numpy()
+    errf = np.max(np.abs(yf[rows] - ref)) / np.max(np.abs(ref))
+    print(op, "fp32 grid rel err", errf)
+    assert errf < 1e-5
+
+
+def test_cylinder_ka200_multi_rhs_columns(cyl200):
+    w, rows, orc, ctx = cyl200
+    X = torch.from_numpy(np.ascontiguousarray(wl.probe_vector(w.n_unknowns, nrhs=8, seed=32).T)).cuda()
+    Y = ctx.matvec("TM", X)
+    for r in (0, 5, 7):
+        assert torch.equal(Y[r], ctx.matvec("TM", X[r].contiguous()))
+
+
+def test_cylinder_ka200_solve_and_backscatter(cyl200):
+    """FP64 GMRES at the benchmark settings: residual with the FP64 operator
+    (shown above to match the oracle) and the Mie backscatter width."""
+    w, rows, orc, ctx = cyl200
+    b = ctx.rhs_planewave(0.0)
+    x, info = ctx.solve("TM", b, tol=1e-6, restart=400)
+    assert info[0]["converged"] == 1
+    r = b - ctx.matvec("TM", x)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1.0000001e-6
+    sig = ctx.rcs(x.reshape(1, -1).contiguous(), [0.0])[0]
+    ex = mie.mie_tm_backscatter(w.k, 200.0 / w.k)
+    print("ka=200 sigma", sig, "mie", ex, "iters", info[0]["iterations"])
+    assert abs(sig - ex) / ex < 2e-2
+
+
+@pytest.fixture(scope="module")
+def star65k():
+    w = wl.star_large()
+    rows = _rows(w.n_unknowns, 12, 6)
+    orc = oaim.AimOracle(w.xy, w.k, w.eta, 1, w.m, w.eps, alpha=w.alpha, near_rows=rows)
+    ctx = aim.Context(w.xy, w.k, w.eta, 1, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1)
+    ctx.filter(w.alpha)
+    return w, rows, orc, ctx
+
+
+@pytest.mark.parametrize("op", ["S_ALPHA", "S", "N"])
+def test_star_65536_matvec_rows(star65k, op):
+    w, rows, orc, ctx = star65k
+    x = wl.probe_vector(w.n_unknowns, seed=41)
+    y = ctx.matvec(op, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = orc.rows_apply(op, x, rows)
+    err = np.max(np.abs(y[rows] - ref)) / np.max(np.abs(ref))
+    print(op, "star N=65536 sampled rows", rows.size, "rel err", err)
+    assert err < 1e-12
+    yf = ctx.matvec(aim.OPS[op] | aim.AIM_OP_GRID_FP32, torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.max(np.abs(yf[rows] - ref)) / np.max(np.abs(ref)) < 1e-5
+
+
+def test_star_65536_gram_inverse_property(star65k):
+    """G^-1 at N = 65536 (block solver with halo): G (G^-1 x) = x."""
+    w, rows, orc, ctx = star65k
+    x = wl.probe_vector(w.n_unknowns, seed=42)
+    z = ctx.matvec("GRAM_INV", torch.from_numpy(x).cuda()).cpu().numpy()
+    from oracle.geometry import segments
+    _, _, h, _, _ = segments(w.xy)
+    Gz = (np.roll(h, 1) + h) / 3 * z + np.roll(h, 1) / 6 * np.roll(z, 1) + h / 6 * np.roll(z, -1)
+    assert np.max(np.abs(Gz - x)) < 1e-12 * np.max(np.abs(x))
