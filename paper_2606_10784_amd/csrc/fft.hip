@@ -14,9 +14,14 @@
 // [0, nr) changes nothing.  The 1/n^2 of the inverse DFT is folded into the
 // stored spectrum.
 //
-// Each FFT is an in-LDS Stockham autosort with radix-8 passes (radix 4 or 2
-// for the last one); each thread holds its butterflies in registers across a
-// barrier, so a single LDS buffer suffices.
+// Each FFT is an in-LDS Stockham autosort with radix-16 passes (radix 8, 4
+// or 2 for the remainder); each thread holds its butterflies in registers
+// across a barrier, so a single LDS buffer suffices.  In the column pass the
+// first forward pass reads the tile from HBM straight into registers (its
+// upper half is the zero padding), the last forward pass, the spectrum
+// multiply and the first inverse pass share one register round (the inverse
+// runs its radices in reverse order so the butterflies line up), and the last
+// inverse pass stores only the kept rows straight to HBM.
 #include "aim_internal.h"
 
 namespace aim {
@@ -118,6 +123,70 @@ __device__ __forceinline__ void dft16(cplx<T>* v) {
   t = v[11]; v[11] = v[14]; v[14] = t;
 }
 
+// 16-point DFT whose inputs 8..15 are zero: even and odd outputs are two
+// 8-point DFTs of v and of v[r] W16^r.
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16_halfin(cplx<T>* v) {
+  using V = cplx<T>;
+  const T c1 = (T)0.92387953251128675612818318939678829, s1 = (T)0.38268343236508977172845998403039887;
+  const T c2 = (T)0.70710678118654752440084436210484903;
+  auto tw = [&](V a, T c, T sn) -> V {   // a * (c - i sn) forward, a * (c + i sn) inverse
+    V r;
+    if (!INV) { r.x = a.x * c + a.y * sn; r.y = a.y * c - a.x * sn; }
+    else { r.x = a.x * c - a.y * sn; r.y = a.y * c + a.x * sn; }
+    return r;
+  };
+  V a[8], o[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) a[r] = v[r];
+  o[0] = v[0];
+  o[1] = tw(v[1], c1, s1);
+  o[2] = tw(v[2], c2, c2);
+  o[3] = tw(v[3], s1, c1);
+  o[4] = rot_mi<V, INV>(v[4]);
+  o[5] = tw(v[5], -s1, c1);
+  o[6] = tw(v[6], -c2, c2);
+  o[7] = tw(v[7], -c1, s1);
+  dft8<T, INV>(a);
+  dft8<T, INV>(o);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[2 * k] = a[k];
+    v[2 * k + 1] = o[k];
+  }
+}
+
+// outputs 0..7 of a 16-point DFT: X[k] = E[k] + W16^k O[k] with E, O the
+// 8-point DFTs of the even and odd inputs; result in v[0..7].
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16_halfout(cplx<T>* v) {
+  using V = cplx<T>;
+  const T c1 = (T)0.92387953251128675612818318939678829, s1 = (T)0.38268343236508977172845998403039887;
+  const T c2 = (T)0.70710678118654752440084436210484903;
+  auto tw = [&](V a, T c, T sn) -> V {
+    V r;
+    if (!INV) { r.x = a.x * c + a.y * sn; r.y = a.y * c - a.x * sn; }
+    else { r.x = a.x * c - a.y * sn; r.y = a.y * c + a.x * sn; }
+    return r;
+  };
+  V e[8], o[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    e[r] = v[2 * r];
+    o[r] = v[2 * r + 1];
+  }
+  dft8<T, INV>(e);
+  dft8<T, INV>(o);
+  v[0] = cadd(e[0], o[0]);
+  v[1] = cadd(e[1], tw(o[1], c1, s1));
+  v[2] = cadd(e[2], tw(o[2], c2, c2));
+  v[3] = cadd(e[3], tw(o[3], s1, c1));
+  v[4] = cadd(e[4], rot_mi<V, INV>(o[4]));
+  v[5] = cadd(e[5], tw(o[5], -s1, c1));
+  v[6] = cadd(e[6], tw(o[6], -c2, c2));
+  v[7] = cadd(e[7], tw(o[7], -c1, s1));
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_r(cplx<T>* v) {
   if constexpr (R == 16) dft16<T, INV>(v);
@@ -159,8 +228,34 @@ __device__ __forceinline__ void tw_powers(V w1, V* wp) {
   }
 }
 
+// Twiddles of butterfly j of a Stockham pass (sub-transform length NS):
+// input r is multiplied by w^(k r), w = e^{-2 pi i/(NS R)}, k = j mod NS.
+template <typename T, int N, bool INV, int NS, int R>
+__device__ __forceinline__ void pass_twiddle(cplx<T>* v, int j, const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
+  if constexpr (NS > 1) {
+    const int k = j & (NS - 1);
+#if AIM_TW_RECUR
+    V w1 = tw[k * (N / (NS * R))];
+    if (INV) w1.y = -w1.y;
+    V wp[R];
+    tw_powers<V, R>(w1, wp);
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], wp[r]);
+#else
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      V w = tw[k * r * (N / (NS * R))];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+#endif
+  }
+}
+
 // One Stockham pass: sub-transform length NS -> NS*R.  Element i of column c
-// lives at buf[pidx(i * NCOL + c)].
+// lives at buf[pidx(i * NCOL + c)]; butterfly b = j * NCOL + c reads elements
+// j + r N/R and writes (j - k) R + k + r NS, k = j mod NS.
 template <typename T, int N, int NCOL, int NT, bool INV, int NS, int R>
 __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
@@ -175,24 +270,7 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __res
       const int c = b % NCOL, j = b / NCOL;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = buf[pidx((j + r * (N / R)) * NCOL + c)];
-      if constexpr (NS > 1) {
-        const int k = j & (NS - 1);
-#if AIM_TW_RECUR
-        V w1 = tw[k * (N / (NS * R))];
-        if (INV) w1.y = -w1.y;
-        V wp[R];
-        tw_powers<V, R>(w1, wp);
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wp[r]);
-#else
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          V w = tw[k * r * (N / (NS * R))];
-          if (INV) w.y = -w.y;
-          v[q][r] = cmul(v[q][r], w);
-        }
-#endif
-      }
+      pass_twiddle<T, N, INV, NS, R>(v[q], j, tw);
       dft_r<T, R, INV>(v[q]);
     }
   }
@@ -219,6 +297,21 @@ __device__ __forceinline__ void fft_passes(cplx<T>* buf, const cplx<T>* __restri
     stockham_pass<T, N, NCOL, NT, INV, NS, R>(buf, tw);
     fft_passes<T, N, NCOL, NT, INV, NS * R>(buf, tw);
   }
+}
+
+// radix-16 passes with sub-transform lengths NS, 16 NS, ... below NSEND
+template <typename T, int N, int NCOL, int NT, bool INV, int NS, int NSEND>
+__device__ __forceinline__ void passes16(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+  if constexpr (NS < NSEND) {
+    stockham_pass<T, N, NCOL, NT, INV, NS, 16>(buf, tw);
+    passes16<T, N, NCOL, NT, INV, NS * 16, NSEND>(buf, tw);
+  }
+}
+
+// radix of the remainder pass: N = 16^p * last_radix(N), last_radix in 2..16
+template <int N> constexpr int last_radix() {
+  if constexpr (N <= 16) return N;
+  else return last_radix<N / 16>();
 }
 
 // ---------------------------------------------------------------------------
@@ -276,57 +369,117 @@ __device__ __forceinline__ int xcd_row(int bid, int nrows) {
 template <int N> constexpr int row_threads() { return N / 16 < 64 ? 64 : (N / 16 > 256 ? 256 : N / 16); }
 
 // Pass 1: gather active values of a row into a zeroed LDS row, FFT along x.
+// Active points have x < N/2, so only that half is cleared and the first pass
+// reads inputs 0..7 of its radix-16 butterflies.
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     const cplx<T>* __restrict__ U, int n_act, const int32_t* __restrict__ row_ptr,
     const int32_t* __restrict__ act_ix, int nr, cplx<T>* __restrict__ Tb,
     const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
+  static_assert(N >= 32, "row pass assumes at least two forward passes");
   constexpr int NT = row_threads<N>();
   constexpr int CB = ColCfg<T, N>::CB;
   constexpr int NBLK = N / CB;
-  __shared__ cplx<T> buf[padded(N)];
+  __shared__ V buf[padded(N)];
   const int row = xcd_row(blockIdx.x, nr), pair = blockIdx.y;
+  const int tid = threadIdx.x;
   if (row >= nr) return;
-  for (int i = threadIdx.x; i < N; i += NT) buf[pidx(i)] = mk<T>(0, 0);
+  for (int i = tid; i < N / 2; i += NT) buf[pidx(i)] = mk<T>(0, 0);
   __syncthreads();
   const int a0 = row_ptr[row], a1 = row_ptr[row + 1];
-  const cplx<T>* Up = U + (size_t)pair * n_act;
-  for (int a = a0 + threadIdx.x; a < a1; a += NT) buf[pidx(act_ix[a])] = Up[a];
+  const V* Up = U + (size_t)pair * n_act;
+  for (int a = a0 + tid; a < a1; a += NT) buf[pidx(act_ix[a])] = Up[a];
   __syncthreads();
-  fft_passes<T, N, 1, NT, false, 1>(buf, tw);
-  cplx<T>* out = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
-  for (int idx = threadIdx.x; idx < N; idx += NT) {
-    const int b = idx / CB, c = idx % CB;
+  {
+    constexpr int NB = N / 16, PER = (NB + NT - 1) / NT;
+    V v[PER][16];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[q][r] = buf[pidx(j + r * (N / 16))];
+        dft16_halfin<T, false>(v[q]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[pidx(j * 16 + r)] = v[q][r];
+      }
+    }
+    __syncthreads();
+  }
+  fft_passes<T, N, 1, NT, false, 16>(buf, tw);
+  // pairs of lanes fill the CB-wide segments of the tiled layout
+  V* out = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  for (int idx = tid; idx < N; idx += NT) {
+    const int bk = idx / CB, c = idx % CB;
     int kx, kxq;
-    col_of(b, c, N, CB, kx, kxq);
-    out[(size_t)b * nr * CB + c] = buf[pidx(kx)];
+    col_of(bk, c, N, CB, kx, kxq);
+    out[(size_t)bk * nr * CB + c] = buf[pidx(kx)];
   }
 }
 
-// Pass 3: inverse FFT along x, gather the active points of the row.
+// Pass 3: inverse FFT along x, gather the active points of the row.  The
+// inverse runs its radices in reverse order so that the last pass is radix 16
+// and computes only the outputs x < N/2, where the active points lie.
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
     const cplx<T>* __restrict__ Tb, int nr, const int32_t* __restrict__ row_ptr,
     const int32_t* __restrict__ act_ix, cplx<T>* __restrict__ Vout, int n_act,
     const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
+  static_assert(N >= 32, "row pass assumes at least two inverse passes");
   constexpr int NT = row_threads<N>();
   constexpr int CB = ColCfg<T, N>::CB;
   constexpr int NBLK = N / CB;
-  __shared__ cplx<T> buf[padded(N)];
+  constexpr int RL = last_radix<N>();
+  __shared__ V buf[padded(N)];
   const int row = xcd_row(blockIdx.x, nr), pair = blockIdx.y;
+  const int tid = threadIdx.x;
   if (row >= nr) return;
-  const cplx<T>* in = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
-  for (int idx = threadIdx.x; idx < N; idx += NT) {
-    const int b = idx / CB, c = idx % CB;
+  const V* in = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  for (int idx = tid; idx < N; idx += NT) {
+    const int bk = idx / CB, c = idx % CB;
     int kx, kxq;
-    col_of(b, c, N, CB, kx, kxq);
-    buf[pidx(kx)] = in[(size_t)b * nr * CB + c];
+    col_of(bk, c, N, CB, kx, kxq);
+    buf[pidx(kx)] = in[(size_t)bk * nr * CB + c];
   }
   __syncthreads();
-  fft_passes<T, N, 1, NT, true, 1>(buf, tw);
+  stockham_pass<T, N, 1, NT, true, 1, RL>(buf, tw);
+  passes16<T, N, 1, NT, true, RL, N / 16>(buf, tw);
+  {
+    constexpr int NS = N / 16, NB = NS, PER = (NB + NT - 1) / NT;
+    V v[PER][16];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[q][r] = buf[pidx(j + r * NS)];
+        pass_twiddle<T, N, true, NS, 16>(v[q], j, tw);
+        dft16_halfout<T, true>(v[q]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = tid + q * NT;
+      if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) buf[pidx(j + r * NS)] = v[q][r];
+      }
+    }
+    __syncthreads();
+  }
   const int a0 = row_ptr[row], a1 = row_ptr[row + 1];
-  cplx<T>* Vp = Vout + (size_t)pair * n_act;
-  for (int a = a0 + threadIdx.x; a < a1; a += NT) Vp[a] = buf[pidx(act_ix[a])];
+  V* Vp = Vout + (size_t)pair * n_act;
+  for (int a = a0 + tid; a < a1; a += NT) Vp[a] = buf[pidx(act_ix[a])];
 }
 
 // Set-up: in-place forward FFT of full rows of length N (row-major array).
@@ -343,47 +496,129 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 }
 
 // Pass 2 (MODE 0): column FFT, spectrum multiply, inverse column FFT, in
-// place on one tile [row][CB] of T.  Cq: quarter spectrum [kxq][kyq].
+// place on one tile [row][CB] of T (nr <= N/2 rows kept, the rest is the
+// zero padding).  Cq: quarter spectrum [kxq][kyq].
 // MODE 1 (set-up): plain forward FFT of CB consecutive columns of a
 // row-major N x N array.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
     cplx<T>* __restrict__ Tb, int nr, const cplx<T>* __restrict__ Cq,
     const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
   constexpr int CB = ColCfg<T, N>::CB;
   constexpr int NT = ColCfg<T, N>::NT;
   constexpr int H = N / 2 + 1;
   constexpr int NBLK = N / CB;
-  __shared__ cplx<T> buf[padded(N * CB)];
+  __shared__ V buf[padded(N * CB)];
   const int b = blockIdx.x;
   const int pair = blockIdx.y;
+  const int tid = threadIdx.x;
   if constexpr (MODE == 0) {
-    cplx<T>* tile = Tb + ((size_t)pair * NBLK + b) * nr * CB;
-    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
-      const int i = idx / CB;
-      buf[pidx(idx)] = (i < nr) ? tile[idx] : mk<T>(0, 0);
+    static_assert(N >= 32, "column pass assumes at least two forward passes");
+    constexpr int RL = last_radix<N>();
+    V* tile = Tb + ((size_t)pair * NBLK + b) * nr * CB;
+    // forward pass 1 (NS = 1, radix 16) from HBM: inputs j + r N/16 with
+    // r >= 8 lie in the zero half
+    {
+      constexpr int NB = (N / 16) * CB, PER = (NB + NT - 1) / NT;
+      V v[PER][16];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB % NT) == 0 || bb < NB) {
+          const int c = bb % CB, j = bb / CB;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int i = j + r * (N / 16);
+            v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB % NT) == 0 || bb < NB) {
+          const int c = bb % CB, j = bb / CB;
+          dft16_halfin<T, false>(v[q]);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) buf[pidx((j * 16 + r) * CB + c)] = v[q][r];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    fft_passes<T, N, CB, NT, false, 1>(buf, tw);
-    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
-      const int ky = idx / CB, c = idx % CB;
-      int kx, kxq;
-      col_of(b, c, N, CB, kx, kxq);
-      const int kyq = ky <= N / 2 ? ky : N - ky;
-      buf[pidx(idx)] = cmul(buf[pidx(idx)], Cq[(size_t)kxq * H + kyq]);
+    passes16<T, N, CB, NT, false, 16, N / RL>(buf, tw);
+    // last forward pass (NS = N/RL) leaves butterfly j holding ky = j + r N/RL,
+    // exactly the inputs of the first inverse pass (NS = 1, radix RL)
+    {
+      constexpr int R = RL, NS = N / RL, NB = NS * CB, PER = (NB + NT - 1) / NT;
+      V v[PER][R];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB % NT) == 0 || bb < NB) {
+          const int c = bb % CB, j = bb / CB;
+          int kx, kxq;
+          col_of(b, c, N, CB, kx, kxq);
+          const V* Cp = Cq + (size_t)kxq * H;
+          V cv[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int ky = j + r * NS;
+            cv[r] = Cp[ky <= N / 2 ? ky : N - ky];
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[q][r] = buf[pidx((j + r * NS) * CB + c)];
+          pass_twiddle<T, N, false, NS, R>(v[q], j, tw);
+          dft_r<T, R, false>(v[q]);
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[q][r] = cmul(v[q][r], cv[r]);
+          dft_r<T, R, true>(v[q]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB % NT) == 0 || bb < NB) {
+          const int c = bb % CB, j = bb / CB;
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[pidx((j * R + r) * CB + c)] = v[q][r];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    fft_passes<T, N, CB, NT, true, 1>(buf, tw);
-    for (int idx = threadIdx.x; idx < nr * CB; idx += NT) tile[idx] = buf[pidx(idx)];
+    passes16<T, N, CB, NT, true, RL, N / 16>(buf, tw);
+    // last inverse pass (NS = N/16, radix 16) straight to HBM: outputs
+    // j + r N/16, only r < 8 can be a kept row
+    {
+      constexpr int NS = N / 16, NB = NS * CB, PER = (NB + NT - 1) / NT;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB % NT) == 0 || bb < NB) {
+          const int c = bb % CB, j = bb / CB;
+          V v[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) v[r] = buf[pidx((j + r * NS) * CB + c)];
+          pass_twiddle<T, N, true, NS, 16>(v, j, tw);
+          dft16_halfout<T, true>(v);
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int i = j + r * NS;
+            if (i < nr) tile[(size_t)i * CB + c] = v[r];
+          }
+        }
+      }
+    }
   } else {
     const int kx0 = b * CB;
-    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+    for (int idx = tid; idx < N * CB; idx += NT) {
       const int i = idx / CB, c = idx % CB;
       buf[pidx(idx)] = Tb[(size_t)i * N + kx0 + c];
     }
     __syncthreads();
     fft_passes<T, N, CB, NT, false, 1>(buf, tw);
-    for (int idx = threadIdx.x; idx < N * CB; idx += NT) {
+    for (int idx = tid; idx < N * CB; idx += NT) {
       const int i = idx / CB, c = idx % CB;
       Tb[(size_t)i * N + kx0 + c] = buf[pidx(idx)];
     }
@@ -434,6 +669,7 @@ aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_
 template <typename T>
 aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int pairs, const cplx<T>* Cq,
                        const cplx<T>* tw, hipStream_t s) {
+  if (mode == 0 && (nr < 1 || nr > n / 2)) return AIM_E_ARG;   // kept rows lie in the unpadded half
   switch (n) {
 #define CASE(NN)                                                                          \
   case NN: {                                                                              \
