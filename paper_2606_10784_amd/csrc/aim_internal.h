@@ -77,16 +77,21 @@ struct DevBuf {
 
 struct GmresWork {
   int restart = 0, nrhs = 0;
-  double2 *V = nullptr, *W = nullptr, *H = nullptr, *g = nullptr, *cs = nullptr, *sn = nullptr,
-          *y = nullptr, *hcol = nullptr, *part = nullptr, *r = nullptr, *x64 = nullptr, *d = nullptr,
-          *b2 = nullptr, *nrm = nullptr;
-  double *bnorm = nullptr, *resid = nullptr, *hn = nullptr, *npart = nullptr, *w0part = nullptr;
-  int *active = nullptr, *reorth = nullptr;
+  // V: restart + 1 basis slots per rhs; H: Hessenberg (rotated in place by the
+  // Givens kernel); Hu: the same columns unrotated, row-major ldh x ldh;
+  // hp: two provisional columns per rhs; coef: s, z, d, 1/gamma of the last
+  // step (delayed orthogonalisation)
+  double2 *V = nullptr, *W = nullptr, *H = nullptr, *Hu = nullptr, *hp = nullptr, *coef = nullptr, *g = nullptr,
+          *cs = nullptr,
+          *sn = nullptr, *y = nullptr, *part = nullptr, *r = nullptr, *d = nullptr, *b2 = nullptr, *nrm = nullptr;
+  double *resid = nullptr, *npart = nullptr;
+  int* active = nullptr;
   double* host_resid = nullptr;   // pinned
   int* pin = nullptr;             // pinned mask staging
   int nchunk = 0;
   size_t bytes = 0;
 };
+void free_gmres_work(GmresWork& w);
 
 struct Ctx {
   HostTables t;

@@ -19,14 +19,7 @@ void free_ctx(Ctx* c) {
   release_spectrum(c);
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
-  GmresWork& w = c->gw;
-  for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
-                  (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
-                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.w0part, (void*)w.reorth, (void*)w.active})
-    if (p) hipFree(p);
-  if (w.host_resid) hipHostFree(w.host_resid);
-  if (w.pin) hipHostFree(w.pin);
-  w = GmresWork();
+  free_gmres_work(c->gw);
 }
 
 size_t footprint(const aim_params* p, int restart, const HostTables* t) {

@@ -1,13 +1,28 @@
 // Restarted GMRES on the device for the AIM systems (FP64 Krylov space).
 //
 // The paper applies its operators inside iterative solvers (abstract, Sec. I)
-// without naming one; this is GMRES(restart) with classical Gram-Schmidt run
-// twice (CGS2) and complex Givens rotations, one independent Krylov space per
-// right-hand side.  Each Arnoldi step is one batched operator application
-// plus a handful of small kernels; the only per-step device-to-host transfer
-// is the residual estimate (8 bytes per right-hand side).  Reductions use a
-// fixed chunking and order, so results do not depend on which other
-// right-hand sides share the batch.
+// without naming one; this is GMRES(restart) with complex Givens rotations,
+// one independent Krylov space per right-hand side.  Orthogonalisation is
+// classical Gram-Schmidt applied twice, with the second pass delayed by one
+// step (the low-synchronisation "DCGS2" Arnoldi): step j runs one operator
+// application, one reduction pass over the basis and one update pass, and the
+// Hessenberg column of step j becomes final in step j + 1.  The only per-step
+// device-to-host transfer is the residual estimate (8 bytes per right-hand
+// side, every few steps).  Reductions use a fixed chunking and order, so
+// results do not depend on which other right-hand sides share the batch.
+//
+// Delayed step j.  At its start Q_j = [q_0 .. q_{j-1}] is orthonormal, slot j
+// holds u_j with A q_{j-1} = Q_j h + u_j (h: provisional column j-1), and
+// w = A u_j has just been formed.  One pass gives s = Q_j^H u_j, alpha = |u_j|^2,
+// z = Q_j^H w, zeta = u_j^H w.  Then
+//   gamma = |u_j - Q_j s| = sqrt(alpha - |s|^2),  q_j = (u_j - Q_j s)/gamma,
+//   column j-1 final: H[0:j, j-1] = h + s, H[j, j-1] = gamma,
+//   d = q_j^H w = (zeta - s^H z)/gamma,  t = (z, d) = Q_{j+1}^H w,
+//   A q_j = (w - A Q_j s)/gamma with A Q_j s = Q_{j+1} H s, hence
+//   provisional column j: (t - H s)/gamma, and
+//   u_{j+1} = (w - Q_{j+1} t)/gamma = (w - Q_j (z - e s) - e u_j)/gamma, e = d/gamma,
+// so every basis vector is projected twice: once as u_{j+1} and once more in
+// step j + 1 (s).  The second update pass writes q_j and u_{j+1} together.
 //
 // AIM_MIXED: iterative refinement  x <- x + d,  A_mixed d ~ b - A_64 x, where
 // A_mixed runs the grid part in complex FP32 and everything else in FP64.
@@ -22,65 +37,278 @@ static constexpr int RED_CHUNK = 2048;
 // Arnoldi steps enqueued between two host reads of the residual estimates
 static constexpr int kCheckEvery = 8;
 
-// partial sums of conj(V_i) . w over a chunk, or |w|^2 when V == nullptr.
-// skip (optional): right-hand sides whose flag is 0 do nothing.  w0part
-// (optional): blocks with i == 0 also leave the partial |w|^2 of the chunk.
-__global__ __launch_bounds__(256) void k_dots(int N, const double2* __restrict__ V, int64_t ld_rhs_v,
-                                              const double2* __restrict__ w, int64_t ld_w,
-                                              const int* __restrict__ active, double2* __restrict__ part,
-                                              int nchunk, int jmax, const int* __restrict__ skip = nullptr,
-                                              double* __restrict__ w0part = nullptr) {
-  const int chunk = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
-  if (!active[r] || (skip && !skip[r])) return;
-  const double2* vi = V ? V + (size_t)r * ld_rhs_v + (size_t)i * N : nullptr;
+// sum over a 256-thread block, same value in every thread, fixed order
+// (butterfly within each wave, then the four waves in order).  red: 4*K doubles.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();   // red may still be read from a previous call
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wv * K + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = ((red[k] + red[K + k]) + red[2 * K + k]) + red[3 * K + k];
+}
+
+// partial |w|^2 over a chunk of rows
+__global__ __launch_bounds__(256) void k_sqnorm(int N, const double2* __restrict__ w, int64_t ld_w,
+                                                const int* __restrict__ active, double* __restrict__ part,
+                                                int nchunk) {
+  __shared__ double red[4];
+  const int chunk = blockIdx.x, r = blockIdx.y;
+  if (!active[r]) return;
   const double2* wr = w + (size_t)r * ld_w;
-  const bool wn = w0part && i == 0;
-  double sx = 0, sy = 0, sw = 0;
+  double v[1] = {0.0};
   const int n0 = chunk * RED_CHUNK, n1 = min(N, n0 + RED_CHUNK);
   for (int n = n0 + threadIdx.x; n < n1; n += 256) {
     const double2 b = wr[n];
-    if (vi) {
-      const double2 a = vi[n];
-      sx += a.x * b.x + a.y * b.y;
-      sy += a.x * b.y - a.y * b.x;
-      if (wn) sw += b.x * b.x + b.y * b.y;
-    } else {
-      sx += b.x * b.x + b.y * b.y;
+    v[0] += b.x * b.x + b.y * b.y;
+  }
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) part[(size_t)r * nchunk + chunk] = v[0];
+}
+
+// out[r].x = sum of the chunk partials (fixed order)
+__global__ void k_sqnorm_reduce(int nrhs, int nchunk, const double* part, const int* active, double2* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs || !active[r]) return;
+  double t = 0.0;
+  for (int c = 0; c < nchunk; ++c) t += part[(size_t)r * nchunk + c];
+  out[r] = make_double2(t, 0.0);
+}
+
+// Reduction pass of delayed step j: partial sums over a chunk of rows of
+// conj(V_i) . u and conj(V_i) . w for the basis slots i <= j, where slot j
+// holds u (so i = j gives |u|^2 and u^H w).  w == nullptr: the u sums only.
+// part layout [r][i][chunk][2].
+// Blocks with blockIdx.y > j form the provisional column j - 1 from the
+// coefficients step j - 1 left in coef (s, z, then d, 1/gamma), one row i per
+// block: ((z, d)_i - (H s)_i) / gamma over the final columns 0 .. j-2 of the
+// row-major unrotated Hessenberg HuT; written to hp[(j - 1) & 1].
+__global__ __launch_bounds__(256) void k_arnoldi_dots(int N, int j, const double2* __restrict__ V, int64_t ldv,
+                                                      const double2* __restrict__ w, int64_t ld_w,
+                                                      const int* __restrict__ active, double2* __restrict__ part,
+                                                      int nchunk, int ldh, const double2* __restrict__ HuT,
+                                                      const double2* __restrict__ coef, double2* __restrict__ hp) {
+  __shared__ double red[16];
+  const int chunk = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
+  if (!active[r]) return;
+  if (i > j) {
+    // provisional column j - 1, row ih
+    const int ih = (i - j - 1) * nchunk + chunk;
+    if (ih >= j) return;
+    const double2* cf = coef + (size_t)r * (2 * ldh + 2);
+    const double2* sj = cf;          // s of step j - 1 (j - 1 entries)
+    const double2* row = HuT + (size_t)r * ldh * ldh + (size_t)ih * ldh;
+    double a[2] = {0.0, 0.0};
+    for (int k = max(0, ih - 1) + threadIdx.x; k < j - 1; k += 256) {
+      const double2 h = row[k], c = sj[k];
+      a[0] += h.x * c.x - h.y * c.y;
+      a[1] += h.x * c.y + h.y * c.x;
+    }
+    block_sum<2>(a, red);
+    if (threadIdx.x == 0) {
+      const double2 t = ih < j - 1 ? cf[ldh + ih] : cf[2 * ldh];
+      const double ig = cf[2 * ldh + 1].x;
+      hp[((size_t)r * 2 + ((j - 1) & 1)) * ldh + ih] = make_double2((t.x - a[0]) * ig, (t.y - a[1]) * ig);
+    }
+    return;
+  }
+  const double2* vi = V + (size_t)r * ldv + (size_t)i * N;
+  const double2* u = V + (size_t)r * ldv + (size_t)j * N;
+  const double2* wr = w ? w + (size_t)r * ld_w : nullptr;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const int n0 = chunk * RED_CHUNK, n1 = min(N, n0 + RED_CHUNK);
+  // loads of 4 rows are issued before any of them is used
+  constexpr int UN = 4;
+  int n = n0 + threadIdx.x;
+  for (; n + (UN - 1) * 256 < n1; n += UN * 256) {
+    double2 a[UN], b[UN], c[UN];
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      a[q] = vi[n + q * 256];
+      b[q] = u[n + q * 256];
+      c[q] = wr ? wr[n + q * 256] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      v[0] += a[q].x * b[q].x + a[q].y * b[q].y;
+      v[1] += a[q].x * b[q].y - a[q].y * b[q].x;
+      v[2] += a[q].x * c[q].x + a[q].y * c[q].y;
+      v[3] += a[q].x * c[q].y - a[q].y * c[q].x;
     }
   }
-  __shared__ double rx[256], ry[256], rw[256];
-  rx[threadIdx.x] = sx;
-  ry[threadIdx.x] = sy;
-  rw[threadIdx.x] = sw;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      rx[threadIdx.x] += rx[threadIdx.x + s];
-      ry[threadIdx.x] += ry[threadIdx.x + s];
-      rw[threadIdx.x] += rw[threadIdx.x + s];
+  for (; n < n1; n += 256) {
+    const double2 a = vi[n], b = u[n];
+    v[0] += a.x * b.x + a.y * b.y;
+    v[1] += a.x * b.y - a.y * b.x;
+    if (wr) {
+      const double2 c = wr[n];
+      v[2] += a.x * c.x + a.y * c.y;
+      v[3] += a.x * c.y - a.y * c.x;
     }
-    __syncthreads();
   }
+  block_sum<4>(v, red);
   if (threadIdx.x == 0) {
-    part[((size_t)r * jmax + i) * nchunk + chunk] = make_double2(rx[0], ry[0]);
-    if (wn) w0part[(size_t)r * nchunk + chunk] = rw[0];
+    double2* o = part + (((size_t)r * ldh + i) * nchunk + chunk) * 2;
+    o[0] = make_double2(v[0], v[1]);
+    o[1] = make_double2(v[2], v[3]);
   }
 }
 
-// out[r][i] = sum_chunk part (fixed order); mode 1: accumulate into H column
-__global__ void k_reduce(int nrhs, int j1, int nchunk, int jmax, const double2* part, const int* active,
-                         double2* out, int64_t ld_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// extra y-blocks of k_arnoldi_dots for the provisional column of step j - 1
+static inline int hs_blocks(int j, int nchunk) { return j >= 1 ? (j + nchunk - 1) / nchunk : 0; }
+
+// Update pass of delayed step j (formulas in the file header).  Every block
+// reduces the chunk partials itself (fixed order); block 0 writes the final
+// column j-1 into HuT (row-major, unrotated, for H s) and H (rotated later)
+// and leaves s, z, d and 1/gamma in coef for the provisional column, which
+// the next reduction pass forms; each block updates GV_ROWS rows of q_j and
+// u_{j+1}.  finalize != 0: only the column j-1 (one block per rhs, w unused).
+// Dynamic LDS: 3 (j + 1) double2.
+constexpr int GV_ROWS = 32, GV_GRP = 8;
+__global__ __launch_bounds__(256) void k_arnoldi_update(int N, int j, int nchunk, int ldh,
+                                                        const double2* __restrict__ part, double2* __restrict__ V,
+                                                        int64_t ldv, const double2* __restrict__ w, int64_t ld_w,
+                                                        const int* __restrict__ active, double2* __restrict__ HuT,
+                                                        double2* __restrict__ H, const double2* __restrict__ hp,
+                                                        double2* __restrict__ coef, int finalize) {
+  extern __shared__ double2 sh[];
+  __shared__ double red[16];
+  __shared__ double px[256], py[256], qx[256], qy[256];
   const int r = blockIdx.y;
-  if (i >= j1 || !active[r]) return;
-  double sx = 0, sy = 0;
-  const double2* p = part + ((size_t)r * jmax + i) * nchunk;
-  for (int c = 0; c < nchunk; ++c) { sx += p[c].x; sy += p[c].y; }
-  out[(size_t)r * ld_out + i] = make_double2(sx, sy);
+  if (!active[r]) return;
+  const int tid = threadIdx.x;
+  const int j1 = j + 1;
+  double2* S = sh;         // s_i (i < j), alpha at j
+  double2* Z = sh + j1;    // z_i (i < j), zeta at j
+  const double2* pr = part + (size_t)r * ldh * nchunk * 2;
+  for (int i = tid; i < j1; i += 256) {
+    double ax = 0, ay = 0, bx = 0, by = 0;
+    const double2* pi = pr + (size_t)i * nchunk * 2;
+    int c = 0;
+    for (; c + 3 < nchunk; c += 4) {   // 8 loads in flight, summed in chunk order
+      double2 t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = pi[2 * c + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ax += t[2 * q].x;
+        ay += t[2 * q].y;
+        bx += t[2 * q + 1].x;
+        by += t[2 * q + 1].y;
+      }
+    }
+    for (; c < nchunk; ++c) {
+      const double2 a = pi[2 * c], b = pi[2 * c + 1];
+      ax += a.x;
+      ay += a.y;
+      bx += b.x;
+      by += b.y;
+    }
+    S[i] = make_double2(ax, ay);
+    Z[i] = make_double2(bx, by);
+  }
+  __syncthreads();
+  // |s|^2 and s^H z
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = tid; i < j; i += 256) {
+    const double2 a = S[i], b = Z[i];
+    v[0] += a.x * a.x + a.y * a.y;
+    v[1] += a.x * b.x + a.y * b.y;
+    v[2] += a.x * b.y - a.y * b.x;
+  }
+  block_sum<3>(v, red);
+  const double g2 = S[j].x - v[0];
+  const double gam = g2 > 0.0 ? sqrt(g2) : 0.0;
+  const double ig = gam > 0.0 ? 1.0 / gam : 0.0;
+  const double2 d = make_double2((Z[j].x - v[1]) * ig, (Z[j].y - v[2]) * ig);
+  const double2 e = make_double2(d.x * ig, d.y * ig);
+  const size_t hcol = (size_t)r * ldh * (ldh - 1);
+  const double2* hprev = hp + ((size_t)r * 2 + ((j - 1) & 1)) * ldh;   // provisional column j-1
+  auto col_prev = [&](int i) -> double2 {                                // final column j-1, row i <= j
+    if (i < j) return make_double2(hprev[i].x + S[i].x, hprev[i].y + S[i].y);
+    return make_double2(gam, 0.0);
+  };
+  if (blockIdx.x == 0) {
+    if (j >= 1)
+      for (int i = tid; i <= j; i += 256) {
+        const double2 c = col_prev(i);
+        HuT[(size_t)r * ldh * ldh + (size_t)i * ldh + (j - 1)] = c;
+        H[hcol + (size_t)(j - 1) * ldh + i] = c;
+      }
+    if (!finalize) {
+      double2* cf = coef + (size_t)r * (2 * ldh + 2);
+      for (int i = tid; i < j; i += 256) {
+        cf[i] = S[i];
+        cf[ldh + i] = Z[i];
+      }
+      if (tid == 0) {
+        cf[2 * ldh] = d;
+        cf[2 * ldh + 1] = make_double2(ig, 0.0);
+      }
+    }
+  }
+  if (finalize) return;
+  // q_j and u_{j+1} for rows n
+  const int lr = tid % GV_ROWS, g = tid / GV_ROWS;
+  const int n = blockIdx.x * GV_ROWS + lr;
+  const double2* vr = V + (size_t)r * ldv;
+  // coefficients of Q_j in u_{j+1}: z - e s
+  double2* T = sh + 2 * j1;
+  for (int i = tid; i < j; i += 256) {
+    const double2 c = S[i], zz = Z[i];
+    T[i] = make_double2(zz.x - (e.x * c.x - e.y * c.y), zz.y - (e.x * c.y + e.y * c.x));
+  }
+  __syncthreads();
+  double sx = 0, sy = 0, tx = 0, ty = 0;
+  auto acc = [&](double2 a, int i) {
+    const double2 c = S[i], t = T[i];
+    sx += a.x * c.x - a.y * c.y;
+    sy += a.x * c.y + a.y * c.x;
+    tx += a.x * t.x - a.y * t.y;
+    ty += a.x * t.y + a.y * t.x;
+  };
+  if (n < N) {
+    constexpr int UN = 8;   // basis loads in flight per thread
+    int i = g;
+    for (; i + (UN - 1) * GV_GRP < j; i += UN * GV_GRP) {
+      double2 a[UN];
+#pragma unroll
+      for (int q = 0; q < UN; ++q) a[q] = vr[(size_t)(i + q * GV_GRP) * N + n];
+      __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of their uses
+#pragma unroll
+      for (int q = 0; q < UN; ++q) acc(a[q], i + q * GV_GRP);
+    }
+    for (; i < j; i += GV_GRP) acc(vr[(size_t)i * N + n], i);
+  }
+  px[tid] = sx;
+  py[tid] = sy;
+  qx[tid] = tx;
+  qy[tid] = ty;
+  __syncthreads();
+  if (g == 0 && n < N) {
+    for (int q = 1; q < GV_GRP; ++q) {
+      sx += px[q * GV_ROWS + lr];
+      sy += py[q * GV_ROWS + lr];
+      tx += qx[q * GV_ROWS + lr];
+      ty += qy[q * GV_ROWS + lr];
+    }
+    double2* uj = V + (size_t)r * ldv + (size_t)j * N;
+    const double2 u = uj[n], wn = w[(size_t)r * ld_w + n];
+    uj[n] = make_double2((u.x - sx) * ig, (u.y - sy) * ig);
+    const double ox = wn.x - tx - (e.x * u.x - e.y * u.y);
+    const double oy = wn.y - ty - (e.x * u.y + e.y * u.x);
+    uj[N + n] = make_double2(ox * ig, oy * ig);
+  }
 }
 
 // w[r] += sgn * sum_i V[r][i] c[r][i]; block = 32 rows x 8 groups of i
-constexpr int GV_ROWS = 32, GV_GRP = 8;
 __global__ __launch_bounds__(256) void k_gemv(int N, int j1, const double2* __restrict__ V, int64_t ld_rhs_v,
                                               const double2* __restrict__ c, int64_t ld_c, double sgn,
                                               const int* __restrict__ active, double2* __restrict__ w,
@@ -113,81 +341,13 @@ __global__ __launch_bounds__(256) void k_gemv(int N, int j1, const double2* __re
   }
 }
 
-// One CGS pass update: h = sum of the Vᴴw chunk partials (fixed order), then
-// w -= V h.  Block 0 also adds h into H[:, j].  With want_norm, each block
-// writes the partial |w|^2 of its rows (the norm of the orthogonalised w).
-// Dynamic LDS: j1 double2.
-__global__ __launch_bounds__(256) void k_cgs_update(int N, int j1, int nchunk, int jmax,
-                                                    const double2* __restrict__ part, const double2* __restrict__ V,
-                                                    int64_t ld_rhs_v, const int* __restrict__ active,
-                                                    double2* __restrict__ w, int64_t ld_w, double2* __restrict__ H,
-                                                    int ldh, int j, int first, int want_norm,
-                                                    double* __restrict__ npart, const int* __restrict__ skip) {
-  extern __shared__ double2 hsh[];
-  const int r = blockIdx.y;
-  if (!active[r] || (skip && !skip[r])) return;
-  const double2* pr = part + (size_t)r * jmax * nchunk;
-  for (int i = threadIdx.x; i < j1; i += 256) {
-    double sx = 0, sy = 0;
-    for (int c = 0; c < nchunk; ++c) {
-      const double2 v = pr[(size_t)i * nchunk + c];
-      sx += v.x;
-      sy += v.y;
-    }
-    hsh[i] = make_double2(sx, sy);
-    if (blockIdx.x == 0) {
-      double2* Hc = H + (size_t)r * ldh * (ldh - 1) + (size_t)j * ldh;
-      Hc[i] = first ? make_double2(sx, sy) : make_double2(Hc[i].x + sx, Hc[i].y + sy);
-    }
-  }
-  __syncthreads();
-  const int lr = threadIdx.x % GV_ROWS, g = threadIdx.x / GV_ROWS;
-  const int n = blockIdx.x * GV_ROWS + lr;
-  const double2* vr = V + (size_t)r * ld_rhs_v;
-  double sx = 0, sy = 0;
-  if (n < N) {
-    for (int i = g; i < j1; i += GV_GRP) {
-      const double2 a = vr[(size_t)i * N + n], b = hsh[i];
-      sx += a.x * b.x - a.y * b.y;
-      sy += a.x * b.y + a.y * b.x;
-    }
-  }
-  __shared__ double px[256], py[256];
-  px[threadIdx.x] = sx;
-  py[threadIdx.x] = sy;
-  __syncthreads();
-  double nrm = 0.0;
-  if (g == 0 && n < N) {
-    for (int q = 1; q < GV_GRP; ++q) {
-      sx += px[q * GV_ROWS + lr];
-      sy += py[q * GV_ROWS + lr];
-    }
-    const double2 o = w[(size_t)r * ld_w + n];
-    const double2 nw = make_double2(o.x - sx, o.y - sy);
-    w[(size_t)r * ld_w + n] = nw;
-    nrm = nw.x * nw.x + nw.y * nw.y;
-  }
-  if (want_norm) {
-    __syncthreads();
-    px[threadIdx.x] = nrm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int q = 0; q < GV_ROWS; ++q) t += px[q];
-      npart[(size_t)r * gridDim.x + blockIdx.x] = t;
-    }
-  }
-}
-
-// v = w / ||w||   (||w|| from the reduction); also records H[j+1, j]
-__global__ void k_normalize(int N, const double2* nrm2, int64_t ld_n, const double2* __restrict__ w, int64_t ld_w,
-                            double2* __restrict__ v, int64_t ld_rhs_v, const int* __restrict__ active, double* hn) {
+// v = w / ||w||   (||w||^2 from the reduction, in nrm2[r].x)
+__global__ void k_normalize(int N, const double2* nrm2, const double2* __restrict__ w, int64_t ld_w,
+                            double2* __restrict__ v, int64_t ld_rhs_v, const int* __restrict__ active) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (!active[r]) return;
-  const double nr = sqrt(nrm2[(size_t)r * ld_n].x);
-  if (n == 0) hn[r] = nr;
-  if (n >= N) return;
+  if (!active[r] || n >= N) return;
+  const double nr = sqrt(nrm2[r].x);
   const double s = nr > 0 ? 1.0 / nr : 0.0;
   const double2 a = w[(size_t)r * ld_w + n];
   v[(size_t)r * ld_rhs_v + n] = make_double2(a.x * s, a.y * s);
@@ -208,57 +368,6 @@ __global__ void k_axpy(int N, const double2* d, double2* x) {
   if (n >= N) return;
   const double2 a = d[(size_t)c * N + n], o = x[(size_t)c * N + n];
   x[(size_t)c * N + n] = make_double2(o.x + a.x, o.y + a.y);
-}
-
-// Selective re-orthogonalisation (Daniel-Gragg-Kaufman-Stewart): a second
-// Gram-Schmidt pass is needed only when the first one removed more than
-// half of |w|^2, i.e. ||w1|| < ||w0|| / sqrt(2).  One block per rhs.
-__global__ void k_reorth_flag(int nchunk, int nparts, const double* __restrict__ w0part,
-                              const double* __restrict__ npart, const int* __restrict__ active, int* reorth) {
-  const int r = blockIdx.x;
-  if (!active[r]) return;
-  __shared__ double a[256], b[256];
-  double s0 = 0, s1 = 0;
-  for (int q = threadIdx.x; q < nchunk; q += 256) s0 += w0part[(size_t)r * nchunk + q];
-  for (int q = threadIdx.x; q < nparts; q += 256) s1 += npart[(size_t)r * nparts + q];
-  a[threadIdx.x] = s0;
-  b[threadIdx.x] = s1;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      a[threadIdx.x] += a[threadIdx.x + st];
-      b[threadIdx.x] += b[threadIdx.x + st];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) reorth[r] = (b[0] < 0.5 * a[0]) ? 1 : 0;
-}
-
-// hn = ||w|| from the block partials (fixed order); v_{j+1} = w / hn; block 0
-// records H[j+1, j] = hn (before rotation).
-__global__ __launch_bounds__(256) void k_scale_norm(int N, int nparts, const double* __restrict__ npart,
-                                                    const double2* __restrict__ w, int64_t ld_w,
-                                                    double2* __restrict__ v, int64_t ld_rhs_v,
-                                                    const int* __restrict__ active, double2* H, int ldh, int j) {
-  const int r = blockIdx.y;
-  if (!active[r]) return;
-  __shared__ double red[256];
-  double t = 0.0;
-  for (int q = threadIdx.x; q < nparts; q += 256) t += npart[(size_t)r * nparts + q];
-  red[threadIdx.x] = t;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  const double hnr = sqrt(red[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0)
-    H[(size_t)r * ldh * (ldh - 1) + (size_t)j * ldh + j + 1] = make_double2(hnr, 0.0);
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const double sc = hnr > 0 ? 1.0 / hnr : 0.0;
-  const double2 a = w[(size_t)r * ld_w + n];
-  v[(size_t)r * ld_rhs_v + n] = make_double2(a.x * sc, a.y * sc);
 }
 
 __device__ __forceinline__ void rot_apply(double ci, double2 si, double2& a, double2 b, double2& out_top) {
@@ -384,17 +493,21 @@ __global__ void k_set_g0(int nrhs, int ldh, const double2* nrm2, const int* acti
 }
 
 // ---------------------------------------------------------------------------
-static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
-  GmresWork& w = c->gw;
-  if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
-  for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.g, (void*)w.cs, (void*)w.sn, (void*)w.y,
-                  (void*)w.hcol, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm, (void*)w.bnorm,
-                  (void*)w.resid, (void*)w.hn, (void*)w.npart, (void*)w.w0part, (void*)w.reorth, (void*)w.active})
+void free_gmres_work(GmresWork& w) {
+  for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.Hu, (void*)w.hp, (void*)w.coef, (void*)w.g, (void*)w.cs,
+                  (void*)w.sn, (void*)w.y, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm,
+                  (void*)w.resid, (void*)w.npart, (void*)w.active})
     if (p) hipFree(p);
   if (w.host_resid) hipHostFree(w.host_resid);
   if (w.pin) hipHostFree(w.pin);
-  c->dev_bytes -= w.bytes;
   w = GmresWork();
+}
+
+static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
+  GmresWork& w = c->gw;
+  if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
+  c->dev_bytes -= w.bytes;
+  free_gmres_work(w);
   const int N = c->t.N;
   const int ldh = restart + 1;
   w.restart = restart;
@@ -407,15 +520,15 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
     return hipMemset(*p, 0, b) == hipSuccess;
   };
   bool ok = A((void**)&w.V, (size_t)nrhs * ldh * N * 16) && A((void**)&w.W, (size_t)nrhs * N * 16) &&
-            A((void**)&w.H, (size_t)nrhs * ldh * restart * 16) && A((void**)&w.g, (size_t)nrhs * ldh * 16) &&
+            A((void**)&w.H, (size_t)nrhs * ldh * restart * 16) && A((void**)&w.Hu, (size_t)nrhs * ldh * ldh * 16) &&
+            A((void**)&w.hp, (size_t)nrhs * 2 * ldh * 16) &&
+            A((void**)&w.coef, (size_t)nrhs * (2 * ldh + 2) * 16) && A((void**)&w.g, (size_t)nrhs * ldh * 16) &&
             A((void**)&w.cs, (size_t)nrhs * restart * 16) && A((void**)&w.sn, (size_t)nrhs * restart * 16) &&
-            A((void**)&w.y, (size_t)nrhs * restart * 16) && A((void**)&w.hcol, (size_t)nrhs * ldh * 16) &&
-            A((void**)&w.part, (size_t)nrhs * ldh * w.nchunk * 16) && A((void**)&w.r, (size_t)nrhs * N * 16) &&
+            A((void**)&w.y, (size_t)nrhs * restart * 16) &&
+            A((void**)&w.part, (size_t)nrhs * ldh * w.nchunk * 2 * 16) && A((void**)&w.r, (size_t)nrhs * N * 16) &&
             A((void**)&w.d, (size_t)nrhs * N * 16) && A((void**)&w.b2, (size_t)nrhs * N * 16) &&
-            A((void**)&w.nrm, (size_t)nrhs * 2 * 16) && A((void**)&w.bnorm, (size_t)nrhs * 8) &&
-            A((void**)&w.resid, (size_t)nrhs * restart * 8) && A((void**)&w.hn, (size_t)nrhs * 8) && A((void**)&w.npart, (size_t)nrhs * ((N + 31) / 32) * 8) && A((void**)&w.w0part, (size_t)nrhs * w.nchunk * 8) &&
-            A((void**)&w.reorth, (size_t)nrhs * 4) &&
-            A((void**)&w.active, (size_t)nrhs * 4 * 2);
+            A((void**)&w.nrm, (size_t)nrhs * 2 * 16) && A((void**)&w.resid, (size_t)nrhs * restart * 8) &&
+            A((void**)&w.npart, (size_t)nrhs * w.nchunk * 8) && A((void**)&w.active, (size_t)nrhs * 4 * 2);
   if (!ok) return AIM_E_OOM;
   if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * restart * 8) != hipSuccess) return AIM_E_OOM;
   // pinned staging for the host-to-device mask copies (one region per use,
@@ -426,7 +539,9 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
   if (hipMemcpy(w.active + nrhs, w.pin, (size_t)nrhs * 4, hipMemcpyHostToDevice) != hipSuccess) return AIM_E_HIP;
   w.bytes = tot;
   {
-    const size_t gb = ((size_t)kCheckEvery * ldh + 2 * (size_t)restart) * 16;
+    // a check may rotate up to kCheckEvery + 1 columns (the last one of a
+    // cycle is finalised with the batch)
+    const size_t gb = ((size_t)(kCheckEvery + 1) * ldh + 2 * (size_t)restart) * 16;
     if (gb > 65536 &&
         hipFuncSetAttribute((const void*)k_givens_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gb) !=
             hipSuccess)
@@ -446,10 +561,9 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
 static aim_status norms(Ctx* c, int nrhs, const double2* w, int64_t ldw, const int* active, double2* out) {
   GmresWork& g = c->gw;
   const int N = c->t.N;
-  hipLaunchKernelGGL(k_dots, dim3(g.nchunk, 1, nrhs), dim3(256), 0, c->stream, N, nullptr, 0, w, ldw, active,
-                     g.part, g.nchunk, 1);
-  hipLaunchKernelGGL(k_reduce, dim3(1, nrhs), dim3(64), 0, c->stream, nrhs, 1, g.nchunk, 1, g.part, active, out,
-                     (int64_t)1);
+  hipLaunchKernelGGL(k_sqnorm, dim3(g.nchunk, nrhs), dim3(256), 0, c->stream, N, w, ldw, active, g.npart, g.nchunk);
+  hipLaunchKernelGGL(k_sqnorm_reduce, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, nrhs, g.nchunk, g.npart,
+                     active, out);
   AIM_HIP_CHECK(hipGetLastError());
   return AIM_OK;
 }
@@ -517,54 +631,54 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
     }
     if (!any || total >= maxit) break;
     AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
-    hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, (int64_t)1, w.W, (int64_t)N, w.V, ldv, w.active,
-                       w.hn);
+    hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, w.W, (int64_t)N, w.V, ldv, w.active);
     hipLaunchKernelGGL(k_set_g0, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, w.nrm, w.active, w.g);
     std::fill(jdone.begin(), jdone.end(), 0);
     std::vector<int> cyc(act);
-    int j = 0;
+    const int gblk = (N + GV_ROWS - 1) / GV_ROWS;
+    // Arnoldi step j finalises Hessenberg column j - 1; jfin columns are
+    // final and rotated
+    int j = 0, jfin = 0;
     while (j < restart && total < maxit) {
-      const int jstart = j;
       const int jend = std::min(std::min(restart, j + kCheckEvery), j + (maxit - total));
       for (; j < jend; ++j) {
-        const int j1 = j + 1;
-        // w = A v_j
+        // w = A u_j
         TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
         res.matvecs++;
-        // CGS with selective re-orthogonalisation: pass 1 always; pass 2 only
-        // where the flag kernel asks for it (decided on the device)
-        const int gblk = (N + GV_ROWS - 1) / GV_ROWS;
-        hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
-                           w.active, w.part, w.nchunk, ldh, (const int*)nullptr, w.w0part);
-        hipLaunchKernelGGL(k_cgs_update, dim3(gblk, nrhs), dim3(256), (size_t)j1 * 16, s, N, j1, w.nchunk, ldh,
-                           w.part, w.V, ldv, w.active, w.W, (int64_t)N, w.H, ldh, j, 1, 1, w.npart,
-                           (const int*)nullptr);
-        hipLaunchKernelGGL(k_reorth_flag, dim3(nrhs), dim3(256), 0, s, w.nchunk, gblk, w.w0part, w.npart, w.active,
-                           w.reorth);
-        hipLaunchKernelGGL(k_dots, dim3(w.nchunk, j1, nrhs), dim3(256), 0, s, N, w.V, ldv, w.W, (int64_t)N,
-                           w.active, w.part, w.nchunk, ldh, (const int*)w.reorth, (double*)nullptr);
-        hipLaunchKernelGGL(k_cgs_update, dim3(gblk, nrhs), dim3(256), (size_t)j1 * 16, s, N, j1, w.nchunk, ldh,
-                           w.part, w.V, ldv, w.active, w.W, (int64_t)N, w.H, ldh, j, 0, 1, w.npart,
-                           (const int*)w.reorth);
-        hipLaunchKernelGGL(k_scale_norm, gN, dim3(256), 0, s, N, gblk, w.npart, w.W, (int64_t)N,
-                           w.V + (size_t)j1 * N, ldv, w.active, w.H, ldh, j);
+        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, j + 1 + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
+                           j, w.V, ldv, w.W, (int64_t)N, w.active, w.part, w.nchunk, ldh, w.Hu, w.coef, w.hp);
+        hipLaunchKernelGGL(k_arnoldi_update, dim3(gblk, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk,
+                           ldh, w.part, w.V, ldv, w.W, (int64_t)N, w.active, w.Hu, w.H, w.hp, w.coef, 0);
         AIM_HIP_CHECK(hipGetLastError());
         total++;
       }
-      // rotations for the steps just taken, then their residual estimates
-      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(64),
-                         ((size_t)(jend - jstart) * ldh + 2 * (size_t)jend) * 16, s, ldh, jstart, jend, w.active, w.H,
-                         w.cs, w.sn, w.g, w.resid);
+      // at the end of a cycle the last column is finalised by a reduction of
+      // u_j alone (no operator application)
+      const bool last = j >= restart || total >= maxit;
+      if (last) {
+        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, j + 1 + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
+                           j, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.part, w.nchunk, ldh, w.Hu,
+                           w.coef, w.hp);
+        hipLaunchKernelGGL(k_arnoldi_update, dim3(1, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk, ldh,
+                           w.part, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.Hu, w.H, w.hp, w.coef,
+                           1);
+        AIM_HIP_CHECK(hipGetLastError());
+      }
+      const int c1 = last ? j : j - 1;
+      if (c1 <= jfin) continue;
+      // rotations for the newly final columns, then their residual estimates
+      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(64), ((size_t)(c1 - jfin) * ldh + 2 * (size_t)c1) * 16, s,
+                         ldh, jfin, c1, w.active, w.H, w.cs, w.sn, w.g, w.resid);
       AIM_HIP_CHECK(hipGetLastError());
       for (int r = 0; r < nrhs; ++r)
         if (act[r])
-          AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jstart, w.resid + (size_t)r * restart + jstart,
-                                       (size_t)(jend - jstart) * 8, hipMemcpyDeviceToHost, s));
+          AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jfin, w.resid + (size_t)r * restart + jfin,
+                                       (size_t)(c1 - jfin) * 8, hipMemcpyDeviceToHost, s));
       AIM_HIP_CHECK(hipStreamSynchronize(s));
       bool left = false, changed = false;
       for (int r = 0; r < nrhs; ++r) {
         if (!act[r]) continue;
-        for (int jj = jstart; jj < jend; ++jj) {
+        for (int jj = jfin; jj < c1; ++jj) {
           res.iters[r]++;
           jdone[r] = jj + 1;
           const double rel = w.host_resid[(size_t)r * restart + jj] / bn[r];
@@ -574,6 +688,7 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
         }
         if (act[r]) left = true;
       }
+      jfin = c1;
       if (!left) break;
       if (changed) AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
     }
