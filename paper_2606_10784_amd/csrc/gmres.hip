@@ -82,11 +82,15 @@ __global__ void k_sqnorm_reduce(int nrhs, int nchunk, const double* part, const 
   out[r] = make_double2(t, 0.0);
 }
 
+constexpr int DOT_COLS = 1;   // basis slots per reduction block (4 sums each)
+static inline int dot_groups(int j) { return (j + DOT_COLS) / DOT_COLS; }
+
 // Reduction pass of delayed step j: partial sums over a chunk of rows of
 // conj(V_i) . u and conj(V_i) . w for the basis slots i <= j, where slot j
 // holds u (so i = j gives |u|^2 and u^H w).  w == nullptr: the u sums only.
-// part layout [r][i][chunk][2].
-// Blocks with blockIdx.y > j form the provisional column j - 1 from the
+// part layout [r][i][chunk][2].  Block (chunk, y) covers the slots
+// DOT_COLS y .. DOT_COLS y + DOT_COLS - 1.
+// Blocks with y >= dot_groups(j) form the provisional column j - 1 from the
 // coefficients step j - 1 left in coef (s, z, then d, 1/gamma), one row i per
 // block: ((z, d)_i - (H s)_i) / gamma over the final columns 0 .. j-2 of the
 // row-major unrotated Hessenberg HuT; written to hp[(j - 1) & 1].
@@ -98,9 +102,9 @@ __global__ __launch_bounds__(256) void k_arnoldi_dots(int N, int j, const double
   __shared__ double red[16];
   const int chunk = blockIdx.x, i = blockIdx.y, r = blockIdx.z;
   if (!active[r]) return;
-  if (i > j) {
+  if (i >= (j + DOT_COLS) / DOT_COLS) {
     // provisional column j - 1, row ih
-    const int ih = (i - j - 1) * nchunk + chunk;
+    const int ih = (i - (j + DOT_COLS) / DOT_COLS) * nchunk + chunk;
     if (ih >= j) return;
     const double2* cf = coef + (size_t)r * (2 * ldh + 2);
     const double2* sj = cf;          // s of step j - 1 (j - 1 entries)
@@ -119,45 +123,71 @@ __global__ __launch_bounds__(256) void k_arnoldi_dots(int N, int j, const double
     }
     return;
   }
-  const double2* vi = V + (size_t)r * ldv + (size_t)i * N;
-  const double2* u = V + (size_t)r * ldv + (size_t)j * N;
+  // basis slots i0 .. i0+3 against u and w over one chunk of rows
+  const int i0 = i * DOT_COLS;
+  const double2* vb = V + (size_t)r * ldv;
+  const double2* u = vb + (size_t)j * N;
   const double2* wr = w ? w + (size_t)r * ld_w : nullptr;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const double2* vc[DOT_COLS];
+#pragma unroll
+  for (int q = 0; q < DOT_COLS; ++q) vc[q] = vb + (size_t)min(i0 + q, j) * N;   // clamped: unused sums
+  double v[4 * DOT_COLS];
+#pragma unroll
+  for (int k = 0; k < 4 * DOT_COLS; ++k) v[k] = 0.0;
   const int n0 = chunk * RED_CHUNK, n1 = min(N, n0 + RED_CHUNK);
-  // loads of 4 rows are issued before any of them is used
-  constexpr int UN = 4;
-  int n = n0 + threadIdx.x;
-  for (; n + (UN - 1) * 256 < n1; n += UN * 256) {
-    double2 a[UN], b[UN], c[UN];
+  constexpr int RU = DOT_COLS >= 4 ? 1 : 4 / DOT_COLS;   // rows per thread in flight
+  for (int n = n0 + threadIdx.x; n < n1; n += RU * 256) {
+    double2 bu[RU], bw[RU], a[RU][DOT_COLS];
 #pragma unroll
-    for (int q = 0; q < UN; ++q) {
-      a[q] = vi[n + q * 256];
-      b[q] = u[n + q * 256];
-      c[q] = wr ? wr[n + q * 256] : make_double2(0.0, 0.0);
+    for (int m = 0; m < RU; ++m) {
+      const int nn = min(n + m * 256, n1 - 1);   // clamped rows are loaded but not summed
+      bu[m] = u[nn];
+      bw[m] = wr ? wr[nn] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < DOT_COLS; ++q) a[m][q] = vc[q][nn];
     }
 #pragma unroll
-    for (int q = 0; q < UN; ++q) {
-      v[0] += a[q].x * b[q].x + a[q].y * b[q].y;
-      v[1] += a[q].x * b[q].y - a[q].y * b[q].x;
-      v[2] += a[q].x * c[q].x + a[q].y * c[q].y;
-      v[3] += a[q].x * c[q].y - a[q].y * c[q].x;
+    for (int m = 0; m < RU; ++m) {
+      if (n + m * 256 >= n1) break;
+#pragma unroll
+      for (int q = 0; q < DOT_COLS; ++q) {
+        v[4 * q + 0] += a[m][q].x * bu[m].x + a[m][q].y * bu[m].y;
+        v[4 * q + 1] += a[m][q].x * bu[m].y - a[m][q].y * bu[m].x;
+        v[4 * q + 2] += a[m][q].x * bw[m].x + a[m][q].y * bw[m].y;
+        v[4 * q + 3] += a[m][q].x * bw[m].y - a[m][q].y * bw[m].x;
+      }
     }
   }
-  for (; n < n1; n += 256) {
-    const double2 a = vi[n], b = u[n];
-    v[0] += a.x * b.x + a.y * b.y;
-    v[1] += a.x * b.y - a.y * b.x;
-    if (wr) {
-      const double2 c = wr[n];
-      v[2] += a.x * c.x + a.y * c.y;
-      v[3] += a.x * c.y - a.y * c.x;
+  // the 4 DOT_COLS sums over the block: halving exchanges within each wave
+  // (each step keeps half of the sums, so lane groups end up with one sum
+  // each), butterflies within the groups, then the four waves in order
+  constexpr int NS = 4 * DOT_COLS;
+  constexpr int H = NS == 16 ? 4 : (NS == 8 ? 3 : 2);   // log2 NS
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int off = 32 >> h, keep = NS >> (h + 1);
+    const bool hi = (lane & off) != 0;
+#pragma unroll
+    for (int k = 0; k < keep; ++k) {
+      const double send = hi ? v[k] : v[k + keep];
+      const double mine = hi ? v[k + keep] : v[k];
+      v[k] = mine + __shfl_xor(send, off);
     }
   }
-  block_sum<4>(v, red);
-  if (threadIdx.x == 0) {
-    double2* o = part + (((size_t)r * ldh + i) * nchunk + chunk) * 2;
-    o[0] = make_double2(v[0], v[1]);
-    o[1] = make_double2(v[2], v[3]);
+#pragma unroll
+  for (int off = 32 >> H; off >= 1; off >>= 1) v[0] += __shfl_xor(v[0], off);
+  // lane m << (6 - H) now holds sum number m
+  __shared__ double wsum[4][NS];
+  if ((lane & ((64 >> H) - 1)) == 0) wsum[wv][lane >> (6 - H)] = v[0];
+  __syncthreads();
+  if (threadIdx.x < 4 * DOT_COLS) {
+    const int k = threadIdx.x, q = k >> 2;
+    const double t = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
+    if (i0 + q <= j) {
+      double* o = (double*)(part + (((size_t)r * ldh + i0 + q) * nchunk + chunk) * 2);
+      o[k & 3] = t;
+    }
   }
 }
 
@@ -187,6 +217,21 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(int N, int j, int nchunk
   const int j1 = j + 1;
   double2* S = sh;         // s_i (i < j), alpha at j
   double2* Z = sh + j1;    // z_i (i < j), zeta at j
+  // the first basis loads of the update do not depend on the coefficients:
+  // issue them before the reduction of the partials
+  constexpr int UN = 8;    // basis loads in flight per thread
+  const int lr = tid % GV_ROWS, g = tid / GV_ROWS;
+  const int n = blockIdx.x * GV_ROWS + lr;
+  const double2* vr = V + (size_t)r * ldv;
+  double2 pre[UN];
+  if (!finalize) {
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+      const int i = g + q * GV_GRP;
+      pre[q] = (n < N && i < j) ? vr[(size_t)i * N + n] : make_double2(0.0, 0.0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
   const double2* pr = part + (size_t)r * ldh * nchunk * 2;
   for (int i = tid; i < j1; i += 256) {
     double ax = 0, ay = 0, bx = 0, by = 0;
@@ -256,9 +301,6 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(int N, int j, int nchunk
   }
   if (finalize) return;
   // q_j and u_{j+1} for rows n
-  const int lr = tid % GV_ROWS, g = tid / GV_ROWS;
-  const int n = blockIdx.x * GV_ROWS + lr;
-  const double2* vr = V + (size_t)r * ldv;
   // coefficients of Q_j in u_{j+1}: z - e s
   double2* T = sh + 2 * j1;
   for (int i = tid; i < j; i += 256) {
@@ -275,8 +317,10 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(int N, int j, int nchunk
     ty += a.x * t.y + a.y * t.x;
   };
   if (n < N) {
-    constexpr int UN = 8;   // basis loads in flight per thread
-    int i = g;
+#pragma unroll
+    for (int q = 0; q < UN; ++q)
+      if (g + q * GV_GRP < j) acc(pre[q], g + q * GV_GRP);
+    int i = g + UN * GV_GRP;
     for (; i + (UN - 1) * GV_GRP < j; i += UN * GV_GRP) {
       double2 a[UN];
 #pragma unroll
@@ -381,9 +425,9 @@ __device__ __forceinline__ void rot_apply(double ci, double2 si, double2& a, dou
 // per column, chains read from LDS), then the new rotations are formed in
 // order.  Writes the residual estimates |g_{j+1}| of those steps.  One block
 // per rhs; dynamic LDS: (j1 - j0) * ldh + 2 * j1 double2.
-__global__ __launch_bounds__(64) void k_givens_batch(int ldh, int j0, int j1, const int* __restrict__ active,
-                                                     double2* H, double2* cs, double2* sn, double2* g,
-                                                     double* resid_hist) {
+__global__ __launch_bounds__(256) void k_givens_batch(int ldh, int j0, int j1, const int* __restrict__ active,
+                                                      double2* H, double2* cs, double2* sn, double2* g,
+                                                      double* resid_hist) {
   extern __shared__ double2 sh[];
   const int r = blockIdx.x;
   if (!active[r]) return;
@@ -395,9 +439,19 @@ __global__ __launch_bounds__(64) void k_givens_batch(int ldh, int j0, int j1, co
   double2* Hr = H + (size_t)r * ldh * R;
   double2* c = cs + (size_t)r * R;
   double2* s = sn + (size_t)r * R;
-  for (int t = 0; t < nc; ++t)
-    for (int i = threadIdx.x; i <= j0 + t + 1; i += 64) Hs[(size_t)t * ldh + i] = Hr[(size_t)(j0 + t) * ldh + i];
-  for (int i = threadIdx.x; i < j0; i += 64) {
+  // the columns j0..j1-1 are contiguous in H (rows 0..j+1 of each are used):
+  // one flat copy with four loads in flight per thread
+  const int tot = nc * ldh;
+  const double2* src = Hr + (size_t)j0 * ldh;
+  for (int b = threadIdx.x; b < tot; b += 4 * 256) {
+    const double2 v0 = src[b], v1 = src[min(b + 256, tot - 1)], v2 = src[min(b + 512, tot - 1)],
+                  v3 = src[min(b + 768, tot - 1)];
+    Hs[b] = v0;
+    if (b + 256 < tot) Hs[b + 256] = v1;
+    if (b + 512 < tot) Hs[b + 512] = v2;
+    if (b + 768 < tot) Hs[b + 768] = v3;
+  }
+  for (int i = threadIdx.x; i < j0; i += 256) {
     Cs[i] = c[i];
     Ss[i] = s[i];
   }
@@ -405,7 +459,24 @@ __global__ __launch_bounds__(64) void k_givens_batch(int ldh, int j0, int j1, co
   if (threadIdx.x < nc) {
     double2* col = Hs + (size_t)threadIdx.x * ldh;
     double2 a = col[0];
-    for (int i = 0; i < j0; ++i) {
+    int i = 0;
+    for (; i + 4 <= j0; i += 4) {   // LDS reads of four rotations ahead of the chain
+      double2 b[4], sq[4];
+      double cq[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        b[q] = col[i + q + 1];
+        cq[q] = Cs[i + q].x;
+        sq[q] = Ss[i + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double2 top;
+        rot_apply(cq[q], sq[q], a, b[q], top);
+        col[i + q] = top;
+      }
+    }
+    for (; i < j0; ++i) {
       double2 top;
       rot_apply(Cs[i].x, Ss[i], a, col[i + 1], top);
       col[i] = top;
@@ -448,9 +519,12 @@ __global__ __launch_bounds__(64) void k_givens_batch(int ldh, int j0, int j1, co
     }
   }
   __syncthreads();
-  for (int t = 0; t < nc; ++t)
-    for (int i = threadIdx.x; i <= j0 + t + 1; i += 64) Hr[(size_t)(j0 + t) * ldh + i] = Hs[(size_t)t * ldh + i];
-  for (int i = j0 + threadIdx.x; i < j1; i += 64) {
+  double2* dst = Hr + (size_t)j0 * ldh;
+  for (int b = threadIdx.x; b < tot; b += 256) {
+    const int t = b / ldh, i = b - t * ldh;
+    if (i <= j0 + t + 1) dst[b] = Hs[b];
+  }
+  for (int i = j0 + threadIdx.x; i < j1; i += 256) {
     c[i] = Cs[i];
     s[i] = Ss[i];
   }
@@ -645,7 +719,7 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
         // w = A u_j
         TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
         res.matvecs++;
-        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, j + 1 + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
+        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
                            j, w.V, ldv, w.W, (int64_t)N, w.active, w.part, w.nchunk, ldh, w.Hu, w.coef, w.hp);
         hipLaunchKernelGGL(k_arnoldi_update, dim3(gblk, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk,
                            ldh, w.part, w.V, ldv, w.W, (int64_t)N, w.active, w.Hu, w.H, w.hp, w.coef, 0);
@@ -656,7 +730,7 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
       // u_j alone (no operator application)
       const bool last = j >= restart || total >= maxit;
       if (last) {
-        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, j + 1 + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
+        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
                            j, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.part, w.nchunk, ldh, w.Hu,
                            w.coef, w.hp);
         hipLaunchKernelGGL(k_arnoldi_update, dim3(1, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk, ldh,
@@ -667,7 +741,7 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
       const int c1 = last ? j : j - 1;
       if (c1 <= jfin) continue;
       // rotations for the newly final columns, then their residual estimates
-      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(64), ((size_t)(c1 - jfin) * ldh + 2 * (size_t)c1) * 16, s,
+      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(256), ((size_t)(c1 - jfin) * ldh + 2 * (size_t)c1) * 16, s,
                          ldh, jfin, c1, w.active, w.H, w.cs, w.sn, w.g, w.resid);
       AIM_HIP_CHECK(hipGetLastError());
       for (int r = 0; r < nrhs; ++r)

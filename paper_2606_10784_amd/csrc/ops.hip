@@ -403,7 +403,17 @@ __global__ __launch_bounds__(256) void k_anterp(int n_act, int nrhs, const int32
   const double2* xr = x + (size_t)r * ldx;
   T sx = 0, sy = 0;
   const int e1 = at_ptr[a + 1];
-  for (int e = at_ptr[a] + l; e < e1; e += 16) {
+  int e = at_ptr[a] + l;
+  for (; e + 16 < e1; e += 32) {   // two entries per lane in flight
+    const int b0 = at_basis[e], b1 = at_basis[e + 16];
+    const T w0e = (T)w[e], w1e = (T)w[e + 16];
+    const double2 x0 = xr[b0], x1 = xr[b1];
+    sx += w0e * (T)x0.x;
+    sy += w0e * (T)x0.y;
+    sx += w1e * (T)x1.x;
+    sy += w1e * (T)x1.y;
+  }
+  if (e < e1) {
     const double2 xv = xr[at_basis[e]];
     const T ww = (T)w[e];
     sx += ww * (T)xv.x;
@@ -452,7 +462,17 @@ __global__ __launch_bounds__(256) void k_interp_near(
       }
     }
     const double2* xr = x + (size_t)r * ldx;
-    for (int q = q0 + l; q < q1; q += LANES) {
+    int q = q0 + l;
+    for (; q + LANES < q1; q += 2 * LANES) {   // two entries per lane in flight
+      const int k0 = ncol[q], k1 = ncol[q + LANES];
+      const double2 c0 = C[q], c1 = C[q + LANES];
+      const double2 x0 = xr[k0], x1 = xr[k1];
+      ax += c0.x * x0.x - c0.y * x0.y;
+      ay += c0.x * x0.y + c0.y * x0.x;
+      ax += c1.x * x1.x - c1.y * x1.y;
+      ay += c1.x * x1.y + c1.y * x1.x;
+    }
+    if (q < q1) {
       const double2 cv = C[q];
       const double2 xv = xr[ncol[q]];
       ax += cv.x * xv.x - cv.y * xv.y;
