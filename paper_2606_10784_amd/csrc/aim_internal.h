@@ -39,6 +39,29 @@ template <typename V, typename S>
 __host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
 
 // ---------------------------------------------------------------------------
+// Frequency order of the column FFT.  The column pass runs a decimation-in-
+// frequency FFT of length n = 16^P * RL (radix 16 P times, then RL in 2..16)
+// in place, so position p holds frequency ky_of_pos(n, p): with
+// p = RL * (16^{P-1} k_1 + ... + k_P) + k_{P+1}, ky = k_1 + 16 k_2 + ... +
+// 16^{P-1} k_P + 16^P k_{P+1}.  The spectrum is stored in this order.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int ky_of_pos(int n, int p) {
+  int rl = n, P = 0;
+  while (rl > 16) {
+    rl >>= 4;
+    ++P;
+  }
+  const int klast = p % rl;
+  int rest = p / rl, ky = 0;
+  for (int i = 0; i < P; ++i) {   // rest = k_1 ... k_P, most significant first
+    ky = (ky << 4) | (rest & 15);
+    rest >>= 4;
+  }
+  // the loop reversed the digit order: ky now holds k_P ... k_1 with k_1 lowest
+  return ky + (klast << (4 * P));
+}
+
+// ---------------------------------------------------------------------------
 // host-side geometry and tables produced by aim_setup (host_setup.cpp)
 // ---------------------------------------------------------------------------
 struct HostTables {
@@ -113,7 +136,8 @@ struct Ctx {
   int32_t *d_at_ptr = nullptr, *d_at_basis = nullptr;
   double* d_at_w[4] = {nullptr, nullptr, nullptr, nullptr};
   float* d_at_wf[4] = {nullptr, nullptr, nullptr, nullptr};
-  // spectra (quarter, [kxq][kyq], pre-scaled by 1/n^2)
+  // spectra: [kxq][p] for kxq <= n/2 and p < n, frequency ky_of_pos(n, p),
+  // pre-scaled by 1/n^2
   double2 *d_C = nullptr, *d_Ca = nullptr, *own_Ca = nullptr;
   float2 *d_Cf = nullptr, *d_Caf = nullptr, *own_Caf = nullptr;
   void* spec = nullptr;          // shared spectrum cache entry

@@ -308,6 +308,58 @@ __device__ __forceinline__ void passes16(cplx<T>* buf, const cplx<T>* __restrict
   }
 }
 
+// One in-place Cooley-Tukey pass with stride S and radix R: butterfly
+// (block, m) owns positions blk S R + m + S r.  Forward (decimation in
+// frequency): R-point DFT, then output k times W_{SR}^{m k}.  Inverse
+// (decimation in time, the exact reverse): input k times W_{SR}^{-m k}, then
+// the inverse R-point DFT.  Each thread writes back the positions it read, so
+// one barrier per pass suffices.
+template <typename T, int N, int NCOL, int NT, bool INV, int S, int R>
+__device__ __forceinline__ void ct_pass(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
+  constexpr int NB = (N / R) * NCOL;
+  constexpr int PER = (NB + NT - 1) / NT;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if ((NB % NT) == 0 || b < NB) {
+      const int c = b % NCOL, t = b / NCOL;
+      const int m = t % S, base = (t / S) * S * R + m;
+      V v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = buf[pidx((base + S * r) * NCOL + c)];
+      if (!INV) {
+        dft_r<T, R, false>(v);
+        pass_twiddle<T, N, false, S, R>(v, m, tw);
+      } else {
+        pass_twiddle<T, N, true, S, R>(v, m, tw);
+        dft_r<T, R, true>(v);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx((base + S * r) * NCOL + c)] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
+// radix-16 forward passes with strides S, S/16, ... down to SEND (inclusive)
+template <typename T, int N, int NCOL, int NT, int S, int SEND>
+__device__ __forceinline__ void dif16_down(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+  if constexpr (S >= SEND && S >= 1) {
+    ct_pass<T, N, NCOL, NT, false, S, 16>(buf, tw);
+    dif16_down<T, N, NCOL, NT, S / 16, SEND>(buf, tw);
+  }
+}
+
+// radix-16 inverse passes with strides S, 16 S, ... up to SEND (inclusive)
+template <typename T, int N, int NCOL, int NT, int S, int SEND>
+__device__ __forceinline__ void dit16_up(cplx<T>* buf, const cplx<T>* __restrict__ tw) {
+  if constexpr (S <= SEND && S >= 1) {
+    ct_pass<T, N, NCOL, NT, true, S, 16>(buf, tw);
+    dit16_up<T, N, NCOL, NT, S * 16, SEND>(buf, tw);
+  }
+}
+
 // radix of the remainder pass: N = 16^p * last_radix(N), last_radix in 2..16
 template <int N> constexpr int last_radix() {
   if constexpr (N <= 16) return N;
@@ -497,7 +549,9 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 
 // Pass 2 (MODE 0): column FFT, spectrum multiply, inverse column FFT, in
 // place on one tile [row][CB] of T (nr <= N/2 rows kept, the rest is the
-// zero padding).  Cq: quarter spectrum [kxq][kyq].
+// zero padding).  The column FFT is an in-place decimation in frequency, so
+// the spectrum Cq is read in its stored order [kxq][p] (frequency
+// ky_of_pos(N, p)), and the inverse is the matching decimation in time.
 // MODE 1 (set-up): plain forward FFT of CB consecutive columns of a
 // row-major N x N array.
 template <typename T, int N, int MODE>
@@ -516,20 +570,21 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
   if constexpr (MODE == 0) {
     static_assert(N >= 32, "column pass assumes at least two forward passes");
     constexpr int RL = last_radix<N>();
+    constexpr int S1 = N / 16;
     V* tile = Tb + ((size_t)pair * NBLK + b) * nr * CB;
-    // forward pass 1 (NS = 1, radix 16) from HBM: inputs j + r N/16 with
+    // forward pass 1 (stride N/16, radix 16) from HBM: inputs m + S1 r with
     // r >= 8 lie in the zero half
     {
-      constexpr int NB = (N / 16) * CB, PER = (NB + NT - 1) / NT;
+      constexpr int NB = S1 * CB, PER = (NB + NT - 1) / NT;
       V v[PER][16];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int bb = tid + q * NT;
         if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, j = bb / CB;
+          const int c = bb % CB, m = bb / CB;
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
-            const int i = j + r * (N / 16);
+            const int i = m + r * S1;
             v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
           }
         }
@@ -538,73 +593,61 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
       for (int q = 0; q < PER; ++q) {
         const int bb = tid + q * NT;
         if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, j = bb / CB;
+          const int c = bb % CB, m = bb / CB;
           dft16_halfin<T, false>(v[q]);
+          pass_twiddle<T, N, false, S1, 16>(v[q], m, tw);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) buf[pidx((j * 16 + r) * CB + c)] = v[q][r];
+          for (int r = 0; r < 16; ++r) buf[pidx((m + r * S1) * CB + c)] = v[q][r];
         }
       }
       __syncthreads();
     }
-    passes16<T, N, CB, NT, false, 16, N / RL>(buf, tw);
-    // last forward pass (NS = N/RL) leaves butterfly j holding ky = j + r N/RL,
-    // exactly the inputs of the first inverse pass (NS = 1, radix RL)
+    dif16_down<T, N, CB, NT, N / 256, RL>(buf, tw);
+    // last forward pass (contiguous groups of RL), spectrum multiply in the
+    // stored frequency order, first inverse pass; lanes run along the groups
     {
-      constexpr int R = RL, NS = N / RL, NB = NS * CB, PER = (NB + NT - 1) / NT;
-      V v[PER][R];
+      constexpr int R = RL, NG = N / RL, NB = NG * CB, PER = (NB + NT - 1) / NT;
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int bb = tid + q * NT;
         if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, j = bb / CB;
+          const int g = bb % NG, c = bb / NG;
           int kx, kxq;
           col_of(b, c, N, CB, kx, kxq);
-          const V* Cp = Cq + (size_t)kxq * H;
-          V cv[R];
+          const V* Cp = Cq + (size_t)kxq * N + (size_t)g * R;
+          V cv[R], v[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int ky = j + r * NS;
-            cv[r] = Cp[ky <= N / 2 ? ky : N - ky];
-          }
+          for (int r = 0; r < R; ++r) cv[r] = Cp[r];
 #pragma unroll
-          for (int r = 0; r < R; ++r) v[q][r] = buf[pidx((j + r * NS) * CB + c)];
-          pass_twiddle<T, N, false, NS, R>(v[q], j, tw);
-          dft_r<T, R, false>(v[q]);
+          for (int r = 0; r < R; ++r) v[r] = buf[pidx((g * R + r) * CB + c)];
+          dft_r<T, R, false>(v);
 #pragma unroll
-          for (int r = 0; r < R; ++r) v[q][r] = cmul(v[q][r], cv[r]);
-          dft_r<T, R, true>(v[q]);
-        }
-      }
-      __syncthreads();
+          for (int r = 0; r < R; ++r) v[r] = cmul(v[r], cv[r]);
+          dft_r<T, R, true>(v);
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, j = bb / CB;
-#pragma unroll
-          for (int r = 0; r < R; ++r) buf[pidx((j * R + r) * CB + c)] = v[q][r];
+          for (int r = 0; r < R; ++r) buf[pidx((g * R + r) * CB + c)] = v[r];
         }
       }
       __syncthreads();
     }
-    passes16<T, N, CB, NT, true, RL, N / 16>(buf, tw);
-    // last inverse pass (NS = N/16, radix 16) straight to HBM: outputs
-    // j + r N/16, only r < 8 can be a kept row
+    dit16_up<T, N, CB, NT, RL, N / 256>(buf, tw);
+    // last inverse pass (stride N/16, radix 16) straight to HBM: outputs
+    // m + S1 r, only r < 8 can be a kept row
     {
-      constexpr int NS = N / 16, NB = NS * CB, PER = (NB + NT - 1) / NT;
+      constexpr int NB = S1 * CB, PER = (NB + NT - 1) / NT;
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int bb = tid + q * NT;
         if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, j = bb / CB;
+          const int c = bb % CB, m = bb / CB;
           V v[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) v[r] = buf[pidx((j + r * NS) * CB + c)];
-          pass_twiddle<T, N, true, NS, 16>(v, j, tw);
+          for (int r = 0; r < 16; ++r) v[r] = buf[pidx((m + r * S1) * CB + c)];
+          pass_twiddle<T, N, true, S1, 16>(v, m, tw);
           dft16_halfout<T, true>(v);
 #pragma unroll
           for (int r = 0; r < 8; ++r) {
-            const int i = j + r * NS;
+            const int i = m + r * S1;
             if (i < nr) tile[(size_t)i * CB + c] = v[r];
           }
         }
