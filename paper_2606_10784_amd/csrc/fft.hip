@@ -467,13 +467,24 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     __syncthreads();
   }
   fft_passes<T, N, 1, NT, false, 16>(buf, tw);
-  // pairs of lanes fill the CB-wide segments of the tiled layout
+  // pairs of lanes fill the CB-wide segments of the tiled layout; the LDS
+  // reads of a thread are all issued before its stores
   V* out = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
-  for (int idx = tid; idx < N; idx += NT) {
-    const int bk = idx / CB, c = idx % CB;
-    int kx, kxq;
-    col_of(bk, c, N, CB, kx, kxq);
-    out[(size_t)bk * nr * CB + c] = buf[pidx(kx)];
+  constexpr int PER = (N + NT - 1) / NT;
+  V v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + q * NT;
+    if ((N % NT) == 0 || idx < N) {
+      int kx, kxq;
+      col_of(idx / CB, idx % CB, N, CB, kx, kxq);
+      v[q] = buf[pidx(kx)];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + q * NT;
+    if ((N % NT) == 0 || idx < N) out[(size_t)(idx / CB) * nr * CB + idx % CB] = v[q];
   }
 }
 
@@ -496,11 +507,24 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
   const int tid = threadIdx.x;
   if (row >= nr) return;
   const V* in = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
-  for (int idx = tid; idx < N; idx += NT) {
-    const int bk = idx / CB, c = idx % CB;
-    int kx, kxq;
-    col_of(bk, c, N, CB, kx, kxq);
-    buf[pidx(kx)] = in[(size_t)bk * nr * CB + c];
+  {
+    // all HBM loads of a thread in flight before its LDS stores
+    constexpr int PER = (N + NT - 1) / NT;
+    V v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * NT;
+      if ((N % NT) == 0 || idx < N) v[q] = in[(size_t)(idx / CB) * nr * CB + idx % CB];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * NT;
+      if ((N % NT) == 0 || idx < N) {
+        int kx, kxq;
+        col_of(idx / CB, idx % CB, N, CB, kx, kxq);
+        buf[pidx(kx)] = v[q];
+      }
+    }
   }
   __syncthreads();
   stockham_pass<T, N, 1, NT, true, 1, RL>(buf, tw);
