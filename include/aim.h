@@ -100,6 +100,9 @@ typedef struct {
   int64_t near_nnz_s, near_nnz_n;   /* nonzeros of the near-field corrections   */
   double k, eps, alpha;             /* alpha = +inf when no filter is set        */
   size_t device_bytes;              /* bytes held on the device by the context   */
+  int32_t near_band;                /* near field kept as a symmetric cyclic band
+                                       of this half-width (bases are numbered
+                                       along the contour), or -1: CSR only        */
 } aim_ctx_info;
 
 typedef struct {

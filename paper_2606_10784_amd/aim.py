@@ -50,7 +50,8 @@ class AimCtxInfo(ctypes.Structure):
     _fields_ = [("n_unknowns", ctypes.c_int32), ("m", ctypes.c_int32), ("n_pad", ctypes.c_int32),
                 ("n_active", ctypes.c_int32), ("active_rows", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("near_nnz_s", ctypes.c_int64), ("near_nnz_n", ctypes.c_int64), ("k", ctypes.c_double),
-                ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+                ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
+                ("near_band", ctypes.c_int32)]
 
 
 class AimSolveInfo(ctypes.Structure):

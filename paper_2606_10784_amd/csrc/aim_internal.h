@@ -81,6 +81,7 @@ struct HostTables {
   std::vector<double> at_w[4];
   // near zone (CSR over basis rows, sorted columns)
   std::vector<int32_t> nr_ptr, nr_col;
+  int band_w = -1;                            // banded symmetric near field: half-width, -1 = CSR
   std::vector<double> gl_x, gl_w;             // stencil quadrature rule on [0,1]
 };
 
@@ -148,6 +149,8 @@ struct Ctx {
   // near field
   int32_t *d_nr_ptr = nullptr, *d_nr_col = nullptr;
   double2 *d_CS = nullptr, *d_CN = nullptr;
+  // banded symmetric copies [d][i] = C(i, (i + d) mod N), d <= band_w
+  double2 *d_CSd = nullptr, *d_CNd = nullptr;
   int64_t nnz = 0;
   // matvec work (sized for max_rhs x nch_max)
   void *d_U = nullptr, *d_T = nullptr, *d_V = nullptr;

@@ -34,6 +34,7 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   b += nch * R * (nr * n + 2 * nact) * 16;               // U, T, V
   b += 2 * H * n * 16 * (p->precision == AIM_MIXED ? 1.5 : 1.0);
   b += near * (4 + 16 * (p->basis == AIM_HAT ? 2 : 1));
+  if (t && t->band_w >= 0) b += (size_t)(t->band_w + 1) * N * 16 * (p->basis == AIM_HAT ? 2 : 1);
   b += N * 16 * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
   b += 3 * N * R * 16;
   b += (size_t)R * (restart + 1) * N * 16 + (size_t)5 * R * N * 16;
@@ -137,6 +138,7 @@ aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info) {
   info->eps = c.t.eps;
   info->alpha = c.filtered ? c.alpha : INFINITY;
   info->device_bytes = c.dev_bytes;
+  info->near_band = c.t.band_w;
   return AIM_OK;
 }
 

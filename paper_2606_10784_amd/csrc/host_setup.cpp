@@ -248,6 +248,21 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
     t.nr_col.insert(t.nr_col.end(), cols.begin(), cols.end());
     t.nr_ptr[i + 1] = (int32_t)t.nr_col.size();
   }
+  // Banded symmetric storage of the near field when it pays: bases are
+  // numbered along the contour, so near pairs have a small cyclic index
+  // distance |i - j|_N <= w, and the near matrices are symmetric (Galerkin,
+  // same test and trial functions; symmetric pattern).  Row i then keeps
+  // only C(i, i + d), d = 0..w, and borrows C(i - d, i) for the other half.
+  {
+    int w = 0;
+    for (int i = 0; i < N; ++i)
+      for (int q = t.nr_ptr[i]; q < t.nr_ptr[i + 1]; ++q) {
+        const int d = ((t.nr_col[q] - i) % N + N) % N;
+        w = std::max(w, std::min(d, N - d));
+      }
+    const double dia_bytes = (double)(w + 1) * N * 16, csr_bytes = (double)t.nr_col.size() * 20;
+    t.band_w = (2 * w + 1 < N && dia_bytes <= 0.75 * csr_bytes) ? w : -1;
+  }
   return AIM_OK;
 }
 

@@ -489,6 +489,74 @@ __global__ __launch_bounds__(256) void k_interp_near(
 }
 
 // ---------------------------------------------------------------------------
+// banded symmetric near field: Cd[d][i] = C(i, (i + d) mod N) for d <= w
+// ---------------------------------------------------------------------------
+__global__ void k_near_to_band(int64_t nnz, int N, int w, const int32_t* __restrict__ rows,
+                               const int32_t* __restrict__ cols, const double2* __restrict__ C,
+                               double2* __restrict__ Cd) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  const int i = rows[q];
+  int d = cols[q] - i;
+  if (d < 0) d += N;
+  if (d <= w) Cd[(size_t)d * N + i] = C[q];
+}
+
+// interpolation + banded near field, 16 lanes per basis row:
+//   y_i = scale * ( sum_ch sgn_ch W_ch . V_ch + sum_{d<=w} Cd[d][i] x_{i+d}
+//                   + sum_{1<=d<=w} Cd[d][i-d] x_{i-d} )   (indices mod N)
+template <typename T, typename TW>
+__global__ __launch_bounds__(256) void k_interp_band(
+    int N, int nrhs, int nch, const TW* __restrict__ W0, const TW* __restrict__ W1, const TW* __restrict__ W2,
+    double sg, const int32_t* __restrict__ aidx, const cplx<T>* __restrict__ V, int n_act, int w,
+    const double2* __restrict__ Cd, const double2* __restrict__ x, int64_t ldx, double2* __restrict__ y,
+    int64_t ldy, double2 scale) {
+  constexpr int L = 16;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = gid / L, l = gid % L;
+  if (row >= N) return;          // whole lane groups exit together
+  const size_t o = (size_t)row * 16 + l;
+  const int a = aidx[o];
+  const double w0 = (double)W0[o];
+  const double w1 = nch > 1 ? (double)W1[o] : 0.0;
+  const double w2 = nch > 1 ? (double)W2[o] : 0.0;
+  for (int r = 0; r < nrhs; ++r) {
+    const cplx<T> v0 = V[(size_t)r * n_act + a];
+    double ax = w0 * (double)v0.x, ay = w0 * (double)v0.y;
+    if (nch > 1) {
+      const cplx<T> v1 = V[(size_t)(nrhs + r) * n_act + a];
+      const cplx<T> v2 = V[(size_t)(2 * nrhs + r) * n_act + a];
+      ax += sg * (w1 * (double)v1.x + w2 * (double)v2.x);
+      ay += sg * (w1 * (double)v1.y + w2 * (double)v2.y);
+    }
+    if (Cd) {
+      const double2* xr = x + (size_t)r * ldx;
+      for (int d = l; d <= w; d += L) {
+        int ju = row + d;
+        if (ju >= N) ju -= N;
+        const double2 cu = Cd[(size_t)d * N + row], xu = xr[ju];
+        ax += cu.x * xu.x - cu.y * xu.y;
+        ay += cu.x * xu.y + cu.y * xu.x;
+        const int dl = d + 1;                      // lower half: C(i - dl, i), dl = 1..w
+        if (dl <= w) {
+          int il = row - dl;
+          if (il < 0) il += N;
+          const double2 cl = Cd[(size_t)dl * N + il], xl = xr[il];
+          ax += cl.x * xl.x - cl.y * xl.y;
+          ay += cl.x * xl.y + cl.y * xl.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) {
+      ax += __shfl_xor(ax, off, L);
+      ay += __shfl_xor(ay, off, L);
+    }
+    if (l == 0) y[(size_t)r * ldy + row] = make_double2(scale.x * ax - scale.y * ay, scale.x * ay + scale.y * ax);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Gram solve
 // ---------------------------------------------------------------------------
 __global__ void k_gram_pulse(int N, int nrhs, const double* h, const double2* x, int64_t ldx, double2* y,
@@ -877,6 +945,19 @@ aim_status setup_device(Ctx* c) {
                          d_rows, c->d_nr_col, d_anx, d_any, c->d_W[0], c->d_W[1], c->d_W[2], c->d_W[3],
                          c->d_ksmall, c->ks, c->d_CS, c->d_CN);
     }
+    if (t.band_w >= 0 && nnz > 0) {
+      const size_t bb = (size_t)(t.band_w + 1) * N * sizeof(double2);
+      TRY(dev_alloc(c, (void**)&c->d_CSd, bb));
+      AIM_HIP_CHECK(hipMemsetAsync(c->d_CSd, 0, bb, s));
+      hipLaunchKernelGGL(k_near_to_band, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, N, t.band_w,
+                         d_rows, c->d_nr_col, c->d_CS, c->d_CSd);
+      if (t.basis == AIM_HAT) {
+        TRY(dev_alloc(c, (void**)&c->d_CNd, bb));
+        AIM_HIP_CHECK(hipMemsetAsync(c->d_CNd, 0, bb, s));
+        hipLaunchKernelGGL(k_near_to_band, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, N, t.band_w,
+                           d_rows, c->d_nr_col, c->d_CN, c->d_CNd);
+      }
+    }
     hipError_t e = hipStreamSynchronize(s);
     hipFree(d_rows);
     hipFree(d_anx);
@@ -989,6 +1070,22 @@ static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near
                          const double2* x, int64_t ldx, double2* y, int64_t ldy, double2 scale) {
   const double2* C = near ? Cn : nullptr;
   ProfScope ps(c, AIM_K_INTERP);
+  const HostTables& t = c->t;
+  if (t.band_w >= 0) {
+    // banded symmetric near field (or none)
+    const double2* Cd = !near ? nullptr : (Cn == c->d_CS ? c->d_CSd : c->d_CNd);
+    dim3 g((unsigned)(((size_t)t.N * 16 + 255) / 256));
+    if (sizeof(T) == 4)
+      hipLaunchKernelGGL((k_interp_band<T, float>), g, dim3(256), 0, c->stream, t.N, nrhs, nch,
+                         c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
+                         c->d_aidx, (const cplx<T>*)c->d_V, t.n_act, t.band_w, Cd, x, ldx, y, ldy, scale);
+    else
+      hipLaunchKernelGGL((k_interp_band<T, double>), g, dim3(256), 0, c->stream, t.N, nrhs, nch,
+                         c->d_W[chans[0]], c->d_W[chans[nch > 1 ? 1 : 0]], c->d_W[chans[nch > 2 ? 2 : 0]], sg,
+                         c->d_aidx, (const cplx<T>*)c->d_V, t.n_act, t.band_w, Cd, x, ldx, y, ldy, scale);
+    AIM_HIP_CHECK(hipGetLastError());
+    return AIM_OK;
+  }
   // wide lane groups when the near-field rows are long
   const bool wide = near && c->nnz >= (int64_t)40 * c->t.N;
   if (wide) launch_interp<T, 64>(c, chans, nch, sg, C, nrhs, x, ldx, y, ldy, scale);

@@ -213,3 +213,31 @@ def test_hat_gram_small_n_path():
     x = wl.probe_vector(90, seed=3)
     y = _n(ctx.matvec("GRAM_INV", _t(x)))
     assert _relmax(y, galerkin.gram_solve(xy, 1, x)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# near-field storage: the cylinder and star fixtures run the banded symmetric
+# path; a contour whose near zone wraps around runs the CSR path
+# --------------------------------------------------------------------------
+def test_near_storage_band_selected(cyl, star):
+    for _, _, ctx in (cyl, star):
+        inf = ctx.info()
+        assert inf["near_band"] > 0
+        assert 2 * inf["near_band"] + 1 < inf["n_unknowns"]
+
+
+@pytest.mark.parametrize("basis,ops", [(0, ["S", "S_ALPHA", "TM"]), (1, ["S", "N"])])
+def test_matvec_csr_near_path(basis, ops):
+    # radius 0.15 at eps = 0.1: the near zone (6 cells) covers the whole contour
+    xy = wl.circle(0.15, 24) if basis == 0 else wl.star5(0.15, 26)
+    m, eps = 32, 0.1
+    alpha = wl.alpha_half_bins(eps)
+    orc = oaim.AimOracle(xy, K, ETA, basis, m, eps, alpha=alpha)
+    ctx = aim.Context(xy, K, ETA, basis, m, eps)
+    ctx.filter(alpha)
+    assert ctx.info()["near_band"] == -1
+    x = wl.probe_vector(xy.shape[0], seed=11)
+    for op in ops:
+        y = _n(ctx.matvec(op, _t(x)))
+        assert _relmax(y, orc.apply(op, x)) < 1e-12, op
+    ctx.close()
