@@ -165,6 +165,24 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
 aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev,
                               const double* phi_host, double* sigma_host);
 
+/* Spectrum of an operator in the Fourier (Laplace-Beltrami) basis of a closed
+   contour whose N bases are numbered along it, as in the paper's Sec. IV
+   experiments (Figs. 2 and 3, the singular values of S, S^alpha and the
+   Calderon products ordered by the Laplace-Beltrami eigenvectors).  For each
+   nu_host[q], q < n_modes, with e[j] = exp(i 2 pi nu j / N):
+     lambda_q = (e^H G^-1 A e) / (e^H e)   for A = AIM_OP_S, AIM_OP_S_ALPHA,
+                                           AIM_OP_N, AIM_OP_TM (G: Gram matrix),
+     lambda_q = (e^H A e) / (e^H e)        for AIM_OP_TE_CP, AIM_OP_TE_CP_UNF.
+   On a uniformly discretised circle the matrices are circulant, e is an
+   exact eigenvector, |lambda_q| is a singular value and, for the Galerkin
+   operators, lambda_q approximates the continuous operator's eigenvalue.
+   AIM_OP_GRID_FP32 may be or-ed in (AIM_MIXED contexts).  Modes are applied
+   max_rhs at a time through aim_matvec's kernels.  lambda_host: n_modes
+   interleaved complex doubles (host).  Synchronous.  Errors: AIM_E_ARG (op,
+   n_modes < 1, basis mismatch as in aim_matvec), AIM_E_OOM, AIM_E_HIP.       */
+aim_status aim_fourier_spectrum(aim_ctx ctx, int32_t op, int32_t n_modes, const int32_t* nu_host,
+                                double* lambda_host);
+
 /* Introspection (sizes, nonzeros, device bytes).                              */
 aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info);
 

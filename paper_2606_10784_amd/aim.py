@@ -77,6 +77,8 @@ EXPORTS = {
                                  ctypes.POINTER(AimSolveInfo)]),
     "aim_rcs_monostatic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "aim_fourier_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimCtxInfo)]),
     "aim_eval_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "aim_near_row": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -212,6 +214,9 @@ class Context:
     def eval_green(self, R):
         return aim_eval_green(self, R)
 
+    def fourier_spectrum(self, op, nus):
+        return aim_fourier_spectrum(self, op, nus)
+
     def near_row(self, op, row):
         return aim_near_row(self, op, row)
 
@@ -273,6 +278,16 @@ def aim_rcs_monostatic(ctx, J, phis):
                                      ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "aim_rcs_monostatic")
     return sig
+
+
+def aim_fourier_spectrum(ctx, op, nus):
+    """lambda_nu of `op` in the contour's Fourier basis (see include/aim.h)."""
+    op = OPS[op] if isinstance(op, str) else int(op)
+    nu = np.ascontiguousarray(np.atleast_1d(np.asarray(nus)).astype(np.int32))
+    out = np.zeros(2 * nu.size)
+    _check(_lib().aim_fourier_spectrum(ctx.handle, op, nu.size, nu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "aim_fourier_spectrum")
+    return out[0::2] + 1j * out[1::2]
 
 
 def aim_eval_green(ctx, R):

@@ -156,6 +156,7 @@ struct Ctx {
   void *d_U = nullptr, *d_T = nullptr, *d_V = nullptr;
   double2 *d_tmp1 = nullptr, *d_tmp2 = nullptr;   // N x max_rhs each
   double2* d_rhs = nullptr;
+  double2* d_spec = nullptr;   // Fourier-spectrum work (modes, products, quotients), on first use
   double* d_red = nullptr;
   size_t dev_bytes = 0;
   GmresWork gw;
@@ -196,6 +197,7 @@ aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, doubl
 aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b);
 aim_status eval_green(Ctx* c, int n, const double* R, double2* out);
 aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma);
+aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host, double2* lambda_host);
 aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
                  int maxit, int restart, aim_solve_info* info);
 void free_ctx(Ctx* c);

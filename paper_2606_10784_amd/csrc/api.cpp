@@ -123,6 +123,12 @@ aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev, cons
   return rcs(&ctx->c, nrhs, (const double2*)j_dev, phi_host, sigma_host);
 }
 
+aim_status aim_fourier_spectrum(aim_ctx ctx, int32_t op, int32_t n_modes, const int32_t* nu_host,
+                                double* lambda_host) {
+  if (!ctx) return AIM_E_ARG;
+  return fourier_spectrum(&ctx->c, op, n_modes, nu_host, (double2*)lambda_host);
+}
+
 aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info) {
   if (!ctx || !info) return AIM_E_ARG;
   const Ctx& c = ctx->c;

@@ -1176,6 +1176,79 @@ aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, d
   return e == hipSuccess ? AIM_OK : AIM_E_HIP;
 }
 
+// ---------------------------------------------------------------------------
+// Fourier (Laplace-Beltrami) spectrum of an operator on a closed contour
+// ---------------------------------------------------------------------------
+// e[r][j] = exp(i 2 pi nu_r j / N), phase reduced exactly: (nu j) mod N
+__global__ void k_fourier_modes(int N, int nrhs, const int32_t* __restrict__ nu, double2* __restrict__ e) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (j >= N || r >= nrhs) return;
+  int64_t q = ((int64_t)nu[r] * j) % N;
+  if (q < 0) q += N;
+  double sn, cs;
+  sincospi(2.0 * (double)q / (double)N, &sn, &cs);
+  e[(size_t)r * N + j] = make_double2(cs, sn);
+}
+
+// out[r] = (1/N) sum_j conj(e[r][j]) y[r][j], fixed reduction order
+__global__ __launch_bounds__(256) void k_mode_quotient(int N, const double2* __restrict__ e,
+                                                       const double2* __restrict__ y, double2* __restrict__ out) {
+  const int r = blockIdx.x;
+  const double2* er = e + (size_t)r * N;
+  const double2* yr = y + (size_t)r * N;
+  double sx = 0.0, sy = 0.0;
+  for (int j = threadIdx.x; j < N; j += 256) {
+    const double2 a = er[j], b = yr[j];
+    sx += a.x * b.x + a.y * b.y;
+    sy += a.x * b.y - a.y * b.x;
+  }
+  __shared__ double rx[256], ry[256];
+  rx[threadIdx.x] = sx;
+  ry[threadIdx.x] = sy;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      rx[threadIdx.x] += rx[threadIdx.x + st];
+      ry[threadIdx.x] += ry[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = make_double2(rx[0] / N, ry[0] / N);
+}
+
+aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host, double2* lambda_host) {
+  const HostTables& t = c->t;
+  const int base = op & 0xff;
+  const bool galerkin = base == AIM_OP_S || base == AIM_OP_S_ALPHA || base == AIM_OP_N || base == AIM_OP_TM;
+  const bool precond = base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF;
+  if (n_modes < 1 || !nu_host || !lambda_host || (!galerkin && !precond)) return AIM_E_ARG;
+  const int N = t.N, R = c->max_rhs;
+  if (!c->d_spec) TRY(dev_alloc(c, (void**)&c->d_spec, ((size_t)3 * N * R + 2 * (size_t)R) * sizeof(double2)));
+  double2* E = c->d_spec;                      // modes
+  double2* Y = E + (size_t)N * R;              // op e
+  double2* Z = Y + (size_t)N * R;              // G^-1 op e
+  double2* Q = Z + (size_t)N * R;              // quotients
+  int32_t* nud = (int32_t*)(Q + R);
+  for (int m0 = 0; m0 < n_modes; m0 += R) {
+    const int nr = std::min(R, n_modes - m0);
+    AIM_HIP_CHECK(hipMemcpyAsync(nud, nu_host + m0, nr * 4, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_fourier_modes, dim3((N + 255) / 256, nr), dim3(256), 0, c->stream, N, nr, nud, E);
+    AIM_HIP_CHECK(hipGetLastError());
+    TRY(matvec(c, op, nr, E, N, Y, N));
+    const double2* out = Y;
+    if (galerkin) {   // quotient of G^-1 op: the continuous operator's eigenvalue on the circle
+      TRY(matvec(c, AIM_OP_GRAM_INV, nr, Y, N, Z, N));
+      out = Z;
+    }
+    hipLaunchKernelGGL(k_mode_quotient, dim3(nr), dim3(256), 0, c->stream, N, E, out, Q);
+    AIM_HIP_CHECK(hipGetLastError());
+    AIM_HIP_CHECK(hipMemcpyAsync(lambda_host + m0, Q, nr * 16, hipMemcpyDeviceToHost, c->stream));
+    AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  }
+  return AIM_OK;
+}
+
 aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma) {
   HostTables& t = c->t;
   if (t.basis != AIM_PULSE || nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
