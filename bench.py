@@ -30,7 +30,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cylinder_ka200",
-                    choices=["cylinder_ka200", "cylinder_ka2pi", "star_te", "cylinder_ka200_360rhs"],
+                    choices=["cylinder_ka200", "cylinder_ka2pi", "star_te", "cylinder_ka200_360rhs", "spectrum"],
                     help="cylinder_ka200: the benchmark line; the others are separate measurements")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=400)
@@ -111,17 +111,22 @@ def kernel_flops(kid, inf):
     return 0.0
 
 
+def _host_threads():
+    """Threads the oracle's numpy/scipy calls use."""
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(w, sample_every=64, reps=2):
     """Oracle AIM matvec on the host: full direct-Toeplitz grid product plus
     the near-field product of every `sample_every`-th row (scaled)."""
     import numpy as np
     from oracle import aim as oaim
     from paper_2606_10784_amd import workloads as wl
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    threads = _host_threads()
     A = oaim.AimOracle(w.xy, w.k, w.eta, w.basis, w.m, w.eps, alpha=w.alpha, near=False)
     rows = np.arange(0, w.n_unknowns, sample_every)
     A.near_pairs = A._near_pairs()
@@ -184,7 +189,6 @@ def batched_360(args):
     solve: FP64 and FP32-grid + FP64 refinement, monostatic RCS."""
     import numpy as np
     import torch
-    from oracle import mie
     from paper_2606_10784_amd import aim
     from paper_2606_10784_amd import workloads as wl
     w = wl.cylinder_large()
@@ -207,15 +211,67 @@ def batched_360(args):
         X, infos = ctx.solve("TM", B, tol=args.tol, restart=args.restart, precision=prec)
         dt = time.perf_counter() - t0
         sig = ctx.rcs(X, phis)
-        ex = mie.mie_tm_backscatter(w.k, 200.0 / w.k)
         out["solves"][lab] = {"seconds": dt, "rhs_solves_per_s": R / dt,
                               "iterations_max": max(d["iterations"] for d in infos),
                               "converged": sum(d["converged"] for d in infos),
                               "resid_true_max": max(d["resid_true"] for d in infos),
-                              "rcs_min": float(sig.min()), "rcs_max": float(sig.max()), "rcs_mie": ex}
+                              "rcs_min": float(sig.min()), "rcs_max": float(sig.max())}
         print(f"[bench] 360 rhs {lab}: {dt:.2f}s", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def spectrum(args):
+    """The paper's Sec. IV spectra at its parameters: every Fourier mode
+    0..N/2 of S and S^alpha (pulses, Fig. 2) and of G^-1 S G^-1 N and
+    G^-1 S^alpha G^-1 N (hats, Fig. 3) through aim_fourier_spectrum, modes/s,
+    and the oracle's quotient for a few modes timed on the host."""
+    import numpy as np
+    import torch
+    from paper_2606_10784_amd import aim
+    from paper_2606_10784_amd import workloads as wl
+    out = {"workload": "paper_circle_spectrum", "spectra": {}}
+    nmax = None
+    for basis, ops in ((wl.PULSE, ("S", "S_ALPHA")), (wl.HAT, ("TE_CP_UNF", "TE_CP"))):
+        w = wl.paper_circle(basis)
+        N = w.n_unknowns
+        nus = np.arange(0, N // 2 + 1)
+        nmax = N // 2
+        t0 = time.perf_counter()
+        ctx = aim.Context(w.xy, w.k, w.eta, basis, w.m, w.eps, quad=w.quad, max_rhs=64)
+        ctx.filter(w.alpha)
+        t_setup = time.perf_counter() - t0
+        for op in ops:
+            ctx.fourier_spectrum(op, nus[:8])   # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam = ctx.fourier_spectrum(op, nus)
+            dt = time.perf_counter() - t0
+            mag = np.abs(lam)
+            aa = w.alpha * 1.0   # radius 1 m
+            sel = lambda lo, hi: mag[(nus >= lo) & (nus <= hi)]
+            out["spectra"][op] = {
+                "N": N, "modes": int(nus.size), "seconds": dt, "modes_per_s": nus.size / dt,
+                "abs_lambda_at": {str(int(v)): float(mag[int(v)]) for v in (0, round(aa / 2), round(aa), nmax)},
+                "max_abs_past_1.2_alpha_a_over_abs_lambda0": float(sel(1.2 * aa, nmax).max() / mag[0]),
+                "setup_s": t_setup}
+            print(f"[bench] spectrum {op}: {nus.size} modes in {dt*1e3:.1f} ms", file=sys.stderr, flush=True)
+        ctx.close()
+    if not args.no_cpu_baseline:
+        # the oracle's quotient of S^alpha for 4 modes on the host
+        from oracle import aim as oaim
+        w = wl.paper_circle(wl.PULSE)
+        N = w.n_unknowns
+        A = oaim.AimOracle(w.xy, w.k, w.eta, wl.PULSE, w.m, w.eps, alpha=w.alpha, near=False)
+        th = 2 * math.pi * np.arange(N) / N
+        t0 = time.perf_counter()
+        for nu in (0, 17, 45, 90):
+            e = np.exp(1j * nu * th)
+            np.vdot(e, A.gram_inv(A.op_S_alpha(e))) / N
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 4 / dt, "unit": "modes/s (S_ALPHA)", "cores": _host_threads(),
+                               "kind": "oracle", "sample": "4 Fourier modes of S^alpha at the paper's parameters"}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -233,6 +289,8 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "spectrum":
+        return spectrum(args)
     if args.workload == "star_te":
         return star_te(args)
     if args.workload == "cylinder_ka200_360rhs":
