@@ -132,3 +132,33 @@ def test_te_calderon_mixed(te):
     res = np.linalg.norm(bp - orc.apply('TE_CP', _n(x))) / np.linalg.norm(bp)
     print("te mixed", info[0], res)
     assert res < 1.05e-7
+
+
+@pytest.mark.parametrize("restart", [7, 23])
+def test_tm_short_restart_cycles(tm, restart):
+    """Restart lengths that do not divide the residual-check batch: every
+    cycle ends by finalising its last Hessenberg column on its own."""
+    w, orc, ctx, b, x_or = tm
+    x, info = ctx.solve("TM", _t(b), tol=1e-8, restart=restart, maxit=20000)
+    res = np.linalg.norm(b - orc.apply('TM', _n(x))) / np.linalg.norm(b)
+    print("restart", restart, "iters", info[0]['iterations'], "restarts", info[0]['restarts'], "resid", res)
+    assert info[0]['converged'] == 1
+    assert info[0]['restarts'] > 1
+    assert res < 1.5e-8
+
+
+def test_tm_maxit_mid_cycle(tm):
+    w, orc, ctx, b, x_or = tm
+    x, info = ctx.solve("TM", _t(b), tol=1e-12, restart=10, maxit=13)
+    assert info[0]['converged'] == 0
+    assert info[0]['iterations'] == 13
+    res = np.linalg.norm(b - orc.apply('TM', _n(x))) / np.linalg.norm(b)
+    assert abs(res - info[0]['resid_true']) < 1e-8 * max(res, 1e-300) + 1e-12
+    assert res < 1.0
+
+
+def test_tm_solve_deterministic(tm):
+    w, orc, ctx, b, x_or = tm
+    x1, _ = ctx.solve("TM", _t(b), tol=1e-6, restart=50)
+    x2, _ = ctx.solve("TM", _t(b), tol=1e-6, restart=50)
+    assert torch.equal(x1, x2)
