@@ -135,6 +135,16 @@ aim_status aim_setup(const aim_params* p, aim_ctx* out);
    or NaN).                                                                    */
 aim_status aim_filter(aim_ctx ctx, double alpha);
 
+/* The alternative of Fig. 1(a): the grid kernel sampled from the analytically
+   filtered Green's function of eq. (6), c^alpha[d] = g^alpha(eps |d|)
+   (regular at d = 0, which keeps its value), embedded with the zero ring and
+   transformed like c_grid; it replaces F(c_grid^alpha) for AIM_OP_S_ALPHA and
+   the TE-CP operator until the next aim_filter / aim_filter_analytic.  The
+   principal-value integral over [0, alpha] is evaluated on the device by
+   Gauss-Legendre panels.  Synchronous.  Errors: AIM_E_ARG (alpha <= k or not
+   finite), AIM_E_OOM, AIM_E_HIP.                                              */
+aim_status aim_filter_analytic(aim_ctx ctx, double alpha);
+
 /* y = op(x) for nrhs columns (1 <= nrhs <= max_rhs); x_dev and y_dev are
    c128 N x nrhs device arrays and must not overlap.  Asynchronous.  Errors:
    AIM_E_ARG (op invalid for the basis or precision), AIM_E_STATE.             */

@@ -32,10 +32,14 @@ the filtered kernel values come from one inverse DFT of the masked spectrum
 (the definition of c^alpha).  An FFT form of eq. (8) is kept only as a
 cross-check.
 
+The alternative of Fig. 1(a), a grid kernel sampled from the analytically
+filtered g^alpha of eq. (6), is analytic_filtered_table.
+
 Pinned by: tests/test_oracle_aim.py (moment reproduction of the stencil
 weights, FFT = direct Toeplitz sum, alpha >= sqrt(2) pi/eps is the identity
 filter, kept-bin fraction, symmetry x^T A y = y^T A x, S_AIM -> dense S,
-circle spectrum of S^alpha_AIM vs the analytic filter).
+circle spectrum of S^alpha_AIM vs the analytic filter, the analytic table
+at the origin closed form and against the tail form of eq. (6)).
 """
 from __future__ import annotations
 
@@ -46,7 +50,7 @@ from scipy.spatial import cKDTree
 
 from . import galerkin
 from .geometry import gauss_legendre01, segments
-from .green import green
+from .green import green, green_alpha_lowpass, green_alpha_origin
 
 CHANNELS_S = ('phi',)
 CHANNELS_N = ('dphi', 'tx', 'ty')
@@ -193,6 +197,22 @@ def filtered_table(grid: Grid, T, alpha):
     return ca[:grid.m, :grid.m].copy(), ca
 
 
+def analytic_filtered_table(grid: Grid, k: float, alpha: float):
+    """Toeplitz table of the grid kernel sampled from the analytically
+    filtered Green's function, eq. (6): T[dy, dx] = g^alpha(eps |d|), the
+    alternative to the numerical filter compared in Fig. 1(a).  g^alpha is
+    regular, so the origin keeps its value (closed form g^alpha(0))."""
+    d = np.arange(grid.m) * grid.eps
+    T = np.zeros((grid.m, grid.m), dtype=complex)
+    for iy in range(grid.m):
+        for ix in range(iy + 1):
+            r = math.hypot(d[iy], d[ix])
+            v = green_alpha_origin(k, alpha) if r == 0.0 else green_alpha_lowpass(r, k, alpha)[0]
+            T[iy, ix] = v
+            T[ix, iy] = v
+    return T
+
+
 class AimOracle:
     """The discrete AIM operators of one geometry / frequency / grid."""
 
@@ -228,6 +248,11 @@ class AimOracle:
     def set_alpha(self, alpha):
         self.alpha = alpha
         self.Ta, _ = filtered_table(self.grid, self.T, alpha)
+
+    def set_alpha_analytic(self, alpha):
+        """S^alpha from the analytically filtered grid kernel (Fig. 1(a))."""
+        self.alpha = alpha
+        self.Ta = analytic_filtered_table(self.grid, self.k, alpha)
 
     def _near_pairs(self):
         tree = cKDTree(self.anc.astype(float))

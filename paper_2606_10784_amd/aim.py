@@ -69,6 +69,7 @@ EXPORTS = {
     "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimParams), ctypes.c_int32]),
     "aim_setup": (ctypes.c_int, [ctypes.POINTER(AimParams), ctypes.POINTER(ctypes.c_void_p)]),
     "aim_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "aim_filter_analytic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "aim_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "aim_rhs_planewave": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_double, ctypes.c_void_p]),
@@ -199,6 +200,9 @@ class Context:
     def filter(self, alpha):
         return aim_filter(self, alpha)
 
+    def filter_analytic(self, alpha):
+        return aim_filter_analytic(self, alpha)
+
     def matvec(self, op, x, y=None):
         return aim_matvec(self, op, x, y)
 
@@ -227,6 +231,10 @@ def aim_setup(xy, k, eta, basis, m, eps, **kw):
 
 def aim_filter(ctx, alpha):
     _check(_lib().aim_filter(ctx.handle, float(alpha)), "aim_filter")
+
+
+def aim_filter_analytic(ctx, alpha):
+    _check(_lib().aim_filter_analytic(ctx.handle, float(alpha)), "aim_filter_analytic")
 
 
 def aim_matvec(ctx, op, x, y=None):

@@ -189,6 +189,7 @@ struct ProfScope {
 aim_status dev_alloc(Ctx* c, void** p, size_t bytes);
 aim_status setup_device(Ctx* c);                        // tables, spectrum, near field
 aim_status apply_filter(Ctx* c, double alpha);
+aim_status apply_filter_analytic(Ctx* c, double alpha);
 aim_status acquire_spectrum(Ctx* c, double keps);
 void release_spectrum(Ctx* c);
 size_t cache_clear();

@@ -99,6 +99,11 @@ aim_status aim_filter(aim_ctx ctx, double alpha) {
   return apply_filter(&ctx->c, alpha);
 }
 
+aim_status aim_filter_analytic(aim_ctx ctx, double alpha) {
+  if (!ctx || std::isnan(alpha)) return AIM_E_ARG;
+  return apply_filter_analytic(&ctx->c, alpha);
+}
+
 aim_status aim_matvec(aim_ctx ctx, int32_t op, int32_t nrhs, const void* x_dev, void* y_dev) {
   if (!ctx || !x_dev || !y_dev || x_dev == y_dev) return AIM_E_ARG;
   const int64_t N = ctx->c.t.N;

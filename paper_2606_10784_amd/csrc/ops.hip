@@ -104,6 +104,72 @@ __global__ void k_extract_spectrum(int n, const double2* C, double2* Q, float2* 
   if (Qf) Qf[(size_t)kx * n + p] = make_float2((float)v.x, (float)v.y);
 }
 
+// ---------------------------------------------------------------------------
+// analytically filtered grid kernel, eq. (6), in grid units (t = s eps,
+// kap = k eps, a = alpha eps, rho = |d|):
+//   g^alpha = (1/2pi) PV int_0^a J0(t rho) t / (t^2 - kap^2) dt - (j/4) J0(kap rho)
+// The principal value is taken by subtracting the pole: with
+// f(t) = t J0(t rho) / (t + kap),
+//   PV int_0^a f(t)/(t - kap) dt = int_0^a (f(t) - f(kap))/(t - kap) dt
+//                                  + f(kap) ln((a - kap)/kap),
+// integrated with 16-point Gauss-Legendre panels on [0, kap] and [kap, a],
+// at least four panels per half-period of J0(t rho).  One wave per sample
+// (lanes over the nodes, fixed-order reduction); samples over the octant
+// 0 <= dx <= dy <= m - 1, index dy (dy + 1) / 2 + dx.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_galpha_octant(int m, double kap, double a, const double* __restrict__ glx,
+                                                       const double* __restrict__ glw, double2* __restrict__ table) {
+  const int lane = threadIdx.x & 63;
+  const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nsamp = (int64_t)m * (m + 1) / 2;
+  if (s >= nsamp) return;
+  // invert s = dy (dy + 1) / 2 + dx
+  int dy = (int)((sqrt(8.0 * (double)s + 1.0) - 1.0) * 0.5);
+  while ((int64_t)dy * (dy + 1) / 2 > s) --dy;
+  while ((int64_t)(dy + 1) * (dy + 2) / 2 <= s) ++dy;
+  const int dx = (int)(s - (int64_t)dy * (dy + 1) / 2);
+  const double rho = sqrt((double)dx * dx + (double)dy * dy);
+  const double fk = 0.5 * j0(kap * rho);   // f(kap)
+  const double osc = rho > 1.0 ? rho : 1.0;
+  const int n1 = max(4, (int)ceil(kap * osc * 4.0 / kPi));
+  const int n2 = max(4, (int)ceil((a - kap) * osc * 4.0 / kPi));
+  const double h1 = kap / n1, h2 = (a - kap) / n2;
+  double acc = 0.0;
+  const int nodes = (n1 + n2) * 16;
+  for (int q = lane; q < nodes; q += 64) {
+    const int pnl = q >> 4, node = q & 15;
+    const bool first = pnl < n1;
+    const double h = first ? h1 : h2;
+    const double t = (first ? pnl * h1 : kap + (pnl - n1) * h2) + h * glx[node];
+    const double f = t * j0(t * rho) / (t + kap);
+    acc += h * glw[node] * (f - fk) / (t - kap);
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    const double pv = acc + fk * log((a - kap) / kap);
+    table[s] = make_double2(kInv2Pi * pv, -0.25 * j0(kap * rho));
+  }
+}
+
+// circulant embedding (wrap-around layout) of the octant table, ring at |d| = m zero
+__global__ void k_fill_from_octant(int m, int n, const double2* __restrict__ table, double2* __restrict__ c) {
+  const int qx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int qy = blockIdx.y;
+  if (qx >= n) return;
+  double2 v = make_double2(0.0, 0.0);
+  if (qx != m && qy != m) {
+    int ax = qx < m ? qx : n - qx, ay = qy < m ? qy : n - qy;
+    if (ax > ay) {
+      const int t = ax;
+      ax = ay;
+      ay = t;
+    }
+    v = table[(int64_t)ay * (ay + 1) / 2 + ax];
+  }
+  c[(size_t)qy * n + qx] = v;
+}
+
 // the same grid kernel at the small offsets the near-field correction needs
 __global__ void k_small_table(int ks, double keps, double2* out) {
   const int dx = threadIdx.x, dy = blockIdx.x;
@@ -1001,6 +1067,52 @@ aim_status apply_filter(Ctx* c, double alpha) {
   }
   c->alpha = alpha;
   c->filtered = !all;
+  return AIM_OK;
+}
+
+aim_status apply_filter_analytic(Ctx* c, double alpha) {
+  const HostTables& t = c->t;
+  const int m = t.m, n = t.n, H = n / 2 + 1;
+  const double kap = t.k * t.eps, a = alpha * t.eps;
+  if (!(alpha > t.k) || !std::isfinite(alpha)) return AIM_E_ARG;
+  hipStream_t s = c->stream;
+  if (!c->own_Ca) {
+    TRY(dev_alloc(c, (void**)&c->own_Ca, (size_t)H * n * sizeof(double2)));
+    if (c->precision == AIM_MIXED) TRY(dev_alloc(c, (void**)&c->own_Caf, (size_t)H * n * sizeof(float2)));
+  }
+  std::vector<double> gx, gw;
+  gauss_legendre01(16, gx, gw);
+  const int64_t nsamp = (int64_t)m * (m + 1) / 2;
+  double2 *table = nullptr, *cfull = nullptr;
+  double* gl = nullptr;
+  bool ok = hipMalloc(&table, nsamp * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc(&cfull, (size_t)n * n * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc(&gl, 32 * sizeof(double)) == hipSuccess;
+  aim_status st = ok ? AIM_OK : AIM_E_OOM;
+  if (st == AIM_OK && (hipMemcpyAsync(gl, gx.data(), 16 * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+                       hipMemcpyAsync(gl + 16, gw.data(), 16 * 8, hipMemcpyHostToDevice, s) != hipSuccess))
+    st = AIM_E_HIP;
+  if (st == AIM_OK) {
+    hipLaunchKernelGGL(k_galpha_octant, dim3((unsigned)((nsamp + 3) / 4)), dim3(256), 0, s, m, kap, a, gl, gl + 16,
+                       table);
+    hipLaunchKernelGGL(k_fill_from_octant, dim3((n + 255) / 256, n), dim3(256), 0, s, m, n, table, cfull);
+    st = hipGetLastError() == hipSuccess ? AIM_OK : AIM_E_HIP;
+  }
+  if (st == AIM_OK) st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
+  if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
+  if (st == AIM_OK) {
+    hipLaunchKernelGGL(k_extract_spectrum, dim3((n + 255) / 256, H), dim3(256), 0, s, n, cfull, c->own_Ca,
+                       c->own_Caf);
+    if (hipStreamSynchronize(s) != hipSuccess) st = AIM_E_HIP;
+  }
+  if (table) (void)hipFree(table);
+  if (cfull) (void)hipFree(cfull);
+  if (gl) (void)hipFree(gl);
+  if (st != AIM_OK) return st;
+  c->d_Ca = c->own_Ca;
+  c->d_Caf = c->own_Caf;
+  c->alpha = alpha;
+  c->filtered = true;
   return AIM_OK;
 }
 

@@ -132,3 +132,27 @@ def test_fig3_spectrum_physics(fig3):
     assert np.all((ratio > 0.7) & (ratio < 1.3))
     above = NUS >= 1.2 * ALPHA * A_RAD
     assert np.max(np.abs(lF[above])) < 1e-5
+
+
+def test_fig1_analytic_kernel_spectrum(fig2):
+    """Fig. 1: the grid kernel sampled from the analytic g^alpha (a) and the
+    numerical filter (b) give comparable operators: both spectra follow the
+    analytic filtered eigenvalues below the cutoff and decay past it."""
+    ctx, _ = fig2
+    lN = ctx.fourier_spectrum("S_ALPHA", NUS)
+    ctx.filter_analytic(ALPHA)
+    try:
+        lA = ctx.fourier_spectrum("S_ALPHA", NUS)
+    finally:
+        ctx.filter(ALPHA)
+    ex = mie.circle_eig_S_alpha(NUS, K, A_RAD, ALPHA)
+    scale = np.maximum(np.abs(ex), 0.2 * np.max(np.abs(ex)))
+    below = NUS <= 0.45 * ALPHA * A_RAD
+    gA = np.abs(lA[below] - ex[below]) / scale[below]
+    gN = np.abs(lN[below] - ex[below]) / scale[below]
+    print("below the cutoff: max gap analytic kernel", gA.max(), "numerical filter", gN.max())
+    assert gA.max() < 0.1
+    assert np.max(np.abs(lA - lN)[below] / scale[below]) < 0.1
+    above = NUS >= 1.5 * ALPHA * A_RAD
+    print("past 1.5 alpha a: max |lambda| / |lambda_0| analytic", np.abs(lA[above]).max() / abs(lA[0]))
+    assert np.abs(lA[above]).max() < 1e-2 * abs(lA[0])

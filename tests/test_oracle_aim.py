@@ -211,3 +211,19 @@ def test_row_sampled_evaluation_matches_full(small_cyl):
     D = aim.AimOracle(xh, K, wl.ETA0, 1, 32, 0.1, near_rows=[5, 30])
     xx = wl.probe_vector(48, seed=8)
     assert np.max(np.abs(D.rows_apply('N', xx, [5, 30]) - C.apply('N', xx)[[5, 30]])) < 1e-12 * np.max(np.abs(C.apply('N', xx)))
+
+
+def test_analytic_filtered_table_pins():
+    """Fig. 1(a) variant: the table samples eq. (6).  The origin equals the
+    closed form g^alpha(0); off-origin samples equal the independent tail
+    form of eq. (6)."""
+    from oracle import green as og
+    grid = aim.Grid(8, 0.1)
+    alpha = 3 * K
+    T = aim.analytic_filtered_table(grid, K, alpha)
+    assert abs(T[0, 0] - og.green_alpha_origin(K, alpha)) < 1e-12
+    for iy, ix in ((0, 1), (3, 2), (7, 7), (5, 0)):
+        r = 0.1 * math.hypot(iy, ix)
+        ref = og.green_alpha_tail(r, K, alpha)[0]
+        assert abs(T[iy, ix] - ref) < 1e-7 * abs(ref)
+        assert T[iy, ix] == T[ix, iy]
