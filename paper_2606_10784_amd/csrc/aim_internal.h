@@ -43,7 +43,7 @@ __host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y
 // frequency FFT of length n = 16^P * RL (radix 16 P times, then RL in 2..16)
 // in place, so position p holds frequency ky_of_pos(n, p): with
 // p = RL * (16^{P-1} k_1 + ... + k_P) + k_{P+1}, ky = k_1 + 16 k_2 + ... +
-// 16^{P-1} k_P + 16^P k_{P+1}.  The spectrum is stored in this order.
+// 16^{P-1} k_P + 16^P k_{P+1}.  The spectrum is stored in this order, folded.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int ky_of_pos(int n, int p) {
   int rl = n, P = 0;
@@ -59,6 +59,26 @@ __host__ __device__ inline int ky_of_pos(int n, int p) {
   }
   // the loop reversed the digit order: ky now holds k_P ... k_1 with k_1 lowest
   return ky + (klast << (4 * P));
+}
+
+// The kernel is even in dy, so the spectrum is even in ky: only half of each
+// row is stored.  Position p = RL g + r holds ky = low + W r with W = n / RL
+// and low = ky_of_pos(n, RL g); its mirror n - ky = (W - low) + W (RL-1-r)
+// sits at the same r reversed in the group with low' = W - low.  A row keeps
+// the groups with low <= W/2: slot j = lowc RL + r holds ky = lowc + W r,
+// (W/2 + 1) RL slots per kxq.
+__host__ __device__ inline int spec_last_radix(int n) {
+  int rl = n;
+  while (rl > 16) rl >>= 4;
+  return rl;
+}
+__host__ __device__ inline int spec_row_len(int n) {
+  const int rl = spec_last_radix(n);
+  return (n / rl / 2 + 1) * rl;
+}
+__host__ __device__ inline int ky_of_slot(int n, int j) {
+  const int rl = spec_last_radix(n);
+  return j / rl + (n / rl) * (j % rl);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,8 +157,8 @@ struct Ctx {
   int32_t *d_at_ptr = nullptr, *d_at_basis = nullptr;
   double* d_at_w[4] = {nullptr, nullptr, nullptr, nullptr};
   float* d_at_wf[4] = {nullptr, nullptr, nullptr, nullptr};
-  // spectra: [kxq][p] for kxq <= n/2 and p < n, frequency ky_of_pos(n, p),
-  // pre-scaled by 1/n^2
+  // spectra: [kxq][j] for kxq <= n/2 and j < spec_row_len(n), frequency
+  // ky_of_slot(n, j), pre-scaled by 1/n^2
   double2 *d_C = nullptr, *d_Ca = nullptr, *own_Ca = nullptr;
   float2 *d_Cf = nullptr, *d_Caf = nullptr, *own_Caf = nullptr;
   void* spec = nullptr;          // shared spectrum cache entry

@@ -253,6 +253,27 @@ __device__ __forceinline__ void pass_twiddle(cplx<T>* v, int j, const cplx<T>* _
   }
 }
 
+// Base twiddle w^1 of butterfly j of a pass with sub-length NS (forward
+// sign), loaded once so a later pass can reuse it without a dependent load.
+template <typename T, int N, int NS, int R>
+__device__ __forceinline__ cplx<T> tw_base(int j, const cplx<T>* __restrict__ tw) {
+  if constexpr (NS > 1) return tw[(j & (NS - 1)) * (N / (NS * R))];
+  else return mk<T>(1, 0);
+}
+
+// pass_twiddle with the base twiddle already in a register
+template <typename T, bool INV, int NS, int R>
+__device__ __forceinline__ void apply_twiddle(cplx<T>* v, cplx<T> w1) {
+  using V = cplx<T>;
+  if constexpr (NS > 1) {
+    if (INV) w1.y = -w1.y;
+    V wp[R];
+    tw_powers<V, R>(w1, wp);
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], wp[r]);
+  }
+}
+
 // One Stockham pass: sub-transform length NS -> NS*R.  Element i of column c
 // lives at buf[pidx(i * NCOL + c)]; butterfly b = j * NCOL + c reads elements
 // j + r N/R and writes (j - k) R + k + r NS, k = j mod NS.
@@ -287,6 +308,72 @@ __device__ __forceinline__ void stockham_pass(cplx<T>* buf, const cplx<T>* __res
     }
   }
   __syncthreads();
+}
+
+// Stockham pass with the base twiddle of each butterfly given (w[q] for
+// butterfly tid + q NT, forward sign); single column
+template <typename T, int N, int NT, bool INV, int NS, int R>
+__device__ __forceinline__ void stockham_pass_w(cplx<T>* buf, const cplx<T>* w) {
+  using V = cplx<T>;
+  constexpr int NB = N / R;
+  constexpr int PER = (NB + NT - 1) / NT;
+  V v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = tid + q * NT;
+    if ((NB % NT) == 0 || j < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[pidx(j + r * (N / R))];
+      apply_twiddle<T, INV, NS, R>(v[q], w[q]);
+      dft_r<T, R, INV>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int j = tid + q * NT;
+    if ((NB % NT) == 0 || j < NB) {
+      const int k = j & (NS - 1);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx(base + r * NS)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// A chain of single-column Stockham passes from sub-length NS up to NSEND,
+// radix 16 (R16) or radix min(16, N/NS); the base twiddles of every pass are
+// loaded up front (chain_tw) so no pass waits on a dependent load.
+template <int N, int NS, bool R16> constexpr int chain_radix() { return R16 ? 16 : (N / NS >= 16 ? 16 : N / NS); }
+template <int N, int NT, int NS, int NSEND, bool R16> constexpr int chain_len() {
+  if constexpr (NS >= NSEND) return 0;
+  else {
+    constexpr int R = chain_radix<N, NS, R16>();
+    return (N / R + NT - 1) / NT + chain_len<N, NT, NS * R, NSEND, R16>();
+  }
+}
+template <typename T, int N, int NT, int NS, int NSEND, bool R16>
+__device__ __forceinline__ void chain_tw(const cplx<T>* __restrict__ tw, cplx<T>* w) {
+  if constexpr (NS < NSEND) {
+    constexpr int R = chain_radix<N, NS, R16>();
+    constexpr int NB = N / R, PER = (NB + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = threadIdx.x + q * NT;
+      w[q] = ((NB % NT) == 0 || j < NB) ? tw_base<T, N, NS, R>(j, tw) : mk<T>(1, 0);
+    }
+    chain_tw<T, N, NT, NS * R, NSEND, R16>(tw, w + PER);
+  }
+}
+template <typename T, int N, int NT, bool INV, int NS, int NSEND, bool R16>
+__device__ __forceinline__ void chain_passes(cplx<T>* buf, const cplx<T>* w) {
+  if constexpr (NS < NSEND) {
+    constexpr int R = chain_radix<N, NS, R16>();
+    stockham_pass_w<T, N, NT, INV, NS, R>(buf, w);
+    chain_passes<T, N, NT, INV, NS * R, NSEND, R16>(buf, w + (N / R + NT - 1) / NT);
+  }
 }
 
 // radix-16 passes, then 8, 4 or 2 for the remainder
@@ -333,6 +420,36 @@ __device__ __forceinline__ void ct_pass(cplx<T>* buf, const cplx<T>* __restrict_
         pass_twiddle<T, N, false, S, R>(v, m, tw);
       } else {
         pass_twiddle<T, N, true, S, R>(v, m, tw);
+        dft_r<T, R, true>(v);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx((base + S * r) * NCOL + c)] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
+// ct_pass with the base twiddle of each of the thread's butterflies given
+// (w[q] for butterfly tid + q NT, forward sign)
+template <typename T, int N, int NCOL, int NT, bool INV, int S, int R>
+__device__ __forceinline__ void ct_pass_w(cplx<T>* buf, const cplx<T>* w) {
+  using V = cplx<T>;
+  constexpr int NB = (N / R) * NCOL;
+  constexpr int PER = (NB + NT - 1) / NT;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if ((NB % NT) == 0 || b < NB) {
+      const int c = b % NCOL, t = b / NCOL;
+      const int m = t % S, base = (t / S) * S * R + m;
+      V v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = buf[pidx((base + S * r) * NCOL + c)];
+      if (!INV) {
+        dft_r<T, R, false>(v);
+        apply_twiddle<T, false, S, R>(v, w[q]);
+      } else {
+        apply_twiddle<T, true, S, R>(v, w[q]);
         dft_r<T, R, true>(v);
       }
 #pragma unroll
@@ -437,6 +554,9 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
   const int row = xcd_row(blockIdx.x, nr), pair = blockIdx.y;
   const int tid = threadIdx.x;
   if (row >= nr) return;
+  constexpr int NW = chain_len<N, NT, 16, N, false>();
+  V wt[NW > 0 ? NW : 1];
+  chain_tw<T, N, NT, 16, N, false>(tw, wt);
   for (int i = tid; i < N / 2; i += NT) buf[pidx(i)] = mk<T>(0, 0);
   __syncthreads();
   const int a0 = row_ptr[row], a1 = row_ptr[row + 1];
@@ -466,7 +586,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     }
     __syncthreads();
   }
-  fft_passes<T, N, 1, NT, false, 16>(buf, tw);
+  chain_passes<T, N, NT, false, 16, N, false>(buf, wt);
   // pairs of lanes fill the CB-wide segments of the tiled layout; the LDS
   // reads of a thread are all issued before its stores
   V* out = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
@@ -507,6 +627,17 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
   const int tid = threadIdx.x;
   if (row >= nr) return;
   const V* in = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  // base twiddles of the radix-16 passes and of the last pass, loaded with
+  // the row
+  constexpr int NW = chain_len<N, NT, RL, N / 16, true>();
+  constexpr int NS_L = N / 16, PER_L = (NS_L + NT - 1) / NT;
+  V wt[NW > 0 ? NW : 1], wl[PER_L];
+  chain_tw<T, N, NT, RL, N / 16, true>(tw, wt);
+#pragma unroll
+  for (int q = 0; q < PER_L; ++q) {
+    const int j = tid + q * NT;
+    wl[q] = ((NS_L % NT) == 0 || j < NS_L) ? tw_base<T, N, NS_L, 16>(j, tw) : mk<T>(1, 0);
+  }
   {
     // all HBM loads of a thread in flight before its LDS stores
     constexpr int PER = (N + NT - 1) / NT;
@@ -528,9 +659,9 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
   }
   __syncthreads();
   stockham_pass<T, N, 1, NT, true, 1, RL>(buf, tw);
-  passes16<T, N, 1, NT, true, RL, N / 16>(buf, tw);
+  chain_passes<T, N, NT, true, RL, N / 16, true>(buf, wt);
   {
-    constexpr int NS = N / 16, NB = NS, PER = (NB + NT - 1) / NT;
+    constexpr int NS = NS_L, NB = NS, PER = PER_L;
     V v[PER][16];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -538,7 +669,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
       if ((NB % NT) == 0 || j < NB) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[q][r] = buf[pidx(j + r * NS)];
-        pass_twiddle<T, N, true, NS, 16>(v[q], j, tw);
+        apply_twiddle<T, true, NS, 16>(v[q], wl[q]);
         dft16_halfout<T, true>(v[q]);
       }
     }
@@ -574,8 +705,9 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 // Pass 2 (MODE 0): column FFT, spectrum multiply, inverse column FFT, in
 // place on one tile [row][CB] of T (nr <= N/2 rows kept, the rest is the
 // zero padding).  The column FFT is an in-place decimation in frequency, so
-// the spectrum Cq is read in its stored order [kxq][p] (frequency
-// ky_of_pos(N, p)), and the inverse is the matching decimation in time.
+// position p holds frequency ky_of_pos(N, p); the spectrum Cq is stored in
+// that order, folded over ky -> N - ky ([kxq][spec_row_len(N)]), and the
+// inverse is the matching decimation in time.
 // MODE 1 (set-up): plain forward FFT of CB consecutive columns of a
 // row-major N x N array.
 template <typename T, int N, int MODE>
@@ -585,7 +717,6 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
   using V = cplx<T>;
   constexpr int CB = ColCfg<T, N>::CB;
   constexpr int NT = ColCfg<T, N>::NT;
-  constexpr int H = N / 2 + 1;
   constexpr int NBLK = N / CB;
   __shared__ V buf[padded(N * CB)];
   const int b = blockIdx.x;
@@ -595,85 +726,129 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
     static_assert(N >= 32, "column pass assumes at least two forward passes");
     constexpr int RL = last_radix<N>();
     constexpr int S1 = N / 16;
+    constexpr int SM = N / 256;                   // middle radix-16 pass stride
+    constexpr bool MID = SM >= RL && SM >= 1;
+    static_assert(!MID || SM / 16 < RL, "at most one middle pass per direction");
+    constexpr int NB1 = S1 * CB, PER1 = (NB1 + NT - 1) / NT;
+    constexpr int NBM = (N / 16) * CB, PERM = (NBM + NT - 1) / NT;
+    constexpr int NG = N / RL, NBF = NG * CB, PERF = (NBF + NT - 1) / NT;
     V* tile = Tb + ((size_t)pair * NBLK + b) * nr * CB;
     // forward pass 1 (stride N/16, radix 16) from HBM: inputs m + S1 r with
     // r >= 8 lie in the zero half
-    {
-      constexpr int NB = S1 * CB, PER = (NB + NT - 1) / NT;
-      V v[PER][16];
+    V v[PER1][16];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, m = bb / CB;
+    for (int q = 0; q < PER1; ++q) {
+      const int bb = tid + q * NT;
+      if ((NB1 % NT) == 0 || bb < NB1) {
+        const int c = bb % CB, m = bb / CB;
 #pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            const int i = m + r * S1;
-            v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
-          }
+        for (int r = 0; r < 8; ++r) {
+          const int i = m + r * S1;
+          v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
         }
       }
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, m = bb / CB;
-          dft16_halfin<T, false>(v[q]);
-          pass_twiddle<T, N, false, S1, 16>(v[q], m, tw);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) buf[pidx((m + r * S1) * CB + c)] = v[q][r];
-        }
-      }
-      __syncthreads();
     }
-    dif16_down<T, N, CB, NT, N / 256, RL>(buf, tw);
+    // everything else this block reads from HBM does not depend on the data:
+    // the spectrum values of the fused pass and the twiddles of the other
+    // passes are issued now and consumed passes later, so their latency
+    // overlaps the first passes instead of stalling each one (the spectrum
+    // only in FP64 up to N = 2048: elsewhere the extra registers would cost
+    // a wave per SIMD or spill).
+    // The spectrum row is folded (ky and N - ky share a slot): group g holds
+    // ky = low + W r with low the base-16 digit reversal of g; a group with
+    // low > W/2 reads its mirror group W - low and reverses r (in registers,
+    // at the multiply, so a prefetch never waits).
+    constexpr int W = N / RL, HS = (W / 2 + 1) * RL;
+    auto mirrored = [&](int g, int& lowc) {
+      int low = 0;
+#pragma unroll
+      for (int t = 1, gg = g; t < W; t *= 16, gg >>= 4) low = low * 16 + (gg & 15);
+      lowc = low > W / 2 ? W - low : low;
+      return low > W / 2;
+    };
+    auto load_spec = [&](int bb, V* cv) {
+      const int g = bb % NG, c = bb / NG;
+      int kx, kxq, lowc;
+      col_of(b, c, N, CB, kx, kxq);
+      mirrored(g, lowc);
+      const V* Cp = Cq + (size_t)kxq * HS + lowc * RL;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) cv[r] = Cp[r];
+    };
+    constexpr bool PRE = sizeof(T) == 8 && N <= 2048 && PERF * RL <= 16;
+    V cv[PERF][RL];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int q = 0; q < PERF; ++q) {
+        const int bb = tid + q * NT;
+        if ((NBF % NT) == 0 || bb < NBF) load_spec(bb, cv[q]);
+      }
+    }
+    V w1[PER1], wm[PERM];
+#pragma unroll
+    for (int q = 0; q < PER1; ++q) {
+      const int bb = tid + q * NT;
+      w1[q] = ((NB1 % NT) == 0 || bb < NB1) ? tw_base<T, N, S1, 16>(bb / CB, tw) : mk<T>(1, 0);
+    }
+    if constexpr (MID) {
+#pragma unroll
+      for (int q = 0; q < PERM; ++q) {
+        const int bb = tid + q * NT;
+        wm[q] = ((NBM % NT) == 0 || bb < NBM) ? tw_base<T, N, SM, 16>((bb / CB) % SM, tw) : mk<T>(1, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER1; ++q) {
+      const int bb = tid + q * NT;
+      if ((NB1 % NT) == 0 || bb < NB1) {
+        const int c = bb % CB, m = bb / CB;
+        dft16_halfin<T, false>(v[q]);
+        apply_twiddle<T, false, S1, 16>(v[q], w1[q]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[pidx((m + r * S1) * CB + c)] = v[q][r];
+      }
+    }
+    __syncthreads();
+    if constexpr (MID) ct_pass_w<T, N, CB, NT, false, SM, 16>(buf, wm);
     // last forward pass (contiguous groups of RL), spectrum multiply in the
     // stored frequency order, first inverse pass; lanes run along the groups
-    {
-      constexpr int R = RL, NG = N / RL, NB = NG * CB, PER = (NB + NT - 1) / NT;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB % NT) == 0 || bb < NB) {
-          const int g = bb % NG, c = bb / NG;
-          int kx, kxq;
-          col_of(b, c, N, CB, kx, kxq);
-          const V* Cp = Cq + (size_t)kxq * N + (size_t)g * R;
-          V cv[R], v[R];
+    for (int q = 0; q < PERF; ++q) {
+      const int bb = tid + q * NT;
+      if ((NBF % NT) == 0 || bb < NBF) {
+        const int g = bb % NG, c = bb / NG;
+        if constexpr (!PRE) load_spec(bb, cv[q]);
+        V u[RL];
 #pragma unroll
-          for (int r = 0; r < R; ++r) cv[r] = Cp[r];
+        for (int r = 0; r < RL; ++r) u[r] = buf[pidx((g * RL + r) * CB + c)];
+        int lowc;
+        const bool mir = mirrored(g, lowc);
+        dft_r<T, RL, false>(u);
 #pragma unroll
-          for (int r = 0; r < R; ++r) v[r] = buf[pidx((g * R + r) * CB + c)];
-          dft_r<T, R, false>(v);
+        for (int r = 0; r < RL; ++r) u[r] = cmul(u[r], mir ? cv[q][RL - 1 - r] : cv[q][r]);
+        dft_r<T, RL, true>(u);
 #pragma unroll
-          for (int r = 0; r < R; ++r) v[r] = cmul(v[r], cv[r]);
-          dft_r<T, R, true>(v);
-#pragma unroll
-          for (int r = 0; r < R; ++r) buf[pidx((g * R + r) * CB + c)] = v[r];
-        }
+        for (int r = 0; r < RL; ++r) buf[pidx((g * RL + r) * CB + c)] = u[r];
       }
-      __syncthreads();
     }
-    dit16_up<T, N, CB, NT, RL, N / 256>(buf, tw);
+    __syncthreads();
+    if constexpr (MID) ct_pass_w<T, N, CB, NT, true, SM, 16>(buf, wm);
     // last inverse pass (stride N/16, radix 16) straight to HBM: outputs
     // m + S1 r, only r < 8 can be a kept row
-    {
-      constexpr int NB = S1 * CB, PER = (NB + NT - 1) / NT;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB % NT) == 0 || bb < NB) {
-          const int c = bb % CB, m = bb / CB;
-          V v[16];
+    for (int q = 0; q < PER1; ++q) {
+      const int bb = tid + q * NT;
+      if ((NB1 % NT) == 0 || bb < NB1) {
+        const int c = bb % CB, m = bb / CB;
+        V u[16];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) v[r] = buf[pidx((m + r * S1) * CB + c)];
-          pass_twiddle<T, N, true, S1, 16>(v, m, tw);
-          dft16_halfout<T, true>(v);
+        for (int r = 0; r < 16; ++r) u[r] = buf[pidx((m + r * S1) * CB + c)];
+        apply_twiddle<T, true, S1, 16>(u, w1[q]);
+        dft16_halfout<T, true>(u);
 #pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            const int i = m + r * S1;
-            if (i < nr) tile[(size_t)i * CB + c] = v[r];
-          }
+        for (int r = 0; r < 8; ++r) {
+          const int i = m + r * S1;
+          if (i < nr) tile[(size_t)i * CB + c] = u[r];
         }
       }
     }

@@ -90,18 +90,20 @@ __global__ void k_sample_kernel(int m, int n, double keps, double2* c) {
   c[(size_t)qy * n + qx] = v;
 }
 
-// spectrum rows kxq <= n/2 in the column-FFT frequency order, scaled by 1/n^2
+// spectrum rows kxq <= n/2 in the folded column-FFT frequency order, scaled
+// by 1/n^2
 __global__ void k_extract_spectrum(int n, const double2* C, double2* Q, float2* Qf) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int hs = spec_row_len(n);
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int kx = blockIdx.y;
-  if (p >= n) return;
-  const int ky = ky_of_pos(n, p);
+  if (j >= hs) return;
+  const int ky = ky_of_slot(n, j);
   const double s = 1.0 / ((double)n * (double)n);
   double2 v = C[(size_t)ky * n + kx];
   v.x *= s;
   v.y *= s;
-  Q[(size_t)kx * n + p] = v;
-  if (Qf) Qf[(size_t)kx * n + p] = make_float2((float)v.x, (float)v.y);
+  Q[(size_t)kx * hs + j] = v;
+  if (Qf) Qf[(size_t)kx * hs + j] = make_float2((float)v.x, (float)v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -179,16 +181,18 @@ __global__ void k_small_table(int ks, double keps, double2* out) {
 
 // numerical filter: keep qx^2 + qy^2 <= thr (|qx|, |qy| the folded frequencies)
 __global__ void k_filter(int n, double thr, bool all, const double2* Q, double2* Qa, float2* Qaf) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int hs = spec_row_len(n);
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int kx = blockIdx.y;
-  if (p >= n) return;
-  const int ky = ky_of_pos(n, p);
+  if (j >= hs) return;
+  const int ky = ky_of_slot(n, j);
   const int kyq = ky <= n / 2 ? ky : n - ky;
   const double r2 = (double)kx * kx + (double)kyq * kyq;
-  double2 v = Q[(size_t)kx * n + p];
+  const size_t o = (size_t)kx * hs + j;
+  double2 v = Q[o];
   if (!all && !(r2 <= thr)) v = make_double2(0.0, 0.0);
-  Qa[(size_t)kx * n + p] = v;
-  if (Qaf) Qaf[(size_t)kx * n + p] = make_float2((float)v.x, (float)v.y);
+  Qa[o] = v;
+  if (Qaf) Qaf[o] = make_float2((float)v.x, (float)v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -872,13 +876,13 @@ aim_status acquire_spectrum(Ctx* c, double keps) {
   e->m = m;
   e->keps = keps;
   e->f32 = f32;
-  e->bytes = (size_t)H * n * (sizeof(double2) + (f32 ? sizeof(float2) : 0));
+  e->bytes = (size_t)H * spec_row_len(n) * (sizeof(double2) + (f32 ? sizeof(float2) : 0));
   spec_evict_locked(kSpecCacheBytes > e->bytes ? kSpecCacheBytes - e->bytes : 0);
   hipStream_t s = c->stream;
   double2* cfull = nullptr;
   bool ok = hipMalloc(&cfull, (size_t)n * n * sizeof(double2)) == hipSuccess;
-  ok = ok && hipMalloc(&e->C, (size_t)H * n * sizeof(double2)) == hipSuccess;
-  if (ok && f32) ok = hipMalloc(&e->Cf, (size_t)H * n * sizeof(float2)) == hipSuccess;
+  ok = ok && hipMalloc(&e->C, (size_t)H * spec_row_len(n) * sizeof(double2)) == hipSuccess;
+  if (ok && f32) ok = hipMalloc(&e->Cf, (size_t)H * spec_row_len(n) * sizeof(float2)) == hipSuccess;
   if (!ok) {
     if (cfull) (void)hipFree(cfull);
     spec_free(e);
@@ -888,7 +892,7 @@ aim_status acquire_spectrum(Ctx* c, double keps) {
   aim_status st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
   if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
   if (st == AIM_OK) {
-    hipLaunchKernelGGL(k_extract_spectrum, dim3((n + 255) / 256, H), dim3(256), 0, s, n, cfull, e->C, e->Cf);
+    hipLaunchKernelGGL(k_extract_spectrum, dim3((spec_row_len(n) + 255) / 256, H), dim3(256), 0, s, n, cfull, e->C, e->Cf);
     if (hipStreamSynchronize(s) != hipSuccess) st = AIM_E_HIP;
   }
   (void)hipFree(cfull);
@@ -1055,11 +1059,11 @@ aim_status apply_filter(Ctx* c, double alpha) {
     c->d_Caf = c->d_Cf;
   } else {
     if (!c->own_Ca) {
-      TRY(dev_alloc(c, (void**)&c->own_Ca, (size_t)H * n * sizeof(double2)));
-      if (c->precision == AIM_MIXED) TRY(dev_alloc(c, (void**)&c->own_Caf, (size_t)H * n * sizeof(float2)));
+      TRY(dev_alloc(c, (void**)&c->own_Ca, (size_t)H * spec_row_len(n) * sizeof(double2)));
+      if (c->precision == AIM_MIXED) TRY(dev_alloc(c, (void**)&c->own_Caf, (size_t)H * spec_row_len(n) * sizeof(float2)));
     }
     const double thr = ((alpha * n) * c->t.eps / (2.0 * kPi)) * ((alpha * n) * c->t.eps / (2.0 * kPi));
-    hipLaunchKernelGGL(k_filter, dim3((n + 255) / 256, H), dim3(256), 0, c->stream, n, thr, false, c->d_C,
+    hipLaunchKernelGGL(k_filter, dim3((spec_row_len(n) + 255) / 256, H), dim3(256), 0, c->stream, n, thr, false, c->d_C,
                        c->own_Ca, c->own_Caf);
     AIM_HIP_CHECK(hipGetLastError());
     c->d_Ca = c->own_Ca;
@@ -1077,8 +1081,8 @@ aim_status apply_filter_analytic(Ctx* c, double alpha) {
   if (!(alpha > t.k) || !std::isfinite(alpha)) return AIM_E_ARG;
   hipStream_t s = c->stream;
   if (!c->own_Ca) {
-    TRY(dev_alloc(c, (void**)&c->own_Ca, (size_t)H * n * sizeof(double2)));
-    if (c->precision == AIM_MIXED) TRY(dev_alloc(c, (void**)&c->own_Caf, (size_t)H * n * sizeof(float2)));
+    TRY(dev_alloc(c, (void**)&c->own_Ca, (size_t)H * spec_row_len(n) * sizeof(double2)));
+    if (c->precision == AIM_MIXED) TRY(dev_alloc(c, (void**)&c->own_Caf, (size_t)H * spec_row_len(n) * sizeof(float2)));
   }
   std::vector<double> gx, gw;
   gauss_legendre01(16, gx, gw);
@@ -1101,7 +1105,7 @@ aim_status apply_filter_analytic(Ctx* c, double alpha) {
   if (st == AIM_OK) st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
   if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
   if (st == AIM_OK) {
-    hipLaunchKernelGGL(k_extract_spectrum, dim3((n + 255) / 256, H), dim3(256), 0, s, n, cfull, c->own_Ca,
+    hipLaunchKernelGGL(k_extract_spectrum, dim3((spec_row_len(n) + 255) / 256, H), dim3(256), 0, s, n, cfull, c->own_Ca,
                        c->own_Caf);
     if (hipStreamSynchronize(s) != hipSuccess) st = AIM_E_HIP;
   }
