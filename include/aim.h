@@ -43,7 +43,7 @@ typedef struct aim_ctx_s* aim_ctx;
 typedef enum {
   AIM_OK = 0,
   AIM_E_ARG = 1,      /* invalid argument (null pointer, size, enum)          */
-  AIM_E_GEOM = 2,     /* a 4x4 stencil leaves the m x m grid                   */
+  AIM_E_GEOM = 2,     /* a stencil leaves the m x m grid                       */
   AIM_E_OOM = 3,      /* device allocation failed                              */
   AIM_E_HIP = 4,      /* HIP runtime error                                     */
   AIM_E_STATE = 5,    /* call not valid in this context state                  */
@@ -93,6 +93,14 @@ typedef struct {
   int32_t precision;      /* AIM_FP64 or AIM_MIXED (also builds the FP32 grid data) */
   int32_t max_rhs;        /* largest nrhs of later calls (>= 1)                     */
   void* stream;           /* hipStream_t for all device work (NULL: default stream) */
+  int32_t node_order;     /* form of Lambda (Sec. III-A).  0: one 4 x 4 cubic
+                             Lagrange stencil per basis at its centre cell, with
+                             the near-field correction (all operators).  P (even,
+                             2..12): every quadrature node gets its own P x P
+                             tensor-Lagrange stencil at its own cell and a basis
+                             row of Lambda is the union of its nodes' stencils;
+                             there is no near-field correction, so only
+                             AIM_OP_S_ALPHA and AIM_OP_GRAM_INV are available    */
 } aim_params;
 
 typedef struct {
@@ -103,6 +111,9 @@ typedef struct {
   int32_t near_band;                /* near field kept as a symmetric cyclic band
                                        of this half-width (bases are numbered
                                        along the contour), or -1: CSR only        */
+  int32_t node_order;               /* aim_params.node_order of the context       */
+  int32_t map_points;               /* grid points per basis row of Lambda (16, or
+                                       the widest per-node row)                    */
 } aim_ctx_info;
 
 typedef struct {
@@ -147,7 +158,8 @@ aim_status aim_filter_analytic(aim_ctx ctx, double alpha);
 
 /* y = op(x) for nrhs columns (1 <= nrhs <= max_rhs); x_dev and y_dev are
    c128 N x nrhs device arrays and must not overlap.  Asynchronous.  Errors:
-   AIM_E_ARG (op invalid for the basis or precision), AIM_E_STATE.             */
+   AIM_E_ARG (op invalid for the basis or precision), AIM_E_STATE (an operator
+   with a near-field correction on a per-node context).                        */
 aim_status aim_matvec(aim_ctx ctx, int32_t op, int32_t nrhs, const void* x_dev, void* y_dev);
 
 /* Plane-wave right-hand sides, one column per angle (propagation direction
@@ -164,7 +176,8 @@ aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_ho
    runs FP64 iterative refinement around an inner GMRES whose grid part is
    FP32.  restart: 1..1000 Krylov vectors per cycle.  info_host: nrhs
    entries (may be NULL).  Synchronous.  Errors: AIM_E_ARG, AIM_E_NOCONV,
-   AIM_E_NUMERIC, AIM_E_OOM.                                                   */
+   AIM_E_NUMERIC, AIM_E_OOM, AIM_E_STATE (per-node context: every system
+   operator needs the near-field correction).                                  */
 aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                      const void* b_dev, void* x_dev, double tol, int32_t maxit,
                      int32_t restart, aim_solve_info* info_host);

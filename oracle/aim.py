@@ -18,6 +18,9 @@ Readings taken where the paper is silent:
     into one 4 x 4 tensor-product cubic Lagrange stencil per basis function,
     anchored at the cell holding the basis centre (pulse: segment midpoint,
     hat: its vertex): W_j[t*4+s] = sum_k w_k v_j(r_k) l_s(x_k) l_t(y_k).
+    The per-node form (stencil_weights_node) gives every quadrature node its
+    own P x P stencil at its own cell (nodes -(P/2-1) .. P/2, so P = 4 is the
+    same cubic stencil); the paper's Sec. IV uses order 10.
   * padding n = 2m (default) with the ring |d| = m of the kernel zero, or the
     paper's n = 2m - 1.
   * the cutoff keeps bins with qx^2 + qy^2 <= (alpha n eps / 2 pi)^2,
@@ -36,7 +39,8 @@ The alternative of Fig. 1(a), a grid kernel sampled from the analytically
 filtered g^alpha of eq. (6), is analytic_filtered_table.
 
 Pinned by: tests/test_oracle_aim.py (moment reproduction of the stencil
-weights, FFT = direct Toeplitz sum, alpha >= sqrt(2) pi/eps is the identity
+weights, per-node weights to degree P-1 and equal to the per-basis stencil
+where all nodes of a basis share its anchor cell, FFT = direct Toeplitz sum, alpha >= sqrt(2) pi/eps is the identity
 filter, kept-bin fraction, symmetry x^T A y = y^T A x, S_AIM -> dense S,
 circle spectrum of S^alpha_AIM vs the analytic filter, the analytic table
 at the origin closed form and against the tail form of eq. (6)).
@@ -142,6 +146,85 @@ def stencil_weights(xy, basis, grid: Grid, p: int, channel: str):
     return W.reshape(nb, 16), G.reshape(nb, 16)
 
 
+def lagrange_nodes(order: int):
+    """Interpolation nodes of an order-P stencil, in cells relative to the
+    anchor cell: -(P/2 - 1), ..., P/2 (P even; P = 4 gives -1, 0, 1, 2)."""
+    if order < 2 or order % 2:
+        raise ValueError("stencil order must be even and >= 2")
+    return np.arange(order) - (order // 2 - 1)
+
+
+def lagrange_basis(tt, order: int):
+    """All order-P Lagrange basis polynomials at tt: (..., P), by the product
+    formula l_i(t) = prod_{j != i} (t - x_j) / (x_i - x_j)."""
+    xs = lagrange_nodes(order).astype(float)
+    tt = np.asarray(tt, dtype=float)[..., None]
+    out = np.ones(tt.shape[:-1] + (order,))
+    for i in range(order):
+        for j in range(order):
+            if j != i:
+                out[..., i] *= (tt[..., 0] - xs[j]) / (xs[i] - xs[j])
+    return out
+
+
+def stencil_weights_node(xy, basis, grid: Grid, p: int, channel: str, order: int):
+    """Lambda in its per-node form (Sec. III-A: Lambda maps every quadrature
+    node to the grid): node r_k of basis j gets its own order x order
+    tensor-product Lagrange stencil anchored at floor((r_k + L)/eps), and the
+    basis row of Lambda Q collects w_k v_j(r_k) l_s(x_k) l_t(y_k) over its
+    nodes.  Returns (W, G) of shape (N, S): the union of a basis's node
+    stencils in ascending grid index, padded to the widest basis with weight
+    0 at the basis's first point."""
+    xy = np.asarray(xy, dtype=float)
+    nb = xy.shape[0]
+    A0, A1, h, t, _ = segments(xy)
+    tau, w = gauss_legendre01(p)
+    xs = lagrange_nodes(order)
+    if basis == 0:
+        pieces = [(np.arange(nb), np.ones(nb), np.zeros(nb))]
+    else:
+        j = np.arange(nb)
+        pieces = [((j - 1) % nb, np.zeros(nb), np.ones(nb)),
+                  (j, np.ones(nb), -np.ones(nb))]
+    bid, lin, wt = [], [], []
+    for seg, c0, c1 in pieces:
+        pts = A0[seg, None, :] + (A1 - A0)[seg, None, :] * tau[None, :, None]   # (nb,p,2)
+        wk = h[seg, None] * w[None, :]
+        phi = c0[:, None] + c1[:, None] * tau[None, :]
+        val = {'phi': phi,
+               'dphi': np.broadcast_to((c1 / h[seg])[:, None], phi.shape),
+               'tx': t[seg, 0][:, None] * phi,
+               'ty': t[seg, 1][:, None] * phi}[channel]
+        gx = (pts[..., 0] + grid.L) / grid.eps
+        gy = (pts[..., 1] + grid.L) / grid.eps
+        ax, ay = np.floor(gx).astype(np.int64), np.floor(gy).astype(np.int64)
+        if min(ax.min(), ay.min()) + xs[0] < 0 or max(ax.max(), ay.max()) + xs[-1] > grid.m - 1:
+            raise GeometryError("stencil leaves the grid")
+        lx = lagrange_basis(gx - ax, order)      # (nb,p,P)
+        ly = lagrange_basis(gy - ay, order)
+        f = wk * val                             # (nb,p)
+        ix = ax[..., None, None] + xs[None, None, None, :]         # (nb,p,1,P)
+        iy = ay[..., None, None] + xs[None, None, :, None]         # (nb,p,P,1)
+        lin.append(np.broadcast_to(iy * grid.m + ix, (nb, p, order, order)).reshape(-1))
+        wt.append((f[..., None, None] * ly[..., :, None] * lx[..., None, :]).reshape(-1))
+        bid.append(np.broadcast_to(np.arange(nb)[:, None, None, None], (nb, p, order, order)).reshape(-1))
+    bid, lin, wt = np.concatenate(bid), np.concatenate(lin), np.concatenate(wt)
+    key = bid * (grid.m * grid.m) + lin
+    uk, inv = np.unique(key, return_inverse=True)
+    acc = np.zeros(uk.size)
+    np.add.at(acc, inv, wt)
+    ub = uk // (grid.m * grid.m)
+    counts = np.bincount(ub, minlength=nb)
+    S = int(counts.max())
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    W = np.zeros((nb, S))
+    G = np.repeat((uk[starts] % (grid.m * grid.m))[:, None], S, axis=1)
+    pos = np.arange(uk.size) - starts[ub]
+    W[ub, pos] = acc
+    G[ub, pos] = uk % (grid.m * grid.m)
+    return W, G
+
+
 def kernel_table(grid: Grid, k: float):
     """T[dy, dx] = g(eps |d|) for 0 <= dx, dy <= m-1, T[0, 0] = 0 (Sec. III-C)."""
     d = np.arange(grid.m) * grid.eps
@@ -217,18 +300,30 @@ class AimOracle:
     """The discrete AIM operators of one geometry / frequency / grid."""
 
     def __init__(self, xy, k, eta, basis, m, eps, p=10, near_radius=6, pad=0,
-                 alpha=math.inf, near=True, near_rows=None):
+                 alpha=math.inf, near=True, near_rows=None, node_order=0):
+        """node_order = 0: one 4 x 4 stencil per basis (with the near-field
+        correction); node_order = P: the per-node order-P Lambda, which has
+        no near-field correction, so only S^alpha (and the Gram solve)."""
         self.xy = np.asarray(xy, dtype=float)
         self.k, self.eta, self.basis = float(k), float(eta), int(basis)
         self.N = self.xy.shape[0]
         self.grid = Grid(m, eps, pad)
         self.p = p
         self.R = near_radius
-        self.anc = anchors(self.xy, basis, self.grid)
+        self.node_order = int(node_order)
+        if self.node_order:
+            near = False
+            self.anc = np.floor((basis_centers(self.xy, basis) + self.grid.L) / self.grid.eps).astype(np.int64)
+        else:
+            self.anc = anchors(self.xy, basis, self.grid)
         chans = CHANNELS_S + (CHANNELS_N if basis == 1 else ())
         self.W, self.Gidx = {}, {}
         for ch in chans:
-            self.W[ch], self.Gidx[ch] = stencil_weights(self.xy, basis, self.grid, p, ch)
+            if self.node_order:
+                self.W[ch], self.Gidx[ch] = stencil_weights_node(self.xy, basis, self.grid, p, ch,
+                                                                 self.node_order)
+            else:
+                self.W[ch], self.Gidx[ch] = stencil_weights(self.xy, basis, self.grid, p, ch)
         gidx = self.Gidx['phi']
         self.act = np.unique(gidx)                       # sorted linear indices
         self.aidx = np.searchsorted(self.act, gidx)      # (N, 16) active indices
@@ -329,6 +424,8 @@ class AimOracle:
         return v
 
     def near_apply(self, op, x):
+        if self.near_pairs is None:
+            raise ValueError("this operator has no near-field correction")
         pairs = self.near_sel_pairs
         C = self.Cnear[op]
         y = np.zeros((self.N,) + x.shape[1:], dtype=complex)

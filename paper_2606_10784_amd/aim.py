@@ -43,7 +43,7 @@ class AimParams(ctypes.Structure):
                 ("k", ctypes.c_double), ("eta", ctypes.c_double), ("basis", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("eps", ctypes.c_double), ("quad", ctypes.c_int32),
                 ("near_radius", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("node_order", ctypes.c_int32)]
 
 
 class AimCtxInfo(ctypes.Structure):
@@ -51,7 +51,7 @@ class AimCtxInfo(ctypes.Structure):
                 ("n_active", ctypes.c_int32), ("active_rows", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("near_nnz_s", ctypes.c_int64), ("near_nnz_n", ctypes.c_int64), ("k", ctypes.c_double),
                 ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
-                ("near_band", ctypes.c_int32)]
+                ("near_band", ctypes.c_int32), ("node_order", ctypes.c_int32), ("map_points", ctypes.c_int32)]
 
 
 class AimSolveInfo(ctypes.Structure):
@@ -141,7 +141,8 @@ def _as_cols(x, N):
     return x, x.shape[0]
 
 
-def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1, stream=None):
+def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1, stream=None,
+                node_order=0):
     arr = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
     p = AimParams()
     p.n_vertices = arr.shape[0]
@@ -149,12 +150,13 @@ def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM
     p.k, p.eta, p.basis, p.m, p.eps = float(k), float(eta), int(basis), int(m), float(eps)
     p.quad, p.near_radius, p.precision, p.max_rhs = int(quad), int(near_radius), int(precision), int(max_rhs)
     p.stream = stream
+    p.node_order = int(node_order)
     return p, arr
 
 
 def aim_footprint_bytes(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
-                        restart=100):
-    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None)
+                        restart=100, node_order=0):
+    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None, node_order)
     return int(_lib().aim_footprint_bytes(ctypes.byref(p), int(restart)))
 
 
@@ -162,13 +164,13 @@ class Context:
     """Owns one aim_ctx (geometry, grid tables, spectra, near field)."""
 
     def __init__(self, xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
-                 stream=None):
+                 stream=None, node_order=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libaim needs a HIP device")
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         p, self._xy = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs,
-                                  _stream_handle(self._stream_obj))
+                                  _stream_handle(self._stream_obj), node_order)
         h = ctypes.c_void_p()
         _check(_lib().aim_setup(ctypes.byref(p), ctypes.byref(h)), "aim_setup")
         self._h = h

@@ -90,9 +90,13 @@ struct HostTables {
   std::vector<double> vx, vy;                 // vertices
   std::vector<double> h, tx, ty;              // per segment
   std::vector<int32_t> anc_x, anc_y;          // anchor cells per basis
+  // grid map rows: S points per basis.  node_order = 0: the 4 x 4 stencil of
+  // the basis (S = 16); node_order = P: the union of the P x P stencils of
+  // the basis's quadrature nodes, padded to the widest basis (weight 0)
+  int node_order = 0, S = 16;
   // channels: 0 = phi, 1 = dphi, 2 = t_x phi, 3 = t_y phi (hats use all four)
-  std::vector<double> W[4];                   // N x 16 per channel
-  std::vector<int32_t> aidx;                  // N x 16 active index of each stencil point
+  std::vector<double> W[4];                   // N x S per channel
+  std::vector<int32_t> aidx;                  // N x S active index of each map point
   std::vector<int32_t> act_ix, act_iy;        // active points, sorted row-major
   int n_act = 0, y0 = 0, nr = 0;              // active rows [y0, y0 + nr)
   std::vector<int32_t> row_ptr;               // nr + 1 offsets into the active list

@@ -28,14 +28,29 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   const size_t nch = p->basis == AIM_HAT ? 3 : 1;
   const size_t H = n / 2 + 1;
   const size_t nr = t ? t->nr : m;
-  const size_t nact = t ? t->n_act : 16 * N;
-  const size_t near = t ? t->nr_col.size() : N * (size_t)((2 * p->near_radius + 1) * 3);
+  // map points per basis: 16, or for the per-node map the cells of the
+  // stencils of a basis's nodes, bounded by their box
+  size_t S = 16;
+  if (t) {
+    S = t->S;
+  } else if (p->node_order > 0 && p->xy && p->eps > 0) {
+    double hmax = 0;
+    for (size_t i = 0; i < N; ++i) {
+      const size_t i1 = (i + 1) % N;
+      hmax = std::max(hmax, std::hypot(p->xy[2 * i1] - p->xy[2 * i], p->xy[2 * i1 + 1] - p->xy[2 * i + 1]));
+    }
+    const size_t side = (size_t)p->node_order + (size_t)std::ceil(hmax / p->eps) + 1;
+    S = side * side * (p->basis == AIM_HAT ? 2 : 1);
+  }
+  const size_t nact = t ? t->n_act : S * N;
+  const size_t near = t ? t->nr_col.size()
+                        : (p->node_order > 0 ? 0 : N * (size_t)((2 * p->near_radius + 1) * 3));
   size_t b = 0;
   b += nch * R * (nr * n + 2 * nact) * 16;               // U, T, V
   b += 2 * H * spec_row_len((int)n) * 16 * (p->precision == AIM_MIXED ? 1.5 : 1.0);
   b += near * (4 + 16 * (p->basis == AIM_HAT ? 2 : 1));
   if (t && t->band_w >= 0) b += (size_t)(t->band_w + 1) * N * 16 * (p->basis == AIM_HAT ? 2 : 1);
-  b += N * 16 * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
+  b += N * S * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
   b += 3 * N * R * 16;
   b += (size_t)R * (restart + 1) * N * 16 + (size_t)5 * R * N * 16;
   return b;
@@ -118,6 +133,7 @@ aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_ho
 aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev, void* x_dev,
                      double tol, int32_t maxit, int32_t restart, aim_solve_info* info_host) {
   if (!ctx || !b_dev || !x_dev || b_dev == x_dev) return AIM_E_ARG;
+  if (ctx->c.t.node_order != 0) return AIM_E_STATE;   // every system operator needs the near field
   return solve(&ctx->c, form, precision, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart,
                info_host);
 }
@@ -150,6 +166,8 @@ aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info) {
   info->alpha = c.filtered ? c.alpha : INFINITY;
   info->device_bytes = c.dev_bytes;
   info->near_band = c.t.band_w;
+  info->node_order = c.t.node_order;
+  info->map_points = c.t.S;
   return AIM_OK;
 }
 

@@ -4,9 +4,13 @@
 // Sec. II: N straight segments, segment j from vertex j to vertex j+1.
 // Eq. (7): p-node Gauss rule per segment.  Sec. III-A: m x m grid of step eps
 // centred at the origin; Lambda projects quadrature nodes onto grid points.
-// Here Lambda is folded with the quadrature weights and the basis values into
-// one 4 x 4 cubic-Lagrange stencil per basis function (16 weights), anchored
-// at the cell that holds the basis centre.
+// Lambda is folded with the quadrature weights and the basis values into one
+// row of grid weights per basis function, in one of two forms:
+//   * one 4 x 4 cubic-Lagrange stencil per basis (16 weights), anchored at
+//     the cell that holds the basis centre (with the near-field correction);
+//   * per node (Sec. III-A read literally): every quadrature node gets its
+//     own P x P tensor-Lagrange stencil at its own cell, and the basis row is
+//     the union of its nodes' stencils (no near-field correction: S^alpha).
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -72,6 +76,17 @@ void twiddles(int n, std::vector<double>& tw) {
   }
 }
 
+// order-P Lagrange basis on the nodes -(P/2 - 1), ..., P/2 at t
+static void lagrangeP(int P, double t, double* l) {
+  const int o = P / 2 - 1;
+  for (int i = 0; i < P; ++i) {
+    double v = 1.0;
+    for (int j = 0; j < P; ++j)
+      if (j != i) v *= (t - (double)(j - o)) / (double)(i - j);
+    l[i] = v;
+  }
+}
+
 static inline void lagrange4(double t, double l[4]) {
   // cubic Lagrange basis on nodes -1, 0, 1, 2
   l[0] = -t * (t - 1.0) * (t - 2.0) / 6.0;
@@ -91,6 +106,9 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
   if (p->near_radius < 0 || p->near_radius + 3 > m - 1) { err = "near_radius out of range"; return AIM_E_ARG; }
   if (p->basis != AIM_PULSE && p->basis != AIM_HAT) { err = "basis"; return AIM_E_ARG; }
   if (p->max_rhs < 1) { err = "max_rhs"; return AIM_E_ARG; }
+  const int P = p->node_order;
+  if (P != 0 && (P < 2 || P > 12 || (P & 1))) { err = "node_order must be 0 or even in 2..12"; return AIM_E_ARG; }
+  t.node_order = P;
   t.N = N;
   t.basis = p->basis;
   t.m = m;
@@ -137,7 +155,7 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
       cy = t.vy[j];
     }
     double ax = std::floor((cx + t.L) / t.eps), ay = std::floor((cy + t.L) / t.eps);
-    if (!(ax - 1 >= 0 && ax + 2 <= m - 1 && ay - 1 >= 0 && ay + 2 <= m - 1)) {
+    if (P == 0 && !(ax - 1 >= 0 && ax + 2 <= m - 1 && ay - 1 >= 0 && ay + 2 <= m - 1)) {
       err = "stencil leaves the grid";
       return AIM_E_GEOM;
     }
@@ -145,45 +163,133 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
     t.anc_y[j] = (int32_t)ay;
   }
 
-  // stencil weights per channel
+  // grid weights per channel and the grid point of each (lin, row-major)
   const int nch = t.nch;
-  for (int c = 0; c < 4; ++c) t.W[c].assign(c < nch ? (size_t)N * 16 : 0, 0.0);
-  for (int j = 0; j < N; ++j) {
-    int nseg = (t.basis == AIM_PULSE) ? 1 : 2;
-    for (int q = 0; q < nseg; ++q) {
-      int s;
-      double c0, c1;
-      if (t.basis == AIM_PULSE) { s = j; c0 = 1.0; c1 = 0.0; }
-      else if (q == 0) { s = (j - 1 + N) % N; c0 = 0.0; c1 = 1.0; }   // rising on segment j-1
-      else { s = j; c0 = 1.0; c1 = -1.0; }                            // falling on segment j
-      int s1 = (s + 1) % N;
-      double ax0 = t.vx[s], ay0 = t.vy[s];
-      double ddx = t.vx[s1] - ax0, ddy = t.vy[s1] - ay0;
-      for (int kq = 0; kq < t.p; ++kq) {
-        double tau = t.gl_x[kq];
-        double px = ax0 + ddx * tau, py = ay0 + ddy * tau;
-        double wk = t.h[s] * t.gl_w[kq];
-        double phi = c0 + c1 * tau;
-        double val[4] = {phi, c1 / t.h[s], t.tx[s] * phi, t.ty[s] * phi};
-        double lx[4], ly[4];
-        lagrange4((px + t.L) / t.eps - t.anc_x[j], lx);
-        lagrange4((py + t.L) / t.eps - t.anc_y[j], ly);
-        for (int c = 0; c < nch; ++c) {
-          double f = wk * val[c];
-          double* Wj = &t.W[c][(size_t)j * 16];
-          for (int tt = 0; tt < 4; ++tt)
-            for (int ss = 0; ss < 4; ++ss) Wj[tt * 4 + ss] += f * lx[ss] * ly[tt];
+  std::vector<int64_t> lin;
+  std::vector<int32_t> cnt(N, 16);     // real (unpadded) points per basis
+  auto pieces = [&](int j, int q, int& s, double& c0, double& c1) {
+    if (t.basis == AIM_PULSE) { s = j; c0 = 1.0; c1 = 0.0; }
+    else if (q == 0) { s = (j - 1 + N) % N; c0 = 0.0; c1 = 1.0; }   // rising on segment j-1
+    else { s = j; c0 = 1.0; c1 = -1.0; }                            // falling on segment j
+  };
+  const int nseg = (t.basis == AIM_PULSE) ? 1 : 2;
+  if (P == 0) {
+    t.S = 16;
+    for (int c = 0; c < 4; ++c) t.W[c].assign(c < nch ? (size_t)N * 16 : 0, 0.0);
+    for (int j = 0; j < N; ++j) {
+      for (int q = 0; q < nseg; ++q) {
+        int s;
+        double c0, c1;
+        pieces(j, q, s, c0, c1);
+        int s1 = (s + 1) % N;
+        double ax0 = t.vx[s], ay0 = t.vy[s];
+        double ddx = t.vx[s1] - ax0, ddy = t.vy[s1] - ay0;
+        for (int kq = 0; kq < t.p; ++kq) {
+          double tau = t.gl_x[kq];
+          double px = ax0 + ddx * tau, py = ay0 + ddy * tau;
+          double wk = t.h[s] * t.gl_w[kq];
+          double phi = c0 + c1 * tau;
+          double val[4] = {phi, c1 / t.h[s], t.tx[s] * phi, t.ty[s] * phi};
+          double lx[4], ly[4];
+          lagrange4((px + t.L) / t.eps - t.anc_x[j], lx);
+          lagrange4((py + t.L) / t.eps - t.anc_y[j], ly);
+          for (int c = 0; c < nch; ++c) {
+            double f = wk * val[c];
+            double* Wj = &t.W[c][(size_t)j * 16];
+            for (int tt = 0; tt < 4; ++tt)
+              for (int ss = 0; ss < 4; ++ss) Wj[tt * 4 + ss] += f * lx[ss] * ly[tt];
+          }
         }
       }
     }
+    lin.resize((size_t)N * 16);
+    for (int j = 0; j < N; ++j)
+      for (int tt = 0; tt < 4; ++tt)
+        for (int ss = 0; ss < 4; ++ss)
+          lin[(size_t)j * 16 + tt * 4 + ss] = (int64_t)(t.anc_y[j] - 1 + tt) * m + (t.anc_x[j] - 1 + ss);
+  } else {
+    // per node: accumulate each basis's node stencils in a dense box over
+    // its cells, then keep the touched cells in row-major order
+    const int o = P / 2 - 1;
+    std::vector<std::vector<int64_t>> blin(N);
+    std::vector<std::vector<double>> bw(N);
+    std::vector<double> box, lx(P), ly(P);
+    std::vector<char> touched;
+    std::vector<int> nax, nay;
+    for (int j = 0; j < N; ++j) {
+      nax.clear();
+      nay.clear();
+      int bx0 = m, by0 = m, bx1 = -1, by1 = -1;
+      for (int q = 0; q < nseg; ++q) {
+        int s;
+        double c0, c1;
+        pieces(j, q, s, c0, c1);
+        const int s1 = (s + 1) % N;
+        for (int kq = 0; kq < t.p; ++kq) {
+          const double tau = t.gl_x[kq];
+          const double px = t.vx[s] + (t.vx[s1] - t.vx[s]) * tau, py = t.vy[s] + (t.vy[s1] - t.vy[s]) * tau;
+          const int ax = (int)std::floor((px + t.L) / t.eps), ay = (int)std::floor((py + t.L) / t.eps);
+          if (ax - o < 0 || ax - o + P - 1 > m - 1 || ay - o < 0 || ay - o + P - 1 > m - 1) {
+            err = "stencil leaves the grid";
+            return AIM_E_GEOM;
+          }
+          nax.push_back(ax);
+          nay.push_back(ay);
+          bx0 = std::min(bx0, ax - o);
+          by0 = std::min(by0, ay - o);
+          bx1 = std::max(bx1, ax - o + P - 1);
+          by1 = std::max(by1, ay - o + P - 1);
+        }
+      }
+      const int BX = bx1 - bx0 + 1, BY = by1 - by0 + 1;
+      box.assign((size_t)BX * BY * nch, 0.0);
+      touched.assign((size_t)BX * BY, 0);
+      int node = 0;
+      for (int q = 0; q < nseg; ++q) {
+        int s;
+        double c0, c1;
+        pieces(j, q, s, c0, c1);
+        const int s1 = (s + 1) % N;
+        for (int kq = 0; kq < t.p; ++kq, ++node) {
+          const double tau = t.gl_x[kq];
+          const double px = t.vx[s] + (t.vx[s1] - t.vx[s]) * tau, py = t.vy[s] + (t.vy[s1] - t.vy[s]) * tau;
+          const double wk = t.h[s] * t.gl_w[kq];
+          const double phi = c0 + c1 * tau;
+          const double val[4] = {phi, c1 / t.h[s], t.tx[s] * phi, t.ty[s] * phi};
+          const int ax = nax[node], ay = nay[node];
+          lagrangeP(P, (px + t.L) / t.eps - ax, lx.data());
+          lagrangeP(P, (py + t.L) / t.eps - ay, ly.data());
+          for (int tt = 0; tt < P; ++tt)
+            for (int ss = 0; ss < P; ++ss) {
+              const size_t cell = (size_t)(ay - o + tt - by0) * BX + (ax - o + ss - bx0);
+              touched[cell] = 1;
+              for (int c = 0; c < nch; ++c) box[cell * nch + c] += wk * val[c] * lx[ss] * ly[tt];
+            }
+        }
+      }
+      for (int yy = 0; yy < BY; ++yy)
+        for (int xx = 0; xx < BX; ++xx) {
+          const size_t cell = (size_t)yy * BX + xx;
+          if (!touched[cell]) continue;
+          blin[j].push_back((int64_t)(by0 + yy) * m + (bx0 + xx));
+          for (int c = 0; c < nch; ++c) bw[j].push_back(box[cell * nch + c]);
+        }
+      cnt[j] = (int)blin[j].size();
+    }
+    t.S = *std::max_element(cnt.begin(), cnt.end());
+    const int S = t.S;
+    for (int c = 0; c < 4; ++c) t.W[c].assign(c < nch ? (size_t)N * S : 0, 0.0);
+    lin.resize((size_t)N * S);
+    for (int j = 0; j < N; ++j)
+      for (int e = 0; e < S; ++e) {
+        const bool real = e < cnt[j];
+        lin[(size_t)j * S + e] = blin[j][real ? e : 0];   // padding: the first point, weight 0
+        for (int c = 0; c < nch; ++c) t.W[c][(size_t)j * S + e] = real ? bw[j][(size_t)e * nch + c] : 0.0;
+      }
   }
+  const int S = t.S;
 
-  // active grid points: union of stencils, sorted by row-major index
-  std::vector<int64_t> lin((size_t)N * 16);
-  for (int j = 0; j < N; ++j)
-    for (int tt = 0; tt < 4; ++tt)
-      for (int ss = 0; ss < 4; ++ss)
-        lin[(size_t)j * 16 + tt * 4 + ss] = (int64_t)(t.anc_y[j] - 1 + tt) * m + (t.anc_x[j] - 1 + ss);
+  // active grid points: union of the map rows, sorted by row-major index
   std::vector<int64_t> act(lin);
   std::sort(act.begin(), act.end());
   act.erase(std::unique(act.begin(), act.end()), act.end());
@@ -194,7 +300,7 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
     t.act_ix[a] = (int32_t)(act[a] % m);
     t.act_iy[a] = (int32_t)(act[a] / m);
   }
-  t.aidx.resize((size_t)N * 16);
+  t.aidx.resize((size_t)N * S);
   for (size_t q = 0; q < lin.size(); ++q)
     t.aidx[q] = (int32_t)(std::lower_bound(act.begin(), act.end(), lin[q]) - act.begin());
   t.y0 = t.act_iy.front();
@@ -203,21 +309,31 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
   for (int a = 0; a < t.n_act; ++a) t.row_ptr[t.act_iy[a] - t.y0 + 1]++;
   for (int r = 0; r < t.nr; ++r) t.row_ptr[r + 1] += t.row_ptr[r];
 
-  // transposed stencils (grid point -> contributing bases), for the gather
+  // transposed map rows (grid point -> contributing bases), for the gather;
+  // padding entries are left out
   t.at_ptr.assign(t.n_act + 1, 0);
-  for (size_t q = 0; q < t.aidx.size(); ++q) t.at_ptr[t.aidx[q] + 1]++;
+  size_t nent = 0;
+  for (int j = 0; j < N; ++j)
+    for (int e = 0; e < cnt[j]; ++e) t.at_ptr[t.aidx[(size_t)j * S + e] + 1]++, ++nent;
   for (int a = 0; a < t.n_act; ++a) t.at_ptr[a + 1] += t.at_ptr[a];
-  t.at_basis.assign(t.aidx.size(), 0);
-  for (int c = 0; c < 4; ++c) t.at_w[c].assign(c < nch ? t.aidx.size() : 0, 0.0);
+  t.at_basis.assign(nent, 0);
+  for (int c = 0; c < 4; ++c) t.at_w[c].assign(c < nch ? nent : 0, 0.0);
   {
     std::vector<int32_t> fill(t.at_ptr.begin(), t.at_ptr.end() - 1);
     for (int j = 0; j < N; ++j)
-      for (int e = 0; e < 16; ++e) {
-        int a = t.aidx[(size_t)j * 16 + e];
+      for (int e = 0; e < cnt[j]; ++e) {
+        int a = t.aidx[(size_t)j * S + e];
         int pos = fill[a]++;
         t.at_basis[pos] = j;
-        for (int c = 0; c < nch; ++c) t.at_w[c][pos] = t.W[c][(size_t)j * 16 + e];
+        for (int c = 0; c < nch; ++c) t.at_w[c][pos] = t.W[c][(size_t)j * S + e];
       }
+  }
+  if (P != 0) {
+    // the per-node map has no near-field correction
+    t.nr_ptr.assign(N + 1, 0);
+    t.nr_col.clear();
+    t.band_w = -1;
+    return AIM_OK;
   }
 
   // near zone: anchor Chebyshev distance <= R (CSR, sorted columns)

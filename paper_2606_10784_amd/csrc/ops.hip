@@ -499,12 +499,14 @@ __global__ __launch_bounds__(256) void k_anterp(int n_act, int nrhs, const int32
 }
 
 // ---------------------------------------------------------------------------
-// interpolation + near field: 16 lanes per basis row
+// interpolation + near field: LANES lanes per basis row, S map points per row
+// (16 for the 4 x 4 stencils: lanes 0..15 hold one point each for all rhs;
+// wider per-node rows are strided over the lanes)
 //   y = scale * ( sum_ch sgn_ch W_ch . V_ch + C_near x )
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int LANES>
 __global__ __launch_bounds__(256) void k_interp_near(
-    int N, int nrhs, int nch, const TW* __restrict__ W0, const TW* __restrict__ W1,
+    int N, int nrhs, int nch, int S, const TW* __restrict__ W0, const TW* __restrict__ W1,
     const TW* __restrict__ W2, double sg, const int32_t* __restrict__ aidx,
     const cplx<T>* __restrict__ V, int n_act, const int32_t* __restrict__ nptr,
     const int32_t* __restrict__ ncol, const double2* __restrict__ C, const double2* __restrict__ x,
@@ -512,8 +514,8 @@ __global__ __launch_bounds__(256) void k_interp_near(
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int row = gid / LANES, l = gid % LANES;
   if (row >= N) return;          // whole lane groups exit together
-  const bool st = l < 16;        // lanes 0..15 hold the 16 stencil entries
-  const size_t o = (size_t)row * 16 + (st ? l : 0);
+  const bool st = l < S;         // lanes below S hold map points
+  const size_t o = (size_t)row * S + (st ? l : 0);
   const int a = st ? aidx[o] : 0;
   const double w0 = st ? (double)W0[o] : 0.0;
   const double w1 = (st && nch > 1) ? (double)W1[o] : 0.0;
@@ -530,6 +532,19 @@ __global__ __launch_bounds__(256) void k_interp_near(
         const cplx<T> v2 = V[(size_t)(2 * nrhs + r) * n_act + a];
         ax += sg * (w1 * (double)v1.x + w2 * (double)v2.x);
         ay += sg * (w1 * (double)v1.y + w2 * (double)v2.y);
+      }
+    }
+    for (int e = l + LANES; e < S; e += LANES) {   // map points beyond the first LANES
+      const size_t oe = (size_t)row * S + e;
+      const int ae = aidx[oe];
+      const cplx<T> v0 = V[(size_t)r * n_act + ae];
+      ax += (double)W0[oe] * (double)v0.x;
+      ay += (double)W0[oe] * (double)v0.y;
+      if (nch > 1) {
+        const cplx<T> v1 = V[(size_t)(nrhs + r) * n_act + ae];
+        const cplx<T> v2 = V[(size_t)(2 * nrhs + r) * n_act + ae];
+        ax += sg * ((double)W1[oe] * (double)v1.x + (double)W2[oe] * (double)v2.x);
+        ay += sg * ((double)W1[oe] * (double)v1.y + (double)W2[oe] * (double)v2.y);
       }
     }
     const double2* xr = x + (size_t)r * ldx;
@@ -1171,11 +1186,11 @@ static void launch_interp(Ctx* c, const int* chans, int nch, double sg, const do
   dim3 g((unsigned)(((size_t)t.N * LANES + threads - 1) / threads));
   const cplx<T>* V = (const cplx<T>*)c->d_V;
   if (sizeof(T) == 4) {
-    hipLaunchKernelGGL((k_interp_near<T, float, LANES>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
+    hipLaunchKernelGGL((k_interp_near<T, float, LANES>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch, t.S,
                        c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
                        c->d_aidx, V, t.n_act, c->d_nr_ptr, c->d_nr_col, C, x, ldx, y, ldy, scale);
   } else {
-    hipLaunchKernelGGL((k_interp_near<T, double, LANES>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch,
+    hipLaunchKernelGGL((k_interp_near<T, double, LANES>), g, dim3(threads), 0, c->stream, t.N, nrhs, nch, t.S,
                        c->d_W[chans[0]], c->d_W[chans[nch > 1 ? 1 : 0]], c->d_W[chans[nch > 2 ? 2 : 0]], sg,
                        c->d_aidx, V, t.n_act, c->d_nr_ptr, c->d_nr_col, C, x, ldx, y, ldy, scale);
   }
@@ -1203,7 +1218,7 @@ static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near
     return AIM_OK;
   }
   // wide lane groups when the near-field rows are long
-  const bool wide = near && c->nnz >= (int64_t)40 * c->t.N;
+  const bool wide = (near && c->nnz >= (int64_t)40 * c->t.N) || t.S > 16;
   if (wide) launch_interp<T, 64>(c, chans, nch, sg, C, nrhs, x, ldx, y, ldy, scale);
   else launch_interp<T, 16>(c, chans, nch, sg, C, nrhs, x, ldx, y, ldy, scale);
   AIM_HIP_CHECK(hipGetLastError());
@@ -1255,6 +1270,8 @@ aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, doubl
   if (f32 && c->precision != AIM_MIXED) return AIM_E_ARG;
   const bool hat = c->t.basis == AIM_HAT;
   if ((base == AIM_OP_N || base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF) && !hat) return AIM_E_ARG;
+  // the per-node map has no near-field correction: only S^alpha and G^-1
+  if (c->t.node_order != 0 && base != AIM_OP_S_ALPHA && base != AIM_OP_GRAM_INV) return AIM_E_STATE;
   const double2 one = make_double2(1.0, 0.0);
   auto grid = [&](int b, const double2* xx, int64_t lx, double2* yy, int64_t ly, double2 sc) {
     return f32 ? op_grid<float>(c, b, nrhs, xx, lx, yy, ly, sc) : op_grid<double>(c, b, nrhs, xx, lx, yy, ly, sc);

@@ -38,3 +38,19 @@ def test_setup_rejects_bad_arguments_without_device():
     assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_GEOM
     assert lib.aim_filter(None, 1.0) == aim.AIM_E_ARG
     assert lib.aim_matvec(None, 0, 1, None, None) == aim.AIM_E_ARG
+
+
+def test_node_map_parameters_checked_on_the_host():
+    """node_order: 0 or even in 2..12 (AIM_E_ARG), every node stencil inside
+    the grid (AIM_E_GEOM); both decided before any device call."""
+    lib = aim._lib()
+    h = ctypes.c_void_p()
+    xy = wl.circle(0.5, 40)
+    for bad in (3, 14, -2):
+        p, _keep = aim.make_params(xy, wl.K0, wl.ETA0, 0, 256, 0.0126, node_order=bad)
+        assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+    p, _keep = aim.make_params(xy, wl.K0, wl.ETA0, 0, 16, 0.07, node_order=10)   # stencils leave the grid
+    assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_GEOM
+    fb = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 128, 0.0126)
+    fn = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 128, 0.0126, node_order=10)
+    assert fn > fb

@@ -227,3 +227,95 @@ def test_analytic_filtered_table_pins():
         ref = og.green_alpha_tail(r, K, alpha)[0]
         assert abs(T[iy, ix] - ref) < 1e-7 * abs(ref)
         assert T[iy, ix] == T[ix, iy]
+
+
+# ---------------------------------------------------------------------------
+# per-node Lambda (each quadrature node has its own order-P stencil)
+# ---------------------------------------------------------------------------
+def _fine_circle(n=40, a=0.5, ratio=6.24):
+    """Circle whose segments span `ratio` grid cells (the paper's h/eps)."""
+    xy = wl.circle(a, n)
+    h = 2 * a * math.sin(math.pi / n)
+    eps = h / ratio
+    m = 1
+    while (m - 1) * eps < 2 * a + 14 * eps:
+        m *= 2
+    return xy, m, eps
+
+
+@pytest.mark.parametrize("order,basis,channel", [(4, 0, 'phi'), (6, 0, 'phi'), (10, 0, 'phi'),
+                                                 (10, 1, 'phi'), (8, 1, 'dphi')])
+def test_node_stencil_reproduces_moments(order, basis, channel):
+    """An order-P tensor Lagrange stencil is exact on x^a y^b for a, b <= P-1
+    at every node, so a basis row of Lambda Q reproduces the quadrature
+    moments of its basis function to that degree (in local coordinates, so
+    the high powers stay well scaled)."""
+    xy, m, eps = _fine_circle()
+    grid = aim.Grid(m, eps)
+    W, G = aim.stencil_weights_node(xy, basis, grid, 10, channel, order)
+    A0, A1, h, t, _ = segments(xy)
+    tau, w = gauss_legendre01(10)
+    nb = xy.shape[0]
+    cen = aim.basis_centers(xy, basis)
+    for j in range(0, nb, 9):
+        X = (grid.coord(G[j] % m) - cen[j, 0]) / eps
+        Y = (grid.coord(G[j] // m) - cen[j, 1]) / eps
+        pcs = [(j, 1.0, 0.0)] if basis == 0 else [((j - 1) % nb, 0.0, 1.0), (j, 1.0, -1.0)]
+        for a_ in range(order):
+            for b_ in range(order):
+                ref = 0.0
+                for s, c0, c1 in pcs:
+                    pts = A0[s] + np.outer(tau, A1[s] - A0[s])
+                    phi = c0 + c1 * tau
+                    val = {'phi': phi, 'dphi': np.full_like(tau, c1 / h[s])}[channel]
+                    px, py = (pts[:, 0] - cen[j, 0]) / eps, (pts[:, 1] - cen[j, 1]) / eps
+                    ref += np.sum(w * h[s] * val * px ** a_ * py ** b_)
+                got = np.sum(W[j] * X ** a_ * Y ** b_)
+                scale = np.sum(np.abs(W[j])) * (np.max(np.abs(X)) + np.max(np.abs(Y))) ** (a_ + b_)
+                assert abs(got - ref) < 1e-12 * scale, (j, a_, b_)
+
+
+def test_node_stencil_order4_is_basis_stencil_when_nodes_share_the_anchor_cell():
+    """Where every node of a basis lies in the cell of the basis anchor, the
+    per-node cubic stencils coincide with the per-basis 4 x 4 stencil, so the
+    two forms of Lambda must give the same weights there."""
+    xy = wl.circle(1.0, 400)              # h = 0.0157 << eps
+    eps = 0.1
+    grid = aim.Grid(wl.grid_side_for(xy, eps), eps)
+    Wb, Gb = aim.stencil_weights(xy, 0, grid, 10, 'phi')
+    Wn, Gn = aim.stencil_weights_node(xy, 0, grid, 10, 'phi', 4)
+    A0, A1, _, _, _ = segments(xy)
+    tau, _ = gauss_legendre01(10)
+    anc = aim.anchors(xy, 0, grid)
+    same = 0
+    for j in range(xy.shape[0]):
+        pts = A0[j] + np.outer(tau, A1[j] - A0[j])
+        cell = np.floor((pts + grid.L) / grid.eps).astype(int)
+        if not np.all(cell == anc[j]):
+            continue
+        same += 1
+        kb = dict(zip(Gb[j].tolist(), Wb[j].tolist()))
+        kn = {}
+        for g, v in zip(Gn[j].tolist(), Wn[j].tolist()):
+            kn[g] = kn.get(g, 0.0) + v
+        assert set(kb) == {g for g, v in kn.items() if v != 0.0 or g in kb}
+        for g, v in kb.items():
+            assert abs(kn[g] - v) < 1e-15 * np.sum(np.abs(Wb[j]))
+    assert same > 100
+
+
+def test_node_stencil_rejects_contour_leaving_grid():
+    xy = wl.circle(0.5, 40)
+    with pytest.raises(aim.GeometryError):
+        aim.stencil_weights_node(xy, 0, aim.Grid(16, 0.07), 10, 'phi', 10)
+
+
+def test_node_operator_symmetric_and_refuses_near_field_ops():
+    xy, m, eps = _fine_circle(n=24, a=0.3)
+    orc = aim.AimOracle(xy, K, 376.73, 0, m, eps, node_order=6, alpha=0.5 * math.pi / eps)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(24) + 1j * rng.standard_normal(24)
+    y = rng.standard_normal(24) + 1j * rng.standard_normal(24)
+    assert abs(y @ orc.apply('S_ALPHA', x) - x @ orc.apply('S_ALPHA', y)) < 1e-13 * np.linalg.norm(x) * np.linalg.norm(y)
+    with pytest.raises(ValueError):
+        orc.apply('S', x)
