@@ -192,20 +192,24 @@ struct Ctx {
   int ev_used = 0;
 };
 
-// brackets one launch of pipeline kernel `kid` with events when profiling
+// brackets one launch of pipeline kernel `kid` with events when profiling:
+// recorded on the stream around the launch, or (attach) handed to the launch
+// through start() / stop() so the dispatch itself timestamps them
 struct ProfScope {
   Ctx* c;
-  bool on = false;
+  bool on = false, attach = false;
   int slot = -1;
-  ProfScope(Ctx* cc, int kid) : c(cc) {
+  ProfScope(Ctx* cc, int kid, bool attach_events = false) : c(cc), attach(attach_events) {
     if (c->prof_kernel != kid) return;
     const int64_t n = c->prof_launches++;
     if (n % c->prof_every != 0 || c->ev_used >= c->prof_max) return;
     slot = c->ev_used++;
-    on = hipEventRecord(c->ev0[slot], c->stream) == hipSuccess;
+    on = attach || hipEventRecord(c->ev0[slot], c->stream) == hipSuccess;
   }
+  hipEvent_t start() const { return on && attach ? c->ev0[slot] : nullptr; }
+  hipEvent_t stop() const { return on && attach ? c->ev1[slot] : nullptr; }
   ~ProfScope() {
-    if (on) (void)hipEventRecord(c->ev1[slot], c->stream);
+    if (on && !attach) (void)hipEventRecord(c->ev1[slot], c->stream);
   }
 };
 

@@ -22,6 +22,8 @@
 // multiply and the first inverse pass share one register round (the inverse
 // runs its radices in reverse order so the butterflies line up), and the last
 // inverse pass stores only the kept rows straight to HBM.
+#include <hip/hip_ext.h>
+
 #include "aim_internal.h"
 
 namespace aim {
@@ -910,14 +912,15 @@ aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_
 
 template <typename T>
 aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int pairs, const cplx<T>* Cq,
-                       const cplx<T>* tw, hipStream_t s) {
+                       const cplx<T>* tw, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   if (mode == 0 && (nr < 1 || nr > n / 2)) return AIM_E_ARG;   // kept rows lie in the unpadded half
   switch (n) {
 #define CASE(NN)                                                                          \
   case NN: {                                                                              \
     dim3 g(NN / ColCfg<T, NN>::CB, pairs);                                                \
     if (mode == 0)                                                                        \
-      hipLaunchKernelGGL((k_cols<T, NN, 0>), g, dim3(ColCfg<T, NN>::NT), 0, s, Tb, nr, Cq, tw); \
+      hipExtLaunchKernelGGL((k_cols<T, NN, 0>), g, dim3(ColCfg<T, NN>::NT), 0, s, ev_start, ev_stop, 0, \
+                            Tb, nr, Cq, tw);                                              \
     else                                                                                  \
       hipLaunchKernelGGL((k_cols<T, NN, 1>), g, dim3(ColCfg<T, NN>::NT), 0, s, Tb, nr, Cq, tw); \
     break;                                                                                \
@@ -950,7 +953,9 @@ template aim_status launch_rows_inv<double>(int, const double2*, int, const int3
                                             double2*, int, const double2*, hipStream_t);
 template aim_status launch_rows_inv<float>(int, const float2*, int, const int32_t*, const int32_t*, int,
                                            float2*, int, const float2*, hipStream_t);
-template aim_status launch_cols<double>(int, int, double2*, int, int, const double2*, const double2*, hipStream_t);
-template aim_status launch_cols<float>(int, int, float2*, int, int, const float2*, const float2*, hipStream_t);
+template aim_status launch_cols<double>(int, int, double2*, int, int, const double2*, const double2*, hipStream_t,
+                                        hipEvent_t, hipEvent_t);
+template aim_status launch_cols<float>(int, int, float2*, int, int, const float2*, const float2*, hipStream_t,
+                                       hipEvent_t, hipEvent_t);
 
 }  // namespace aim
