@@ -447,6 +447,14 @@ class AimOracle:
         y = y - self.k ** 2 * yt
         return y + self.near_apply('N', x) if near else y
 
+    def op_N_alpha(self, x):
+        """N through the filtered grid kernel, no near-field correction (the
+        Maue channels of eq. (2) with the table of eq. (10))."""
+        y = self.interpolate('dphi', self.grid_apply(self.Ta, self.anterpolate('dphi', x)))
+        yt = (self.interpolate('tx', self.grid_apply(self.Ta, self.anterpolate('tx', x)))
+              + self.interpolate('ty', self.grid_apply(self.Ta, self.anterpolate('ty', x))))
+        return y - self.k ** 2 * yt
+
     def gram_inv(self, x):
         return galerkin.gram_solve(self.xy, self.basis, x)
 
@@ -464,6 +472,7 @@ class AimOracle:
             'S': self.op_S,
             'S_ALPHA': self.op_S_alpha,
             'N': self.op_N,
+            'N_ALPHA': self.op_N_alpha,
             'GRAM_INV': self.gram_inv,
             'TM': self.op_TM,
             'TE_CP': lambda v: self.op_TE_CP(v, True),
