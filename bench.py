@@ -30,7 +30,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cylinder_ka200",
-                    choices=["cylinder_ka200", "cylinder_ka2pi", "star_te", "cylinder_ka200_360rhs", "spectrum"],
+                    choices=["cylinder_ka200", "cylinder_ka2pi", "star_te", "cylinder_ka200_360rhs", "spectrum",
+                             "tm_calderon"],
                     help="cylinder_ka200: the benchmark line; the others are separate measurements")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=400)
@@ -184,6 +185,54 @@ def star_te(args):
     ctx.close()
 
 
+def tm_calderon(args):
+    """Cylinder ka = 200 (N = 16384 pulses) with its dual hat space (32768
+    refined hats): the TM EFIE against the TM Calderon forms, unfiltered and
+    with N^alpha at the 50 % cutoff; operator timings and solves."""
+    import numpy as np
+    import torch
+    from paper_2606_10784_amd import aim
+    from paper_2606_10784_amd import workloads as wl
+    w = wl.cylinder_large()
+    t0 = time.perf_counter()
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1, dual=1)
+    ctx.filter(w.alpha)
+    torch.cuda.synchronize()
+    inf = ctx.info()
+    out = {"workload": w.name + "_tm_calderon", "N": inf["n_unknowns"], "dual_unknowns": inf["dual_unknowns"],
+           "grid": f"{w.m}x{w.m} pad {inf['n_pad']}", "alpha": w.alpha, "setup_s": time.perf_counter() - t0,
+           "matvec_ms": {}, "solves": {}}
+    b = ctx.rhs_planewave(0.0)
+    for op in ("TM", "TM_PC", "TM_PC_UNF", "TM_CP", "TM_CP_UNF"):
+        y = ctx.matvec(op, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            ctx.matvec(op, b, y)
+        e1.record()
+        torch.cuda.synchronize()
+        out["matvec_ms"][op] = e0.elapsed_time(e1) / 20
+    ref = None
+    for form in ("TM", "TM_CP_UNF", "TM_CP"):
+        for prec in (aim.AIM_FP64, aim.AIM_MIXED):
+            ctx.solve(form, b, tol=args.tol, restart=args.restart, maxit=3000, precision=prec)   # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = ctx.solve(form, b, tol=args.tol, restart=args.restart, maxit=3000, precision=prec)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            xs = x.cpu().numpy()
+            if ref is None:
+                ref = xs
+            key = f"{form}_{'fp64' if prec == aim.AIM_FP64 else 'mixed'}"
+            out["solves"][key] = {"seconds": dt, "iterations": info[0]["iterations"], "outer": info[0]["outer"],
+                                  "converged": info[0]["converged"], "resid_true": info[0]["resid_true"],
+                                  "rel_diff_vs_tm_efie": float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))}
+            print(f"[bench] {key} its={info[0]['iterations']} {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def batched_360(args):
     """Cylinder ka = 200 with 360 plane waves (1 degree steps) in one batched
     solve: FP64 and FP32-grid + FP64 refinement, monostatic RCS."""
@@ -278,8 +327,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -291,6 +339,8 @@ def main():
         sys.exit(1)
     if args.workload == "spectrum":
         return spectrum(args)
+    if args.workload == "tm_calderon":
+        return tm_calderon(args)
     if args.workload == "star_te":
         return star_te(args)
     if args.workload == "cylinder_ka200_360rhs":

@@ -64,7 +64,19 @@ enum {
   AIM_OP_GRAM_INV = 3, /* G^-1 x, G the Gram matrix of Sec. II                */
   AIM_OP_TM = 4,       /* jk eta S_AIM x (TM-EFIE operator)                    */
   AIM_OP_TE_CP = 5,    /* G^-1 S^alpha G^-1 N x, eq. (3) with S^alpha          */
-  AIM_OP_TE_CP_UNF = 6 /* G^-1 S_AIM G^-1 N x, eq. (3) unfiltered              */
+  AIM_OP_TE_CP_UNF = 6, /* G^-1 S_AIM G^-1 N x, eq. (3) unfiltered             */
+  AIM_OP_N_ALPHA = 7,  /* N^alpha x: the Maue channels of eq. (2) through the
+                          filtered kernel of eq. (10), no near field; hats     */
+  /* TM Calderon operators (pulse contexts set up with dual = 1).  The dual
+     hats psi_j live on the barycentric refinement of the polygon (vertices
+     v_j and the segment midpoints M_j): psi_j is 1 at M_j, 1/2 at v_j and
+     v_j+1, 0 at M_j-1 and M_j+1, linear on each half segment.  G_pd is the
+     pulse/dual mixed Gram matrix (3h_i/4 on the diagonal, h_i/8 beside it),
+     N'(alpha) the hypersingular operator on the refined hats.             */
+  AIM_OP_TM_PC = 8,      /* G_pd^-T N^alpha_dual G_pd^-1 x (the preconditioner) */
+  AIM_OP_TM_PC_UNF = 9,  /* G_pd^-T N_dual G_pd^-1 x (N with near field)         */
+  AIM_OP_TM_CP = 10,     /* AIM_OP_TM_PC applied to jk eta S_AIM x               */
+  AIM_OP_TM_CP_UNF = 11  /* AIM_OP_TM_PC_UNF applied to jk eta S_AIM x           */
 };
 /* OR-ed into op: run the grid part (maps + FFT convolution) in complex FP32;
    the near field and the in/out vectors stay FP64.  Requires a context set up
@@ -75,7 +87,10 @@ enum {
 enum {
   AIM_TM_EFIE = 0,                 /* jk eta S j = b                          */
   AIM_TE_CALDERON = 1,             /* G^-1 S^a G^-1 N j = G^-1 S^a G^-1 b     */
-  AIM_TE_CALDERON_UNFILTERED = 2   /* G^-1 S G^-1 N j = G^-1 S G^-1 b          */
+  AIM_TE_CALDERON_UNFILTERED = 2,  /* G^-1 S G^-1 N j = G^-1 S G^-1 b          */
+  AIM_TM_CALDERON = 3,             /* P^alpha jk eta S j = P^alpha b,
+                                      P^alpha = G_pd^-T N^alpha_dual G_pd^-1    */
+  AIM_TM_CALDERON_UNFILTERED = 4   /* the same with N_dual (near field)          */
 };
 
 enum { AIM_FP64 = 0, AIM_MIXED = 1 };
@@ -100,7 +115,11 @@ typedef struct {
                              tensor-Lagrange stencil at its own cell and a basis
                              row of Lambda is the union of its nodes' stencils;
                              there is no near-field correction, so only
-                             AIM_OP_S_ALPHA and AIM_OP_GRAM_INV are available    */
+                             AIM_OP_S_ALPHA, AIM_OP_N_ALPHA and AIM_OP_GRAM_INV
+                             are available                                       */
+  int32_t dual;           /* pulse basis only: 1 also sets up the dual hat space
+                             of the TM Calderon operators (a hat context on the
+                             refined polygon, 2N vertices, same grid)           */
 } aim_params;
 
 typedef struct {
@@ -114,6 +133,7 @@ typedef struct {
   int32_t node_order;               /* aim_params.node_order of the context       */
   int32_t map_points;               /* grid points per basis row of Lambda (16, or
                                        the widest per-node row)                    */
+  int32_t dual_unknowns;            /* refined hats of the dual space (2N), or 0   */
 } aim_ctx_info;
 
 typedef struct {

@@ -21,15 +21,18 @@ LIB_PATH = os.path.join(_HERE, "libaim.so")
 
 AIM_OK, AIM_E_ARG, AIM_E_GEOM, AIM_E_OOM, AIM_E_HIP, AIM_E_STATE, AIM_E_NOCONV, AIM_E_NUMERIC = range(8)
 AIM_PULSE, AIM_HAT = 0, 1
-AIM_OP_S, AIM_OP_S_ALPHA, AIM_OP_N, AIM_OP_GRAM_INV, AIM_OP_TM, AIM_OP_TE_CP, AIM_OP_TE_CP_UNF = range(7)
+(AIM_OP_S, AIM_OP_S_ALPHA, AIM_OP_N, AIM_OP_GRAM_INV, AIM_OP_TM, AIM_OP_TE_CP, AIM_OP_TE_CP_UNF, AIM_OP_N_ALPHA,
+ AIM_OP_TM_PC, AIM_OP_TM_PC_UNF, AIM_OP_TM_CP, AIM_OP_TM_CP_UNF) = range(12)
 AIM_OP_GRID_FP32 = 0x100
-AIM_TM_EFIE, AIM_TE_CALDERON, AIM_TE_CALDERON_UNFILTERED = range(3)
+AIM_TM_EFIE, AIM_TE_CALDERON, AIM_TE_CALDERON_UNFILTERED, AIM_TM_CALDERON, AIM_TM_CALDERON_UNFILTERED = range(5)
 AIM_FP64, AIM_MIXED = 0, 1
 AIM_K_ANTERP, AIM_K_ROWS_FWD, AIM_K_COLS, AIM_K_ROWS_INV, AIM_K_INTERP = range(5)
 
 OPS = {'S': AIM_OP_S, 'S_ALPHA': AIM_OP_S_ALPHA, 'N': AIM_OP_N, 'GRAM_INV': AIM_OP_GRAM_INV,
-       'TM': AIM_OP_TM, 'TE_CP': AIM_OP_TE_CP, 'TE_CP_UNF': AIM_OP_TE_CP_UNF}
-FORMS = {'TM': AIM_TM_EFIE, 'TE_CP': AIM_TE_CALDERON, 'TE_CP_UNF': AIM_TE_CALDERON_UNFILTERED}
+       'TM': AIM_OP_TM, 'TE_CP': AIM_OP_TE_CP, 'TE_CP_UNF': AIM_OP_TE_CP_UNF, 'N_ALPHA': AIM_OP_N_ALPHA,
+       'TM_PC': AIM_OP_TM_PC, 'TM_PC_UNF': AIM_OP_TM_PC_UNF, 'TM_CP': AIM_OP_TM_CP, 'TM_CP_UNF': AIM_OP_TM_CP_UNF}
+FORMS = {'TM': AIM_TM_EFIE, 'TE_CP': AIM_TE_CALDERON, 'TE_CP_UNF': AIM_TE_CALDERON_UNFILTERED,
+         'TM_CP': AIM_TM_CALDERON, 'TM_CP_UNF': AIM_TM_CALDERON_UNFILTERED}
 
 
 class AimError(RuntimeError):
@@ -43,7 +46,8 @@ class AimParams(ctypes.Structure):
                 ("k", ctypes.c_double), ("eta", ctypes.c_double), ("basis", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("eps", ctypes.c_double), ("quad", ctypes.c_int32),
                 ("near_radius", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("node_order", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("node_order", ctypes.c_int32),
+                ("dual", ctypes.c_int32)]
 
 
 class AimCtxInfo(ctypes.Structure):
@@ -51,7 +55,8 @@ class AimCtxInfo(ctypes.Structure):
                 ("n_active", ctypes.c_int32), ("active_rows", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("near_nnz_s", ctypes.c_int64), ("near_nnz_n", ctypes.c_int64), ("k", ctypes.c_double),
                 ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
-                ("near_band", ctypes.c_int32), ("node_order", ctypes.c_int32), ("map_points", ctypes.c_int32)]
+                ("near_band", ctypes.c_int32), ("node_order", ctypes.c_int32), ("map_points", ctypes.c_int32),
+                ("dual_unknowns", ctypes.c_int32)]
 
 
 class AimSolveInfo(ctypes.Structure):
@@ -142,7 +147,7 @@ def _as_cols(x, N):
 
 
 def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1, stream=None,
-                node_order=0):
+                node_order=0, dual=0):
     arr = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
     p = AimParams()
     p.n_vertices = arr.shape[0]
@@ -151,12 +156,13 @@ def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM
     p.quad, p.near_radius, p.precision, p.max_rhs = int(quad), int(near_radius), int(precision), int(max_rhs)
     p.stream = stream
     p.node_order = int(node_order)
+    p.dual = int(dual)
     return p, arr
 
 
 def aim_footprint_bytes(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
-                        restart=100, node_order=0):
-    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None, node_order)
+                        restart=100, node_order=0, dual=0):
+    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None, node_order, dual)
     return int(_lib().aim_footprint_bytes(ctypes.byref(p), int(restart)))
 
 
@@ -164,13 +170,13 @@ class Context:
     """Owns one aim_ctx (geometry, grid tables, spectra, near field)."""
 
     def __init__(self, xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
-                 stream=None, node_order=0):
+                 stream=None, node_order=0, dual=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libaim needs a HIP device")
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         p, self._xy = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs,
-                                  _stream_handle(self._stream_obj), node_order)
+                                  _stream_handle(self._stream_obj), node_order, dual)
         h = ctypes.c_void_p()
         _check(_lib().aim_setup(ctypes.byref(p), ctypes.byref(h)), "aim_setup")
         self._h = h

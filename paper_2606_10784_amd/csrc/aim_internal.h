@@ -143,6 +143,12 @@ void free_gmres_work(GmresWork& w);
 
 struct Ctx {
   HostTables t;
+  // dual hat space of the TM Calderon operators: a hat context on the
+  // refined polygon (owned), and the coefficients tau_d of T^-1, T the
+  // circulant (1/8, 3/4, 1/8) with G_pd = diag(h) T
+  Ctx* dual = nullptr;
+  double* d_tau = nullptr;
+  int tau_D = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   int precision = AIM_FP64;
@@ -218,6 +224,7 @@ aim_status dev_alloc(Ctx* c, void** p, size_t bytes);
 aim_status setup_device(Ctx* c);                        // tables, spectrum, near field
 aim_status apply_filter(Ctx* c, double alpha);
 aim_status apply_filter_analytic(Ctx* c, double alpha);
+aim_status setup_dual(Ctx* c);                          // T^-1 coefficients of the dual pairing
 aim_status acquire_spectrum(Ctx* c, double keps);
 void release_spectrum(Ctx* c);
 size_t cache_clear();

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <new>
+#include <vector>
 
 #include "aim_internal.h"
 
@@ -16,10 +17,39 @@ namespace aim {
 void free_ctx(Ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  if (c->dual) {
+    free_ctx(c->dual);
+    delete c->dual;
+    c->dual = nullptr;
+  }
   release_spectrum(c);
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
   free_gmres_work(c->gw);
+}
+
+// the refined polygon of the dual hat space: v_j at 2j, midpoints at 2j+1
+static std::vector<double> refined_xy(const aim_params* p) {
+  const int N = p->n_vertices;
+  std::vector<double> r(4 * (size_t)N);
+  for (int j = 0; j < N; ++j) {
+    const int j1 = (j + 1) % N;
+    r[4 * j] = p->xy[2 * j];
+    r[4 * j + 1] = p->xy[2 * j + 1];
+    r[4 * j + 2] = 0.5 * (p->xy[2 * j] + p->xy[2 * j1]);
+    r[4 * j + 3] = 0.5 * (p->xy[2 * j + 1] + p->xy[2 * j1 + 1]);
+  }
+  return r;
+}
+
+static aim_params dual_params(const aim_params* p, const std::vector<double>& rxy) {
+  aim_params q = *p;
+  q.n_vertices = 2 * p->n_vertices;
+  q.xy = rxy.data();
+  q.basis = AIM_HAT;
+  q.node_order = 0;
+  q.dual = 0;
+  return q;
 }
 
 size_t footprint(const aim_params* p, int restart, const HostTables* t) {
@@ -53,6 +83,11 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   b += N * S * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
   b += 3 * N * R * 16;
   b += (size_t)R * (restart + 1) * N * 16 + (size_t)5 * R * N * 16;
+  if (p->dual && p->basis == AIM_PULSE && p->xy) {   // the dual hat context (no Krylov space)
+    const std::vector<double> rxy = refined_xy(p);
+    const aim_params q = dual_params(p, rxy);
+    b += footprint(&q, 1, nullptr) - (size_t)R * 2 * q.n_vertices * 16 - (size_t)5 * R * q.n_vertices * 16;
+  }
   return b;
 }
 
@@ -83,23 +118,45 @@ aim_status aim_setup(const aim_params* p, aim_ctx* out) {
   if (!p || !out) return AIM_E_ARG;
   *out = nullptr;
   if (p->precision != AIM_FP64 && p->precision != AIM_MIXED) return AIM_E_ARG;
+  if (p->dual != 0 && (p->dual != 1 || p->basis != AIM_PULSE || p->node_order != 0)) return AIM_E_ARG;
   aim_ctx_s* h = new (std::nothrow) aim_ctx_s();
   if (!h) return AIM_E_OOM;
   Ctx* c = &h->c;
   std::string err;
   aim_status st = build_host_tables(p, c->t, err);
+  std::vector<double> rxy;
+  aim_params q;
+  if (st == AIM_OK && p->dual) {
+    // host tables of the dual hat space before any device work
+    rxy = refined_xy(p);
+    q = dual_params(p, rxy);
+    c->dual = new (std::nothrow) Ctx();
+    st = c->dual ? build_host_tables(&q, c->dual->t, err) : AIM_E_OOM;
+  }
   if (st != AIM_OK) {
+    delete c->dual;
+    c->dual = nullptr;
     delete h;
     return st;
   }
-  c->stream = (hipStream_t)p->stream;
-  c->precision = p->precision;
-  c->max_rhs = p->max_rhs;
+  for (Ctx* x : {c, c->dual}) {
+    if (!x) continue;
+    x->stream = (hipStream_t)p->stream;
+    x->precision = p->precision;
+    x->max_rhs = p->max_rhs;
+  }
   if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c->dual;
+    c->dual = nullptr;
     delete h;
     return AIM_E_HIP;
   }
   st = setup_device(c);
+  if (st == AIM_OK && c->dual) {
+    c->dual->device = c->device;
+    st = setup_device(c->dual);
+    if (st == AIM_OK) st = setup_dual(c);
+  }
   if (st != AIM_OK) {
     free_ctx(c);
     delete h;
@@ -111,12 +168,16 @@ aim_status aim_setup(const aim_params* p, aim_ctx* out) {
 
 aim_status aim_filter(aim_ctx ctx, double alpha) {
   if (!ctx || std::isnan(alpha) || !(alpha > 0)) return AIM_E_ARG;
-  return apply_filter(&ctx->c, alpha);
+  aim_status st = apply_filter(&ctx->c, alpha);
+  if (st == AIM_OK && ctx->c.dual) st = apply_filter(ctx->c.dual, alpha);
+  return st;
 }
 
 aim_status aim_filter_analytic(aim_ctx ctx, double alpha) {
   if (!ctx || std::isnan(alpha)) return AIM_E_ARG;
-  return apply_filter_analytic(&ctx->c, alpha);
+  aim_status st = apply_filter_analytic(&ctx->c, alpha);
+  if (st == AIM_OK && ctx->c.dual) st = apply_filter_analytic(ctx->c.dual, alpha);
+  return st;
 }
 
 aim_status aim_matvec(aim_ctx ctx, int32_t op, int32_t nrhs, const void* x_dev, void* y_dev) {
@@ -164,10 +225,11 @@ aim_status aim_get_info(aim_ctx ctx, aim_ctx_info* info) {
   info->k = c.t.k;
   info->eps = c.t.eps;
   info->alpha = c.filtered ? c.alpha : INFINITY;
-  info->device_bytes = c.dev_bytes;
+  info->device_bytes = c.dev_bytes + (c.dual ? c.dual->dev_bytes : 0);
   info->near_band = c.t.band_w;
   info->node_order = c.t.node_order;
   info->map_points = c.t.S;
+  info->dual_unknowns = c.dual ? c.dual->t.N : 0;
   return AIM_OK;
 }
 

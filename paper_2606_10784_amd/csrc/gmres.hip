@@ -810,6 +810,8 @@ static int form_op(int form) {
     case AIM_TM_EFIE: return AIM_OP_TM;
     case AIM_TE_CALDERON: return AIM_OP_TE_CP;
     case AIM_TE_CALDERON_UNFILTERED: return AIM_OP_TE_CP_UNF;
+    case AIM_TM_CALDERON: return AIM_OP_TM_CP;
+    case AIM_TM_CALDERON_UNFILTERED: return AIM_OP_TM_CP_UNF;
   }
   return -1;
 }
@@ -838,15 +840,20 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
   if (op < 0 || nrhs < 1 || nrhs > c->max_rhs || !(tol > 0) || maxit < 1 || restart < 1 || restart > 1000)
     return AIM_E_ARG;
   if (precision == AIM_MIXED && c->precision != AIM_MIXED) return AIM_E_ARG;
-  if (form != AIM_TM_EFIE && c->t.basis != AIM_HAT) return AIM_E_ARG;
-  if (form == AIM_TM_EFIE && c->t.basis != AIM_PULSE) return AIM_E_ARG;
+  const bool tm = form == AIM_TM_EFIE || form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED;
+  if (c->t.basis != (tm ? AIM_PULSE : AIM_HAT)) return AIM_E_ARG;
+  if ((form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED) && !c->dual) return AIM_E_STATE;
   TRY(ensure_work(c, restart, nrhs));
   // keep nrm wide enough for true_resid (2 nrhs)
   GmresWork& w = c->gw;
   const int N = c->t.N;
   hipStream_t s = c->stream;
   const double2* rhs = b;
-  if (form != AIM_TM_EFIE) {
+  if (form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED) {
+    // preconditioned right-hand side G_pd^-T N'(alpha) G_pd^-1 b
+    TRY(matvec(c, form == AIM_TM_CALDERON ? AIM_OP_TM_PC : AIM_OP_TM_PC_UNF, nrhs, b, N, w.b2, N));
+    rhs = w.b2;
+  } else if (form != AIM_TM_EFIE) {
     // preconditioned right-hand side G^-1 S G^-1 b
     TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, b, N, c->d_tmp1, N));
     TRY(matvec(c, form == AIM_TE_CALDERON ? AIM_OP_S_ALPHA : AIM_OP_S, nrhs, c->d_tmp1, N, c->d_tmp2, N));

@@ -1244,8 +1244,117 @@ static aim_status op_grid(Ctx* c, int base_op, int nrhs, const double2* x, int64
     case AIM_OP_N:
       TRY(grid_apply<T>(c, chN, 3, false, nrhs, x, ldx));
       return interp<T>(c, chN, 3, -k2, true, c->d_CN, nrhs, x, ldx, y, ldy, scale);
+    case AIM_OP_N_ALPHA:
+      TRY(grid_apply<T>(c, chN, 3, true, nrhs, x, ldx));
+      return interp<T>(c, chN, 3, -k2, false, nullptr, nrhs, x, ldx, y, ldy, scale);
   }
   return AIM_E_ARG;
+}
+
+// ---------------------------------------------------------------------------
+// dual pairing of the TM Calderon operators.  G_pd = diag(h) T with T the
+// circulant (1/8, 3/4, 1/8); T^-1 is the circulant
+//   tau_d = sqrt(2) (rho^d + rho^(N-d)) / (1 - rho^N),  rho = 2 sqrt(2) - 3,
+// (the two geometric solutions of the three-term recurrence, matched at the
+// wrap) whose terms fall below 1e-18 of tau_0 past |d| = 24, so it is
+// applied as a (2D+1)-term cyclic convolution (all N terms when N <= 2D+1).
+// Dual hats in refined hats: psi_j = h'_2j / 2 + h'_2j+1 + h'_2j+2 / 2.
+// ---------------------------------------------------------------------------
+static constexpr int kTauD = 24;
+
+aim_status setup_dual(Ctx* c) {
+  const int N = c->t.N;
+  const bool full = N <= 2 * kTauD + 1;
+  const int nt = full ? N : kTauD + 1;
+  std::vector<double> tau(nt);
+  const long double rho = 2.0L * std::sqrt(2.0L) - 3.0L;
+  const long double rN = std::pow(rho, (long double)N);
+  for (int d = 0; d < nt; ++d)
+    tau[d] = (double)(std::sqrt(2.0L) * (std::pow(rho, (long double)d) + std::pow(rho, (long double)(N - d))) /
+                      (1.0L - rN));
+  c->tau_D = full ? -1 : kTauD;   // -1: one-sided sum over all N offsets
+  TRY(upload(c, &c->d_tau, tau.data(), nt * 8));
+  AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return AIM_OK;
+}
+
+// (T^-1 z)_i for column z (length N): D >= 0 two-sided band, D < 0 all N
+__device__ __forceinline__ double2 tinv_at(int N, int D, const double* __restrict__ tau, int i,
+                                           const double2* __restrict__ z, const double* __restrict__ hs) {
+  double ax = 0.0, ay = 0.0;
+  if (D < 0) {
+    for (int d = 0; d < N; ++d) {
+      int q = i + d;
+      if (q >= N) q -= N;
+      const double f = hs ? tau[d] / hs[q] : tau[d];
+      ax += f * z[q].x;
+      ay += f * z[q].y;
+    }
+  } else {
+    for (int d = -D; d <= D; ++d) {
+      int q = i + d;
+      q = q < 0 ? q + N : (q >= N ? q - N : q);
+      const double f = hs ? tau[d < 0 ? -d : d] / hs[q] : tau[d < 0 ? -d : d];
+      ax += f * z[q].x;
+      ay += f * z[q].y;
+    }
+  }
+  return make_double2(ax, ay);
+}
+
+// u = R^T G_pd^-1 x (refined-hat coefficients, 2N per column): with
+// z = T^-1 diag(1/h) x, u_2j+1 = z_j and u_2j = (z_j-1 + z_j) / 2
+__global__ void k_dual_in(int N, int nrhs, int D, const double* __restrict__ tau, const double* __restrict__ h,
+                          const double2* __restrict__ x, int64_t ldx, double2* __restrict__ u, int64_t ldu) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (j >= N) return;
+  const double2* xr = x + (size_t)r * ldx;
+  const double2 zj = tinv_at(N, D, tau, j, xr, h);
+  const double2 zm = tinv_at(N, D, tau, j == 0 ? N - 1 : j - 1, xr, h);
+  double2* ur = u + (size_t)r * ldu;
+  ur[2 * j + 1] = zj;
+  ur[2 * j] = make_double2(0.5 * (zm.x + zj.x), 0.5 * (zm.y + zj.y));
+}
+
+// y = G_pd^-T R w = diag(1/h) T^-1 g, g_j = w_2j / 2 + w_2j+1 + w_2j+2 / 2
+__global__ void k_dual_gather(int N, int nrhs, const double2* __restrict__ w, int64_t ldw, double2* __restrict__ g,
+                              int64_t ldg) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (j >= N) return;
+  const double2* wr = w + (size_t)r * ldw;
+  const double2 a = wr[2 * j], b = wr[2 * j + 1], e = wr[j == N - 1 ? 0 : 2 * j + 2];
+  g[(size_t)r * ldg + j] = make_double2(0.5 * a.x + b.x + 0.5 * e.x, 0.5 * a.y + b.y + 0.5 * e.y);
+}
+
+__global__ void k_dual_out(int N, int nrhs, int D, const double* __restrict__ tau, const double* __restrict__ h,
+                           const double2* __restrict__ g, int64_t ldg, double2* __restrict__ y, int64_t ldy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const double2 t = tinv_at(N, D, tau, i, g + (size_t)r * ldg, nullptr);
+  const double ih = 1.0 / h[i];
+  y[(size_t)r * ldy + i] = make_double2(t.x * ih, t.y * ih);
+}
+
+// y = G_pd^-T N'(alpha) G_pd^-1 x through the dual hat context
+static aim_status tm_precond(Ctx* c, bool filtered, bool f32, int nrhs, const double2* x, int64_t ldx, double2* y,
+                             int64_t ldy) {
+  Ctx* d = c->dual;
+  const int N = c->t.N, N2 = d->t.N;
+  const dim3 g((N + 255) / 256, nrhs);
+  hipLaunchKernelGGL(k_dual_in, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_h, x, ldx, d->d_tmp1,
+                     (int64_t)N2);
+  AIM_HIP_CHECK(hipGetLastError());
+  const int nop = (filtered ? AIM_OP_N_ALPHA : AIM_OP_N) | (f32 ? AIM_OP_GRID_FP32 : 0);
+  TRY(matvec(d, nop, nrhs, d->d_tmp1, N2, d->d_tmp2, N2));
+  hipLaunchKernelGGL(k_dual_gather, g, dim3(256), 0, c->stream, N, nrhs, d->d_tmp2, (int64_t)N2, d->d_tmp1,
+                     (int64_t)N);
+  hipLaunchKernelGGL(k_dual_out, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_h, d->d_tmp1,
+                     (int64_t)N, y, ldy);
+  AIM_HIP_CHECK(hipGetLastError());
+  return AIM_OK;
 }
 
 static aim_status gram_inv(Ctx* c, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy) {
@@ -1272,9 +1381,14 @@ aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, doubl
   if (nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
   if (f32 && c->precision != AIM_MIXED) return AIM_E_ARG;
   const bool hat = c->t.basis == AIM_HAT;
-  if ((base == AIM_OP_N || base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF) && !hat) return AIM_E_ARG;
-  // the per-node map has no near-field correction: only S^alpha and G^-1
-  if (c->t.node_order != 0 && base != AIM_OP_S_ALPHA && base != AIM_OP_GRAM_INV) return AIM_E_STATE;
+  if ((base == AIM_OP_N || base == AIM_OP_N_ALPHA || base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF) && !hat)
+    return AIM_E_ARG;
+  const bool tmc = base >= AIM_OP_TM_PC && base <= AIM_OP_TM_CP_UNF;
+  if (tmc && hat) return AIM_E_ARG;
+  if (tmc && !c->dual) return AIM_E_STATE;   // set up without the dual space
+  // the per-node map has no near-field correction: only the filtered operators and G^-1
+  if (c->t.node_order != 0 && base != AIM_OP_S_ALPHA && base != AIM_OP_N_ALPHA && base != AIM_OP_GRAM_INV)
+    return AIM_E_STATE;
   const double2 one = make_double2(1.0, 0.0);
   auto grid = [&](int b, const double2* xx, int64_t lx, double2* yy, int64_t ly, double2 sc) {
     return f32 ? op_grid<float>(c, b, nrhs, xx, lx, yy, ly, sc) : op_grid<double>(c, b, nrhs, xx, lx, yy, ly, sc);
@@ -1284,7 +1398,15 @@ aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, doubl
     case AIM_OP_S:
     case AIM_OP_S_ALPHA:
     case AIM_OP_N:
+    case AIM_OP_N_ALPHA:
       return grid(base, x, ldx, y, ldy, one);
+    case AIM_OP_TM_PC:
+    case AIM_OP_TM_PC_UNF:
+      return tm_precond(c, base == AIM_OP_TM_PC, f32, nrhs, x, ldx, y, ldy);
+    case AIM_OP_TM_CP:
+    case AIM_OP_TM_CP_UNF:
+      TRY(grid(AIM_OP_S, x, ldx, c->d_tmp1, N, make_double2(0.0, c->t.k * c->t.eta)));
+      return tm_precond(c, base == AIM_OP_TM_CP, f32, nrhs, c->d_tmp1, N, y, ldy);
     case AIM_OP_TM:
       return grid(AIM_OP_S, x, ldx, y, ldy, make_double2(0.0, c->t.k * c->t.eta));
     case AIM_OP_GRAM_INV:
@@ -1356,8 +1478,10 @@ __global__ __launch_bounds__(256) void k_mode_quotient(int N, const double2* __r
 aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host, double2* lambda_host) {
   const HostTables& t = c->t;
   const int base = op & 0xff;
-  const bool galerkin = base == AIM_OP_S || base == AIM_OP_S_ALPHA || base == AIM_OP_N || base == AIM_OP_TM;
-  const bool precond = base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF;
+  const bool galerkin = base == AIM_OP_S || base == AIM_OP_S_ALPHA || base == AIM_OP_N || base == AIM_OP_N_ALPHA ||
+                        base == AIM_OP_TM;
+  const bool precond = base == AIM_OP_TE_CP || base == AIM_OP_TE_CP_UNF || base == AIM_OP_TM_CP ||
+                       base == AIM_OP_TM_CP_UNF;
   if (n_modes < 1 || !nu_host || !lambda_host || (!galerkin && !precond)) return AIM_E_ARG;
   const int N = t.N, R = c->max_rhs;
   if (!c->d_spec) TRY(dev_alloc(c, (void**)&c->d_spec, ((size_t)3 * N * R + 2 * (size_t)R) * sizeof(double2)));

@@ -54,3 +54,15 @@ def test_node_map_parameters_checked_on_the_host():
     fb = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 128, 0.0126)
     fn = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 128, 0.0126, node_order=10)
     assert fn > fb
+
+
+def test_dual_space_parameters_checked_on_the_host():
+    lib = aim._lib()
+    h = ctypes.c_void_p()
+    xy = wl.circle(0.5, 40)
+    for basis, dual in ((1, 1), (0, 2)):      # dual hats only for pulses; dual is 0 or 1
+        p, _keep = aim.make_params(xy, wl.K0, wl.ETA0, basis, 64, 0.05, dual=dual)
+        assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+    f0 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05)
+    f1 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, dual=1)
+    assert f1 > f0
