@@ -214,15 +214,18 @@ aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev,
    Calderon products ordered by the Laplace-Beltrami eigenvectors).  For each
    nu_host[q], q < n_modes, with e[j] = exp(i 2 pi nu j / N):
      lambda_q = (e^H G^-1 A e) / (e^H e)   for A = AIM_OP_S, AIM_OP_S_ALPHA,
-                                           AIM_OP_N, AIM_OP_TM (G: Gram matrix),
-     lambda_q = (e^H A e) / (e^H e)        for AIM_OP_TE_CP, AIM_OP_TE_CP_UNF.
+                                           AIM_OP_N, AIM_OP_N_ALPHA, AIM_OP_TM
+                                           (G: Gram matrix),
+     lambda_q = (e^H A e) / (e^H e)        for AIM_OP_TE_CP, AIM_OP_TE_CP_UNF,
+                                           AIM_OP_TM_CP, AIM_OP_TM_CP_UNF.
    On a uniformly discretised circle the matrices are circulant, e is an
    exact eigenvector, |lambda_q| is a singular value and, for the Galerkin
    operators, lambda_q approximates the continuous operator's eigenvalue.
    AIM_OP_GRID_FP32 may be or-ed in (AIM_MIXED contexts).  Modes are applied
    max_rhs at a time through aim_matvec's kernels.  lambda_host: n_modes
    interleaved complex doubles (host).  Synchronous.  Errors: AIM_E_ARG (op,
-   n_modes < 1, basis mismatch as in aim_matvec), AIM_E_OOM, AIM_E_HIP.       */
+   n_modes < 1, basis mismatch as in aim_matvec), AIM_E_STATE (as in
+   aim_matvec), AIM_E_OOM, AIM_E_HIP.                                          */
 aim_status aim_fourier_spectrum(aim_ctx ctx, int32_t op, int32_t n_modes, const int32_t* nu_host,
                                 double* lambda_host);
 
