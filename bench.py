@@ -272,22 +272,24 @@ def batched_360(args):
 
 def spectrum(args):
     """The paper's Sec. IV spectra at its parameters: every Fourier mode
-    0..N/2 of S and S^alpha (pulses, Fig. 2) and of G^-1 S G^-1 N and
-    G^-1 S^alpha G^-1 N (hats, Fig. 3) through aim_fourier_spectrum, modes/s,
-    and the oracle's quotient for a few modes timed on the host."""
+    0..N/2 of S and S^alpha (pulses, Fig. 2), of G^-1 S G^-1 N and
+    G^-1 S^alpha G^-1 N (hats, Fig. 3) and of the TM Calderon products (pulses
+    with the dual hats) through aim_fourier_spectrum, modes/s, and the
+    oracle's quotient for a few modes timed on the host."""
     import numpy as np
     import torch
     from paper_2606_10784_amd import aim
     from paper_2606_10784_amd import workloads as wl
     out = {"workload": "paper_circle_spectrum", "spectra": {}}
     nmax = None
-    for basis, ops in ((wl.PULSE, ("S", "S_ALPHA")), (wl.HAT, ("TE_CP_UNF", "TE_CP"))):
+    for basis, ops, dual in ((wl.PULSE, ("S", "S_ALPHA"), 0), (wl.HAT, ("TE_CP_UNF", "TE_CP"), 0),
+                             (wl.PULSE, ("TM_CP_UNF", "TM_CP"), 1)):
         w = wl.paper_circle(basis)
         N = w.n_unknowns
         nus = np.arange(0, N // 2 + 1)
         nmax = N // 2
         t0 = time.perf_counter()
-        ctx = aim.Context(w.xy, w.k, w.eta, basis, w.m, w.eps, quad=w.quad, max_rhs=64)
+        ctx = aim.Context(w.xy, w.k, w.eta, basis, w.m, w.eps, quad=w.quad, max_rhs=64, dual=dual)
         ctx.filter(w.alpha)
         t_setup = time.perf_counter() - t0
         for op in ops:

@@ -148,6 +148,7 @@ struct Ctx {
   // circulant (1/8, 3/4, 1/8) with G_pd = diag(h) T
   Ctx* dual = nullptr;
   double* d_tau = nullptr;
+  double* d_ih = nullptr;   // 1 / h per segment
   int tau_D = 0;
   hipStream_t stream = nullptr;
   int device = 0;

@@ -1266,35 +1266,39 @@ aim_status setup_dual(Ctx* c) {
   const int N = c->t.N;
   const bool full = N <= 2 * kTauD + 1;
   const int nt = full ? N : kTauD + 1;
-  std::vector<double> tau(nt);
+  std::vector<double> tau(nt), ih(N);
   const long double rho = 2.0L * std::sqrt(2.0L) - 3.0L;
   const long double rN = std::pow(rho, (long double)N);
   for (int d = 0; d < nt; ++d)
     tau[d] = (double)(std::sqrt(2.0L) * (std::pow(rho, (long double)d) + std::pow(rho, (long double)(N - d))) /
                       (1.0L - rN));
+  for (int i = 0; i < N; ++i) ih[i] = 1.0 / c->t.h[i];
   c->tau_D = full ? -1 : kTauD;   // -1: one-sided sum over all N offsets
   TRY(upload(c, &c->d_tau, tau.data(), nt * 8));
+  TRY(upload(c, &c->d_ih, ih.data(), (size_t)N * 8));
   AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
   return AIM_OK;
 }
 
-// (T^-1 z)_i for column z (length N): D >= 0 two-sided band, D < 0 all N
+// (T^-1 diag(s) z)_i for column z (length N), s = 1 when sc is null:
+// D >= 0 the two-sided band of kTauD terms each side, D < 0 all N offsets
 __device__ __forceinline__ double2 tinv_at(int N, int D, const double* __restrict__ tau, int i,
-                                           const double2* __restrict__ z, const double* __restrict__ hs) {
+                                           const double2* __restrict__ z, const double* __restrict__ sc) {
   double ax = 0.0, ay = 0.0;
   if (D < 0) {
     for (int d = 0; d < N; ++d) {
       int q = i + d;
       if (q >= N) q -= N;
-      const double f = hs ? tau[d] / hs[q] : tau[d];
+      const double f = sc ? tau[d] * sc[q] : tau[d];
       ax += f * z[q].x;
       ay += f * z[q].y;
     }
   } else {
-    for (int d = -D; d <= D; ++d) {
+#pragma unroll
+    for (int d = -kTauD; d <= kTauD; ++d) {
       int q = i + d;
       q = q < 0 ? q + N : (q >= N ? q - N : q);
-      const double f = hs ? tau[d < 0 ? -d : d] / hs[q] : tau[d < 0 ? -d : d];
+      const double f = sc ? tau[d < 0 ? -d : d] * sc[q] : tau[d < 0 ? -d : d];
       ax += f * z[q].x;
       ay += f * z[q].y;
     }
@@ -1303,21 +1307,27 @@ __device__ __forceinline__ double2 tinv_at(int N, int D, const double* __restric
 }
 
 // u = R^T G_pd^-1 x (refined-hat coefficients, 2N per column): with
-// z = T^-1 diag(1/h) x, u_2j+1 = z_j and u_2j = (z_j-1 + z_j) / 2
-__global__ void k_dual_in(int N, int nrhs, int D, const double* __restrict__ tau, const double* __restrict__ h,
-                          const double2* __restrict__ x, int64_t ldx, double2* __restrict__ u, int64_t ldu) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (j >= N) return;
+// z = T^-1 diag(1/h) x, u_2j+1 = z_j and u_2j = (z_j-1 + z_j) / 2.  Block b
+// forms z_j for j = 255 b - 1 .. 255 b + 254 in LDS and writes u for the
+// 255 indices j >= 255 b, so every z is computed once.
+__global__ __launch_bounds__(256) void k_dual_in(int N, int nrhs, int D, const double* __restrict__ tau,
+                                                 const double* __restrict__ ih, const double2* __restrict__ x,
+                                                 int64_t ldx, double2* __restrict__ u, int64_t ldu) {
+  __shared__ double2 zs[256];
+  const int t = threadIdx.x, r = blockIdx.y;
+  const int j = blockIdx.x * 255 + t - 1;       // this thread's z index (j = -1: the halo)
   const double2* xr = x + (size_t)r * ldx;
-  const double2 zj = tinv_at(N, D, tau, j, xr, h);
-  const double2 zm = tinv_at(N, D, tau, j == 0 ? N - 1 : j - 1, xr, h);
-  double2* ur = u + (size_t)r * ldu;
-  ur[2 * j + 1] = zj;
-  ur[2 * j] = make_double2(0.5 * (zm.x + zj.x), 0.5 * (zm.y + zj.y));
+  if (j < N) zs[t] = tinv_at(N, D, tau, j < 0 ? N - 1 : j, xr, ih);
+  __syncthreads();
+  if (t >= 1 && j < N) {
+    double2* ur = u + (size_t)r * ldu;
+    const double2 zj = zs[t], zm = zs[t - 1];
+    ur[2 * j + 1] = zj;
+    ur[2 * j] = make_double2(0.5 * (zm.x + zj.x), 0.5 * (zm.y + zj.y));
+  }
 }
 
-// y = G_pd^-T R w = diag(1/h) T^-1 g, g_j = w_2j / 2 + w_2j+1 + w_2j+2 / 2
+// g_j = w_2j / 2 + w_2j+1 + w_2j+2 / 2 (R w)
 __global__ void k_dual_gather(int N, int nrhs, const double2* __restrict__ w, int64_t ldw, double2* __restrict__ g,
                               int64_t ldg) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1328,14 +1338,14 @@ __global__ void k_dual_gather(int N, int nrhs, const double2* __restrict__ w, in
   g[(size_t)r * ldg + j] = make_double2(0.5 * a.x + b.x + 0.5 * e.x, 0.5 * a.y + b.y + 0.5 * e.y);
 }
 
-__global__ void k_dual_out(int N, int nrhs, int D, const double* __restrict__ tau, const double* __restrict__ h,
+// y = G_pd^-T g = diag(1/h) T^-1 g
+__global__ void k_dual_out(int N, int nrhs, int D, const double* __restrict__ tau, const double* __restrict__ ih,
                            const double2* __restrict__ g, int64_t ldg, double2* __restrict__ y, int64_t ldy) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i >= N) return;
   const double2 t = tinv_at(N, D, tau, i, g + (size_t)r * ldg, nullptr);
-  const double ih = 1.0 / h[i];
-  y[(size_t)r * ldy + i] = make_double2(t.x * ih, t.y * ih);
+  y[(size_t)r * ldy + i] = make_double2(t.x * ih[i], t.y * ih[i]);
 }
 
 // y = G_pd^-T N'(alpha) G_pd^-1 x through the dual hat context
@@ -1344,14 +1354,14 @@ static aim_status tm_precond(Ctx* c, bool filtered, bool f32, int nrhs, const do
   Ctx* d = c->dual;
   const int N = c->t.N, N2 = d->t.N;
   const dim3 g((N + 255) / 256, nrhs);
-  hipLaunchKernelGGL(k_dual_in, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_h, x, ldx, d->d_tmp1,
-                     (int64_t)N2);
+  hipLaunchKernelGGL(k_dual_in, dim3((N + 254) / 255, nrhs), dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau,
+                     c->d_ih, x, ldx, d->d_tmp1, (int64_t)N2);
   AIM_HIP_CHECK(hipGetLastError());
   const int nop = (filtered ? AIM_OP_N_ALPHA : AIM_OP_N) | (f32 ? AIM_OP_GRID_FP32 : 0);
   TRY(matvec(d, nop, nrhs, d->d_tmp1, N2, d->d_tmp2, N2));
   hipLaunchKernelGGL(k_dual_gather, g, dim3(256), 0, c->stream, N, nrhs, d->d_tmp2, (int64_t)N2, d->d_tmp1,
                      (int64_t)N);
-  hipLaunchKernelGGL(k_dual_out, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_h, d->d_tmp1,
+  hipLaunchKernelGGL(k_dual_out, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_ih, d->d_tmp1,
                      (int64_t)N, y, ldy);
   AIM_HIP_CHECK(hipGetLastError());
   return AIM_OK;
