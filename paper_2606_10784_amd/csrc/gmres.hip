@@ -874,10 +874,11 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
   } else {
     // iterative refinement: FP64 residual, FP32-grid inner GMRES
     std::vector<double> rel;
-    // Inner solves stop no lower than 10 tol: the FP32 rounding of the grid
-    // product slows the inner Krylov convergence as the inner residual
-    // approaches it, and one more refinement step is cheaper than those steps.
-    const double tin_min = std::min(1e-2, 10.0 * tol);
+    // Inner solves stop no lower than 1e-5 relative (and no lower than
+    // 10 tol): the FP32 grid product is accurate to ~1e-6 relative, the
+    // inner Krylov convergence slows as the inner residual approaches that
+    // level, and one more refinement step is cheaper than those steps.
+    const double tin_min = std::min(1e-2, std::max(1e-5, 10.0 * tol));
     for (outer = 0; outer < 30; ++outer) {
       TRY(true_resid(c, op, nrhs, rhs, x, rel));
       matvecs++;

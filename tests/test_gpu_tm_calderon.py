@@ -123,6 +123,24 @@ def test_tm_calderon_solve_equals_tm_efie():
     assert its["TM_CP_UNF"] < its["TM"]
 
 
+def test_tm_calderon_mixed_precision_solve():
+    """FP64 refinement around an inner GMRES whose grid parts (S and the
+    dual N) are FP32: the FP64 residual of the preconditioned system meets the
+    tolerance and the current equals the FP64 solve's."""
+    a, n, eps = 1.0, 192, 1.0 / 15
+    xy = wl.circle(a, n)
+    ctx, _ = _setup(xy, eps, math.sqrt(2 * math.pi) / eps, precision=aim.AIM_MIXED, max_rhs=1, oracle=False)
+    b = ctx.rhs_planewave(0.0)
+    x64, i64 = ctx.solve("TM_CP_UNF", b, tol=1e-8, restart=200, maxit=2000)
+    xm, im = ctx.solve("TM_CP_UNF", b, tol=1e-8, restart=200, maxit=2000, precision=aim.AIM_MIXED)
+    print("fp64", i64[0]["iterations"], i64[0]["resid_true"], " mixed", im[0]["iterations"], im[0]["outer"],
+          im[0]["resid_true"])
+    assert im[0]["converged"] == 1 and im[0]["resid_true"] <= 1e-8
+    d = np.linalg.norm(xm.cpu().numpy() - x64.cpu().numpy()) / np.linalg.norm(x64.cpu().numpy())
+    print("mixed vs fp64 current", d)
+    assert d < 1e-6
+
+
 def test_tm_calderon_spectrum_on_the_circle():
     """Fourier quotients of the preconditioned TM operator (divided by
     jk eta): unfiltered, the product lambda^N lambda^S of the circle (plateau
