@@ -60,6 +60,12 @@ def test_node_map_s_alpha_matches_oracle(basis, order):
     errf = np.max(np.abs(yf - ref)) / np.max(np.abs(ref))
     print("fp32 grid", errf)
     assert errf < 1e-5
+    if basis == 1:   # the Maue channels through the per-node map
+        refn = orc.apply('N_ALPHA', x)
+        yn = ctx.matvec('N_ALPHA', xt).cpu().numpy().T
+        errn = np.max(np.abs(yn - refn)) / np.max(np.abs(refn))
+        print("N_ALPHA fp64", errn)
+        assert errn < 1e-12
 
 
 def test_node_map_refuses_operators_that_need_the_near_field():
