@@ -70,7 +70,7 @@ def serving(n_req, slots=4, budget=96 << 30):
     stream, then Poisson arrivals at 0.7 of that capacity."""
     from paper_2606_10784_amd import serve
     from paper_2606_10784_amd import workloads as wl
-    exe = serve.GpuExecutor(restart=300)
+    exe = serve.GpuExecutor(restart=1000)
     reqs = wl.serving_stream(n_req, rate=0.0)
     srv = serve.Server(exe, hbm_budget=budget, slots=slots)
     cap = serve.summarize(srv.run(reqs, realtime=False), srv.wall)

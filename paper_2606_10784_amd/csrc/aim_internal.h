@@ -137,6 +137,7 @@ struct GmresWork {
   double* host_resid = nullptr;   // pinned
   int* pin = nullptr;             // pinned mask staging
   int nchunk = 0;
+  size_t lds_max = 65536;         // LDS bytes one block may use on this device
   size_t bytes = 0;
 };
 void free_gmres_work(GmresWork& w);

@@ -614,8 +614,13 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
   w.bytes = tot;
   {
     // a check may rotate up to kCheckEvery + 1 columns (the last one of a
-    // cycle is finalised with the batch)
-    const size_t gb = ((size_t)(kCheckEvery + 1) * ldh + 2 * (size_t)restart) * 16;
+    // cycle is finalised with the batch); batches that do not fit one
+    // block's LDS are split by givens_batches()
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || lds <= 0)
+      return AIM_E_HIP;
+    w.lds_max = (size_t)lds;
+    const size_t gb = std::min(((size_t)(kCheckEvery + 1) * ldh + 2 * (size_t)restart) * 16, w.lds_max);
     if (gb > 65536 &&
         hipFuncSetAttribute((const void*)k_givens_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gb) !=
             hipSuccess)
@@ -740,10 +745,16 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
       }
       const int c1 = last ? j : j - 1;
       if (c1 <= jfin) continue;
-      // rotations for the newly final columns, then their residual estimates
-      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(256), ((size_t)(c1 - jfin) * ldh + 2 * (size_t)c1) * 16, s,
-                         ldh, jfin, c1, w.active, w.H, w.cs, w.sn, w.g, w.resid);
-      AIM_HIP_CHECK(hipGetLastError());
+      // rotations for the newly final columns, then their residual estimates;
+      // in column groups whose LDS footprint fits one block (long restarts)
+      for (int a = jfin; a < c1;) {
+        int e = c1;
+        while (e > a + 1 && ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16 > w.lds_max) --e;
+        hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(256), ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16, s,
+                           ldh, a, e, w.active, w.H, w.cs, w.sn, w.g, w.resid);
+        AIM_HIP_CHECK(hipGetLastError());
+        a = e;
+      }
       for (int r = 0; r < nrhs; ++r)
         if (act[r])
           AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jfin, w.resid + (size_t)r * restart + jfin,

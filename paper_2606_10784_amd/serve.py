@@ -59,7 +59,7 @@ def gpu_footprint(req, restart):
 class GpuExecutor:
     """Runs one request on the calling thread's own stream."""
 
-    def __init__(self, restart=300, maxit=4000, keep_solution=False):
+    def __init__(self, restart=1000, maxit=4000, keep_solution=False):
         self.restart = restart
         self.maxit = maxit
         self.keep = keep_solution

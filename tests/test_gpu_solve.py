@@ -162,3 +162,21 @@ def test_tm_solve_deterministic(tm):
     x1, _ = ctx.solve("TM", _t(b), tol=1e-6, restart=50)
     x2, _ = ctx.solve("TM", _t(b), tol=1e-6, restart=50)
     assert torch.equal(x1, x2)
+
+
+def test_longest_restart_on_a_large_star():
+    """restart = 1000 (the largest allowed): the Givens batches past ~600
+    columns exceed one block's LDS and are split; the solve converges to the
+    same current as a short-restart solve, in fewer steps."""
+    rq = wl.serving_stream(24, 0.0)[9]          # star, ka ~ 320, N = 6400, m = 1024
+    print(f"long restart N={len(rq.xy)} m={rq.m}", flush=True)
+    ctx = aim.Context(rq.xy, rq.k, rq.eta, 0, rq.m, rq.eps, max_rhs=1)
+    b = ctx.rhs_planewave(float(rq.phis[0]))
+    x1, i1 = ctx.solve("TM", b, tol=1e-6, restart=1000, maxit=4000)
+    x3, i3 = ctx.solve("TM", b, tol=1e-6, restart=300, maxit=6000)
+    print("iterations restart 1000:", i1[0]["iterations"], " restart 300:", i3[0]["iterations"])
+    assert i1[0]["converged"] == 1 and i3[0]["converged"] == 1
+    assert i1[0]["iterations"] > 620                  # reached the split batches
+    assert i1[0]["iterations"] < i3[0]["iterations"]
+    a, c = x1.cpu().numpy(), x3.cpu().numpy()
+    assert np.linalg.norm(a - c) / np.linalg.norm(c) < 1e-3
