@@ -56,3 +56,22 @@ def test_every_grid_size_matches_oracle(m, basis):
         assert e32 < 1e-5
     z = torch.zeros_like(xt)
     assert torch.count_nonzero(ctx.matvec("S_ALPHA", z)).item() == 0
+
+
+@pytest.mark.parametrize("basis", [0, 1])
+def test_smallest_polygon_and_grid(basis):
+    """The smallest accepted inputs: an octagon (N = 8, every pair in the near
+    zone) on the 16 x 16 grid, one rhs."""
+    xy = wl.circle(0.45, 8)
+    print(f"octagon basis={basis}", flush=True)
+    alpha = wl.alpha_half_bins(EPS)
+    ctx = aim.Context(xy, K, ETA, basis, 16, EPS, max_rhs=1)
+    ctx.filter(alpha)
+    orc = oaim.AimOracle(xy, K, ETA, basis, 16, EPS, alpha=alpha)
+    x = np.random.default_rng(8).standard_normal(8) + 1j * np.random.default_rng(9).standard_normal(8)
+    for op in (("S", "S_ALPHA", "TM") if basis == 0 else ("S_ALPHA", "N", "GRAM_INV", "TE_CP")):
+        ref = orc.apply(op, x)
+        y = ctx.matvec(op, torch.from_numpy(x).cuda()).cpu().numpy()
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        print(op, err)
+        assert err < 1e-12
