@@ -37,7 +37,7 @@ def _fine_circle(n, a, ratio=6.24, margin=14):
     return xy, m, eps
 
 
-@pytest.mark.parametrize("basis,order", [(0, 10), (0, 6), (1, 8)])
+@pytest.mark.parametrize("basis,order", [(0, 10), (0, 6), (0, 2), (1, 8)])
 def test_node_map_s_alpha_matches_oracle(basis, order):
     xy, m, eps = _fine_circle(40, 0.5)
     alpha = 8 * K
