@@ -180,3 +180,23 @@ def test_longest_restart_on_a_large_star():
     assert i1[0]["iterations"] < i3[0]["iterations"]
     a, c = x1.cpu().numpy(), x3.cpu().numpy()
     assert np.linalg.norm(a - c) / np.linalg.norm(c) < 1e-3
+
+
+def test_degenerate_right_hand_sides():
+    """A zero column beside a nonzero one: x = 0 for it, converged, no NaN;
+    and an exact initial guess: returned after the first residual check."""
+    n = 64
+    xy = wl.circle(1.0, n)
+    ctx = aim.Context(xy, K, ETA, 0, 64, 0.1, max_rhs=2)
+    b1 = ctx.rhs_planewave(0.7).cpu().numpy()
+    B = torch.from_numpy(np.stack([np.zeros(n, complex), b1])).cuda()
+    X, info = ctx.solve("TM", B, tol=1e-10, restart=40, maxit=200)
+    Xs = X.cpu().numpy()
+    print([(d["iterations"], d["converged"], d["resid_true"]) for d in info])
+    assert np.all(np.isfinite(Xs))
+    assert np.all(Xs[0] == 0) and info[0]["converged"] == 1 and info[0]["iterations"] == 0
+    assert info[1]["converged"] == 1 and info[1]["resid_true"] <= 1e-10
+    x0 = torch.from_numpy(Xs[1]).cuda()
+    x2, i2 = ctx.solve("TM", torch.from_numpy(b1).cuda(), x0=x0, tol=1e-8, restart=40, maxit=200)
+    assert i2[0]["converged"] == 1 and i2[0]["iterations"] == 0
+    assert np.array_equal(x2.cpu().numpy(), Xs[1])
