@@ -95,6 +95,10 @@ enum {
 
 enum { AIM_FP64 = 0, AIM_MIXED = 1 };
 
+/* Largest batch of right-hand sides: max_rhs of aim_setup and nrhs of
+   aim_rhs_planewave (launch grids carry one block row per rhs and channel).  */
+#define AIM_MAX_RHS 4096
+
 typedef struct {
   int32_t n_vertices;     /* N >= 3: closed polygon, CCW, segment j = v_j -> v_{j+1} */
   const double* xy;       /* host, 2N interleaved (x, y); copied during aim_setup   */
@@ -106,7 +110,7 @@ typedef struct {
   int32_t quad;           /* Gauss-Legendre nodes per segment in the stencils (>=1) */
   int32_t near_radius;    /* anchor Chebyshev radius of the near zone (>= 3)        */
   int32_t precision;      /* AIM_FP64 or AIM_MIXED (also builds the FP32 grid data) */
-  int32_t max_rhs;        /* largest nrhs of later calls (>= 1)                     */
+  int32_t max_rhs;        /* largest nrhs of later calls (1..AIM_MAX_RHS)           */
   void* stream;           /* hipStream_t for all device work (NULL: default stream) */
   int32_t node_order;     /* form of Lambda (Sec. III-A).  0: one 4 x 4 cubic
                              Lagrange stencil per basis at its centre cell, with
@@ -185,7 +189,8 @@ aim_status aim_matvec(aim_ctx ctx, int32_t op, int32_t nrhs, const void* x_dev, 
 /* Plane-wave right-hand sides, one column per angle (propagation direction
    (cos phi, sin phi), amplitude amp): pulse basis b_i = <phi_i, E_z^inc>
    (TM); hat basis b_i = <phi_i, (jk/eta) t.E^inc> with
-   E^inc = eta amp (z x khat) e^{-jk khat.r} (Sec. II).  b_dev: c128 N x nrhs.  */
+   E^inc = eta amp (z x khat) e^{-jk khat.r} (Sec. II).  b_dev: c128 N x nrhs,
+   1 <= nrhs <= AIM_MAX_RHS (else AIM_E_ARG).  Synchronises the stream.        */
 aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_host,
                              double amp, void* b_dev);
 

@@ -26,6 +26,7 @@ AIM_PULSE, AIM_HAT = 0, 1
 AIM_OP_GRID_FP32 = 0x100
 AIM_TM_EFIE, AIM_TE_CALDERON, AIM_TE_CALDERON_UNFILTERED, AIM_TM_CALDERON, AIM_TM_CALDERON_UNFILTERED = range(5)
 AIM_FP64, AIM_MIXED = 0, 1
+AIM_MAX_RHS = 4096
 AIM_K_ANTERP, AIM_K_ROWS_FWD, AIM_K_COLS, AIM_K_ROWS_INV, AIM_K_INTERP = range(5)
 
 OPS = {'S': AIM_OP_S, 'S_ALPHA': AIM_OP_S_ALPHA, 'N': AIM_OP_N, 'GRAM_INV': AIM_OP_GRAM_INV,

@@ -105,7 +105,7 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
   if (p->quad < 1 || p->quad > 64) { err = "quad must be in [1, 64]"; return AIM_E_ARG; }
   if (p->near_radius < 0 || p->near_radius + 3 > m - 1) { err = "near_radius out of range"; return AIM_E_ARG; }
   if (p->basis != AIM_PULSE && p->basis != AIM_HAT) { err = "basis"; return AIM_E_ARG; }
-  if (p->max_rhs < 1) { err = "max_rhs"; return AIM_E_ARG; }
+  if (p->max_rhs < 1 || p->max_rhs > AIM_MAX_RHS) { err = "max_rhs"; return AIM_E_ARG; }
   const int P = p->node_order;
   if (P != 0 && (P < 2 || P > 12 || (P & 1))) { err = "node_order must be 0 or even in 2..12"; return AIM_E_ARG; }
   t.node_order = P;

@@ -1433,15 +1433,18 @@ aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, doubl
 
 aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b) {
   HostTables& t = c->t;
-  if (nrhs < 1) return AIM_E_ARG;
+  if (nrhs < 1 || nrhs > AIM_MAX_RHS) return AIM_E_ARG;
   double* d_phi = nullptr;
-  AIM_HIP_CHECK(hipMalloc(&d_phi, nrhs * 8));
-  hipMemcpyAsync(d_phi, phi_host, nrhs * 8, hipMemcpyHostToDevice, c->stream);
-  hipLaunchKernelGGL(k_rhs, dim3((t.N + 127) / 128, nrhs), dim3(128), 0, c->stream, t.N, nrhs, t.basis, t.p,
-                     c->d_glx, c->d_glw, c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, d_phi, t.k, t.eta, amp, b);
-  hipError_t e = hipStreamSynchronize(c->stream);
+  AIM_HIP_CHECK(hipMalloc(&d_phi, (size_t)nrhs * 8));
+  hipError_t e = hipMemcpyAsync(d_phi, phi_host, (size_t)nrhs * 8, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_rhs, dim3((t.N + 127) / 128, nrhs), dim3(128), 0, c->stream, t.N, nrhs, t.basis, t.p,
+                       c->d_glx, c->d_glw, c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, d_phi, t.k, t.eta, amp, b);
+    e = hipGetLastError();
+  }
+  const hipError_t es = hipStreamSynchronize(c->stream);
   hipFree(d_phi);
-  return e == hipSuccess ? AIM_OK : AIM_E_HIP;
+  return e == hipSuccess && es == hipSuccess ? AIM_OK : AIM_E_HIP;
 }
 
 // ---------------------------------------------------------------------------

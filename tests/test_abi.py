@@ -1,6 +1,7 @@
 """C-ABI library: loads and exports every function include/aim.h declares
 (no compute calls; runs without a GPU)."""
 import ctypes
+import os
 
 import pytest
 
@@ -66,3 +67,18 @@ def test_dual_space_parameters_checked_on_the_host():
     f0 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05)
     f1 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, dual=1)
     assert f1 > f0
+
+
+def test_batch_size_bounded_on_the_host():
+    """max_rhs in 1..AIM_MAX_RHS (the launch grids hold one block row per rhs
+    and channel), decided before any device call; the binding's constant is
+    the header's."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "aim.h")).read()
+    assert int(re.search(r"#define AIM_MAX_RHS (\d+)", hdr).group(1)) == aim.AIM_MAX_RHS
+    lib = aim._lib()
+    h = ctypes.c_void_p()
+    xy = wl.circle(0.5, 40)
+    for bad in (0, aim.AIM_MAX_RHS + 1):
+        p, _keep = aim.make_params(xy, wl.K0, wl.ETA0, 0, 64, 0.05, max_rhs=bad)
+        assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
