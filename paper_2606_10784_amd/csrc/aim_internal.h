@@ -72,6 +72,14 @@ __host__ __device__ inline int spec_last_radix(int n) {
   while (rl > 16) rl >>= 4;
   return rl;
 }
+// Rows per tile of the row/column intermediate (the tile stride is ldt rows
+// of CB values).  The row passes touch every tile of a pair at this stride,
+// so a row count with a large power-of-two factor concentrates them on few
+// HBM channels (960 rows at CB = 2 in FP64, a 30 720 B = 15 * 2^11 B stride:
+// the inverse row pass 22 % slower than at 958 rows).  A multiple of 4 gets
+// one padding row, which leaves at most a factor 2 in the row count.
+inline int tile_rows(int nr) { return nr % 4 == 0 ? nr + 1 : nr; }
+
 __host__ __device__ inline int spec_row_len(int n) {
   const int rl = spec_last_radix(n);
   return (n / rl / 2 + 1) * rl;

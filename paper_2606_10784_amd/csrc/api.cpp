@@ -76,7 +76,7 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   const size_t near = t ? t->nr_col.size()
                         : (p->node_order > 0 ? 0 : N * (size_t)((2 * p->near_radius + 1) * 3));
   size_t b = 0;
-  b += nch * R * (nr * n + 2 * nact) * 16;               // U, T, V
+  b += nch * R * ((size_t)tile_rows((int)nr) * n + 2 * nact) * 16;   // U, T, V
   b += 2 * H * spec_row_len((int)n) * 16 * (p->precision == AIM_MIXED ? 1.5 : 1.0);
   b += near * (4 + 16 * (p->basis == AIM_HAT ? 2 : 1));
   if (t && t->band_w >= 0) b += (size_t)(t->band_w + 1) * N * 16 * (p->basis == AIM_HAT ? 2 : 1);

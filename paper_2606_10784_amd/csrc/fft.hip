@@ -535,7 +535,8 @@ __device__ __forceinline__ int xcd_row(int bid, int nrows) {
 }
 
 // ---------------------------------------------------------------------------
-// kernels.  T layout (tiled): [pair][block][row][CB]
+// kernels.  T layout (tiled): [pair][block][row][CB] with ldt >= nr rows
+// per tile (tile_rows); rows nr .. ldt-1 are never read or written
 // ---------------------------------------------------------------------------
 template <int N> constexpr int row_threads() { return N / 16 < 64 ? 64 : (N / 16 > 256 ? 256 : N / 16); }
 
@@ -545,7 +546,7 @@ template <int N> constexpr int row_threads() { return N / 16 < 64 ? 64 : (N / 16
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     const cplx<T>* __restrict__ U, int n_act, const int32_t* __restrict__ row_ptr,
-    const int32_t* __restrict__ act_ix, int nr, cplx<T>* __restrict__ Tb,
+    const int32_t* __restrict__ act_ix, int nr, int ldt, cplx<T>* __restrict__ Tb,
     const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
   static_assert(N >= 32, "row pass assumes at least two forward passes");
@@ -591,7 +592,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
   chain_passes<T, N, NT, false, 16, N, false>(buf, wt);
   // pairs of lanes fill the CB-wide segments of the tiled layout; the LDS
   // reads of a thread are all issued before its stores
-  V* out = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  V* out = Tb + (size_t)pair * NBLK * ldt * CB + (size_t)row * CB;
   constexpr int PER = (N + NT - 1) / NT;
   V v[PER];
 #pragma unroll
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = tid + q * NT;
-    if ((N % NT) == 0 || idx < N) out[(size_t)(idx / CB) * nr * CB + idx % CB] = v[q];
+    if ((N % NT) == 0 || idx < N) out[(size_t)(idx / CB) * ldt * CB + idx % CB] = v[q];
   }
 }
 
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
 // and computes only the outputs x < N/2, where the active points lie.
 template <typename T, int N>
 __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
-    const cplx<T>* __restrict__ Tb, int nr, const int32_t* __restrict__ row_ptr,
+    const cplx<T>* __restrict__ Tb, int nr, int ldt, const int32_t* __restrict__ row_ptr,
     const int32_t* __restrict__ act_ix, cplx<T>* __restrict__ Vout, int n_act,
     const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
   const int row = xcd_row(blockIdx.x, nr), pair = blockIdx.y;
   const int tid = threadIdx.x;
   if (row >= nr) return;
-  const V* in = Tb + (size_t)pair * NBLK * nr * CB + (size_t)row * CB;
+  const V* in = Tb + (size_t)pair * NBLK * ldt * CB + (size_t)row * CB;
   // base twiddles of the radix-16 passes and of the last pass, loaded with
   // the row
   constexpr int NW = chain_len<N, NT, RL, N / 16, true>();
@@ -647,7 +648,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_inv(
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * NT;
-      if ((N % NT) == 0 || idx < N) v[q] = in[(size_t)(idx / CB) * nr * CB + idx % CB];
+      if ((N % NT) == 0 || idx < N) v[q] = in[(size_t)(idx / CB) * ldt * CB + idx % CB];
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -714,7 +715,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 // row-major N x N array.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
-    cplx<T>* __restrict__ Tb, int nr, const cplx<T>* __restrict__ Cq,
+    cplx<T>* __restrict__ Tb, int nr, int ldt, const cplx<T>* __restrict__ Cq,
     const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
   constexpr int CB = ColCfg<T, N>::CB;
@@ -734,7 +735,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
     constexpr int NB1 = S1 * CB, PER1 = (NB1 + NT - 1) / NT;
     constexpr int NBM = (N / 16) * CB, PERM = (NBM + NT - 1) / NT;
     constexpr int NG = N / RL, NBF = NG * CB, PERF = (NBF + NT - 1) / NT;
-    V* tile = Tb + ((size_t)pair * NBLK + b) * nr * CB;
+    V* tile = Tb + ((size_t)pair * NBLK + b) * ldt * CB;
     // forward pass 1 (stride N/16, radix 16) from HBM: inputs m + S1 r with
     // r >= 8 lie in the zero half
     V v[PER1][16];
@@ -876,14 +877,15 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
 
 template <typename T>
 aim_status launch_rows_fwd(int n, const cplx<T>* U, int n_act, const int32_t* row_ptr,
-                           const int32_t* act_ix, int nr, int pairs, cplx<T>* Tb,
+                           const int32_t* act_ix, int nr, int ldt, int pairs, cplx<T>* Tb,
                            const cplx<T>* tw, hipStream_t s) {
+  if (ldt < nr) return AIM_E_ARG;
   dim3 g(8 * ((nr + 7) / 8), pairs);
   switch (n) {
 #define CASE(NN)                                                                               \
   case NN:                                                                                     \
     hipLaunchKernelGGL((k_rows_fwd<T, NN>), g, dim3(row_threads<NN>()), 0, s, U, n_act, row_ptr, \
-                       act_ix, nr, Tb, tw);                                                    \
+                       act_ix, nr, ldt, Tb, tw);                                               \
     break;
     AIM_FOR_SIZES(CASE)
 #undef CASE
@@ -893,15 +895,16 @@ aim_status launch_rows_fwd(int n, const cplx<T>* U, int n_act, const int32_t* ro
 }
 
 template <typename T>
-aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_ptr,
+aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, int ldt, const int32_t* row_ptr,
                            const int32_t* act_ix, int pairs, cplx<T>* V, int n_act,
                            const cplx<T>* tw, hipStream_t s) {
+  if (ldt < nr) return AIM_E_ARG;
   dim3 g(8 * ((nr + 7) / 8), pairs);
   switch (n) {
 #define CASE(NN)                                                                               \
   case NN:                                                                                     \
-    hipLaunchKernelGGL((k_rows_inv<T, NN>), g, dim3(row_threads<NN>()), 0, s, Tb, nr, row_ptr,  \
-                       act_ix, V, n_act, tw);                                                  \
+    hipLaunchKernelGGL((k_rows_inv<T, NN>), g, dim3(row_threads<NN>()), 0, s, Tb, nr, ldt,      \
+                       row_ptr, act_ix, V, n_act, tw);                                         \
     break;
     AIM_FOR_SIZES(CASE)
 #undef CASE
@@ -911,18 +914,19 @@ aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_
 }
 
 template <typename T>
-aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int pairs, const cplx<T>* Cq,
+aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int ldt, int pairs, const cplx<T>* Cq,
                        const cplx<T>* tw, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  if (mode == 0 && (nr < 1 || nr > n / 2)) return AIM_E_ARG;   // kept rows lie in the unpadded half
+  // kept rows lie in the unpadded half
+  if (mode == 0 && (nr < 1 || nr > n / 2 || ldt < nr)) return AIM_E_ARG;
   switch (n) {
 #define CASE(NN)                                                                          \
   case NN: {                                                                              \
     dim3 g(NN / ColCfg<T, NN>::CB, pairs);                                                \
     if (mode == 0)                                                                        \
       hipExtLaunchKernelGGL((k_cols<T, NN, 0>), g, dim3(ColCfg<T, NN>::NT), 0, s, ev_start, ev_stop, 0, \
-                            Tb, nr, Cq, tw);                                              \
+                            Tb, nr, ldt, Cq, tw);                                         \
     else                                                                                  \
-      hipLaunchKernelGGL((k_cols<T, NN, 1>), g, dim3(ColCfg<T, NN>::NT), 0, s, Tb, nr, Cq, tw); \
+      hipLaunchKernelGGL((k_cols<T, NN, 1>), g, dim3(ColCfg<T, NN>::NT), 0, s, Tb, nr, ldt, Cq, tw); \
     break;                                                                                \
   }
     AIM_FOR_SIZES(CASE)
@@ -945,17 +949,17 @@ aim_status launch_rows_fft_inplace(int n, double2* A, const double2* tw, hipStre
   return hipGetLastError() == hipSuccess ? AIM_OK : AIM_E_HIP;
 }
 
-template aim_status launch_rows_fwd<double>(int, const double2*, int, const int32_t*, const int32_t*, int, int,
+template aim_status launch_rows_fwd<double>(int, const double2*, int, const int32_t*, const int32_t*, int, int, int,
                                             double2*, const double2*, hipStream_t);
-template aim_status launch_rows_fwd<float>(int, const float2*, int, const int32_t*, const int32_t*, int, int,
+template aim_status launch_rows_fwd<float>(int, const float2*, int, const int32_t*, const int32_t*, int, int, int,
                                            float2*, const float2*, hipStream_t);
-template aim_status launch_rows_inv<double>(int, const double2*, int, const int32_t*, const int32_t*, int,
+template aim_status launch_rows_inv<double>(int, const double2*, int, int, const int32_t*, const int32_t*, int,
                                             double2*, int, const double2*, hipStream_t);
-template aim_status launch_rows_inv<float>(int, const float2*, int, const int32_t*, const int32_t*, int,
+template aim_status launch_rows_inv<float>(int, const float2*, int, int, const int32_t*, const int32_t*, int,
                                            float2*, int, const float2*, hipStream_t);
-template aim_status launch_cols<double>(int, int, double2*, int, int, const double2*, const double2*, hipStream_t,
-                                        hipEvent_t, hipEvent_t);
-template aim_status launch_cols<float>(int, int, float2*, int, int, const float2*, const float2*, hipStream_t,
+template aim_status launch_cols<double>(int, int, double2*, int, int, int, const double2*, const double2*,
+                                        hipStream_t, hipEvent_t, hipEvent_t);
+template aim_status launch_cols<float>(int, int, float2*, int, int, int, const float2*, const float2*, hipStream_t,
                                        hipEvent_t, hipEvent_t);
 
 }  // namespace aim

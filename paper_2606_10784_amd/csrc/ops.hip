@@ -20,14 +20,14 @@ namespace aim {
 
 template <typename T>
 aim_status launch_rows_fwd(int n, const cplx<T>* U, int n_act, const int32_t* row_ptr,
-                           const int32_t* act_ix, int nr, int pairs, cplx<T>* Tb,
+                           const int32_t* act_ix, int nr, int ldt, int pairs, cplx<T>* Tb,
                            const cplx<T>* tw, hipStream_t s);
 template <typename T>
-aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, const int32_t* row_ptr,
+aim_status launch_rows_inv(int n, const cplx<T>* Tb, int nr, int ldt, const int32_t* row_ptr,
                            const int32_t* act_ix, int pairs, cplx<T>* V, int n_act,
                            const cplx<T>* tw, hipStream_t s);
 template <typename T>
-aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int pairs, const cplx<T>* Cq,
+aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int ldt, int pairs, const cplx<T>* Cq,
                        const cplx<T>* tw, hipStream_t s, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr);
 aim_status launch_rows_fft_inplace(int n, double2* A, const double2* tw, hipStream_t s);
@@ -906,7 +906,7 @@ aim_status acquire_spectrum(Ctx* c, double keps) {
   }
   hipLaunchKernelGGL(k_sample_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, m, n, keps, cfull);
   aim_status st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
-  if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
+  if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, n, 1, nullptr, c->d_tw, s);
   if (st == AIM_OK) {
     hipLaunchKernelGGL(k_extract_spectrum, dim3((spec_row_len(n) + 255) / 256, H), dim3(256), 0, s, n, cfull, e->C, e->Cf);
     if (hipStreamSynchronize(s) != hipSuccess) st = AIM_E_HIP;
@@ -1058,7 +1058,7 @@ aim_status setup_device(Ctx* c) {
   const size_t be = 16;   // FP64 complex (FP32 uses the first half)
   TRY(dev_alloc(c, &c->d_U, pairs * t.n_act * be));
   TRY(dev_alloc(c, &c->d_V, pairs * t.n_act * be));
-  TRY(dev_alloc(c, &c->d_T, pairs * (size_t)t.nr * n * be));
+  TRY(dev_alloc(c, &c->d_T, pairs * (size_t)tile_rows(t.nr) * n * be));
   TRY(dev_alloc(c, (void**)&c->d_tmp1, (size_t)N * c->max_rhs * 16));
   TRY(dev_alloc(c, (void**)&c->d_tmp2, (size_t)N * c->max_rhs * 16));
   TRY(dev_alloc(c, (void**)&c->d_rhs, (size_t)N * c->max_rhs * 16));
@@ -1119,7 +1119,7 @@ aim_status apply_filter_analytic(Ctx* c, double alpha) {
     st = hipGetLastError() == hipSuccess ? AIM_OK : AIM_E_HIP;
   }
   if (st == AIM_OK) st = launch_rows_fft_inplace(n, cfull, c->d_tw, s);
-  if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, 1, nullptr, c->d_tw, s);
+  if (st == AIM_OK) st = launch_cols<double>(n, 1, cfull, n, n, 1, nullptr, c->d_tw, s);
   if (st == AIM_OK) {
     hipLaunchKernelGGL(k_extract_spectrum, dim3((spec_row_len(n) + 255) / 256, H), dim3(256), 0, s, n, cfull, c->own_Ca,
                        c->own_Caf);
@@ -1166,17 +1166,17 @@ static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int n
                           : (const cplx<T>*)(filt ? (void*)c->d_Ca : (void*)c->d_C);
   {
     ProfScope ps(c, AIM_K_ROWS_FWD);
-    TRY(launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, pairs, Tb, tw, s));
+    TRY(launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, tile_rows(t.nr), pairs, Tb, tw, s));
   }
   {
     // the dominant kernel's sampled launches carry their events in the
     // dispatch itself, so the interval is the kernel's own execution
     ProfScope ps(c, AIM_K_COLS, true);
-    TRY(launch_cols<T>(t.n, 0, Tb, t.nr, pairs, Cq, tw, s, ps.start(), ps.stop()));
+    TRY(launch_cols<T>(t.n, 0, Tb, t.nr, tile_rows(t.nr), pairs, Cq, tw, s, ps.start(), ps.stop()));
   }
   {
     ProfScope ps(c, AIM_K_ROWS_INV);
-    TRY(launch_rows_inv<T>(t.n, Tb, t.nr, c->d_row_ptr, c->d_act_ix, pairs, V, t.n_act, tw, s));
+    TRY(launch_rows_inv<T>(t.n, Tb, t.nr, tile_rows(t.nr), c->d_row_ptr, c->d_act_ix, pairs, V, t.n_act, tw, s));
   }
   return AIM_OK;
 }
