@@ -269,3 +269,27 @@ def test_filter_analytic_matches_oracle():
     with pytest.raises(aim.AimError):
         ctx.filter_analytic(0.5 * K)
     ctx.close()
+
+
+@pytest.mark.parametrize("a", [1.0, 1.1, 1.2])
+def test_tile_row_stride_padding(a):
+    """The FFT intermediate pads a tile to nr + 1 rows when the active row
+    count nr is a multiple of 4 (radii 1.0 and 1.2: 24 and 28 rows) and keeps
+    nr rows otherwise (radius 1.1: 26).  Both layouts match the oracle: FP64
+    bound 1e-12, FP32 grid 1e-5."""
+    xy = wl.circle(a, 128)
+    m, eps = 64, 0.1
+    orc = oaim.AimOracle(xy, K, ETA, 0, m, eps)
+    nr = int(np.ptp(np.asarray(orc.act_iy))) + 1
+    ctx = aim.Context(xy, K, ETA, 0, m, eps, max_rhs=2, precision=aim.AIM_MIXED)
+    try:
+        assert ctx.info()["active_rows"] == nr
+        x = wl.probe_vector(128, nrhs=2, seed=11)
+        ref = np.stack([orc.apply("S", x[:, r]) for r in range(2)], axis=1)
+        y = _n(ctx.matvec("S", _t(x)))
+        yf = _n(ctx.matvec(aim.OPS["S"] | aim.AIM_OP_GRID_FP32, _t(x)))
+        e64, e32 = _relmax(y, ref), _relmax(yf, ref)
+        print(f"a={a} nr={nr} (mod 4: {nr % 4}) fp64 {e64:.2e} fp32 grid {e32:.2e}")
+        assert e64 < 1e-12 and e32 < 1e-5
+    finally:
+        ctx.close()
