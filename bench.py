@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--restart", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+                    help="with --mode matvec: also run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--matvecs", type=int, default=50, help="matvec-only timing loop length")
     ap.add_argument("--mode", default="solve", choices=["solve", "matvec"],
                     help="matvec: set-up plus --matvecs FP64 matvecs only (short runs for counters)")
@@ -460,12 +460,19 @@ def main():
     t_mixed = time.perf_counter() - tm0
     dx = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
 
-    if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
+    # achievable HBM rate: a plain 1 GiB device-to-device copy (read + write)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    for _ in range(3):
         dst.copy_(src)
-        torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
 
     alg_b = kernel_bytes(dom, inf)
     achieved = alg_b / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
@@ -505,7 +512,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(names[dom]),
                      "alg_bytes_per_launch": alg_b, "avg_ms": dom_ms, "samples": dom_samples,
                      "sample_every": PROF_EVERY,
-                     "flops_per_launch": kernel_flops(dom, inf)},
+                     "flops_per_launch": kernel_flops(dom, inf),
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "setup_s": t_setup,
     }
     ctx.close()
