@@ -197,17 +197,11 @@ __device__ __forceinline__ void dft_r(cplx<T>* v) {
   else dft2<cplx<T>, INV>(v[0], v[1]);
 }
 
-#ifndef AIM_PAD_SHIFT
-#define AIM_PAD_SHIFT 4
-#endif
-#ifndef AIM_TW_RECUR
-#define AIM_TW_RECUR 1
-#endif
 // LDS index with one pad slot per 16 elements: the radix-16 first pass
 // stores with a stride of 16 elements, which the pad turns into 17 so the
 // lanes of a wave spread over all banks.
-__device__ __forceinline__ int pidx(int i) { return i + (i >> AIM_PAD_SHIFT); }
-__host__ __device__ constexpr int padded(int n) { return n + (n >> AIM_PAD_SHIFT); }
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
 
 // w^r for r = 1..R-1 from w = w^1 by a product tree of depth <= 4
 template <typename V, int R>
@@ -237,21 +231,12 @@ __device__ __forceinline__ void pass_twiddle(cplx<T>* v, int j, const cplx<T>* _
   using V = cplx<T>;
   if constexpr (NS > 1) {
     const int k = j & (NS - 1);
-#if AIM_TW_RECUR
     V w1 = tw[k * (N / (NS * R))];
     if (INV) w1.y = -w1.y;
     V wp[R];
     tw_powers<V, R>(w1, wp);
 #pragma unroll
     for (int r = 1; r < R; ++r) v[r] = cmul(v[r], wp[r]);
-#else
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-      V w = tw[k * r * (N / (NS * R))];
-      if (INV) w.y = -w.y;
-      v[r] = cmul(v[r], w);
-    }
-#endif
   }
 }
 
@@ -491,11 +476,8 @@ template <int N> constexpr int last_radix() {
 // pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror N - q); the last slot pair
 // of the last block holds the self-mirrored columns 0 and N/2.
 // ---------------------------------------------------------------------------
-#ifndef AIM_COL_LDS_BYTES
-#define AIM_COL_LDS_BYTES 80000   // padded LDS per column block: two blocks per CU
-#endif
 template <typename T, int N> struct ColCfg {
-  static constexpr int BYTES = AIM_COL_LDS_BYTES;
+  static constexpr int BYTES = 80000;   // padded LDS per column block: two blocks per CU
   static constexpr int CB0 = BYTES / (padded(N) * (int)sizeof(cplx<T>));
   static constexpr int CB1 = CB0 < 2 ? 2 : (CB0 > 16 ? 16 : CB0);
   static constexpr int CB = (CB1 >= 16) ? 16 : (CB1 >= 8 ? 8 : (CB1 >= 4 ? 4 : 2));
