@@ -115,3 +115,28 @@ def test_star_65536_gram_inverse_property(star65k):
     _, _, h, _, _ = segments(w.xy)
     Gz = (np.roll(h, 1) + h) / 3 * z + np.roll(h, 1) / 6 * np.roll(z, 1) + h / 6 * np.roll(z, -1)
     assert np.max(np.abs(Gz - x)) < 1e-12 * np.max(np.abs(x))
+
+
+def test_cylinder_ka200_360_incidences_batch(cyl200):
+    """The batched configuration: 360 right-hand sides through one launch
+    sequence (grid rows = 360 pairs).  Sampled columns equal their
+    single-column launches bitwise (FP64 and FP32 grid), and two columns
+    match the oracle on the sampled rows."""
+    w, rows, orc, _ = cyl200
+    ctx = aim.Context(w.xy, w.k, w.eta, 0, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=360)
+    try:
+        ctx.filter(w.alpha)
+        X = torch.from_numpy(np.ascontiguousarray(wl.probe_vector(w.n_unknowns, nrhs=360, seed=33).T)).cuda()
+        for op in (aim.OPS["S"], aim.OPS["S"] | aim.AIM_OP_GRID_FP32):
+            Y = ctx.matvec(op, X)
+            for r in (0, 1, 179, 358, 359):
+                assert torch.equal(Y[r], ctx.matvec(op, X[r].contiguous())), (op, r)
+        Y = ctx.matvec("S", X).cpu().numpy()
+        Xh = X.cpu().numpy()
+        for r in (0, 359):
+            ref = orc.rows_apply("S", Xh[r], rows)
+            err = np.max(np.abs(Y[r][rows] - ref)) / np.max(np.abs(ref))
+            print("360-rhs batch column", r, "rel err", err)
+            assert err < 1e-12
+    finally:
+        ctx.close()
