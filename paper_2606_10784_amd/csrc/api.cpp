@@ -15,15 +15,15 @@ struct aim_ctx_s {
 namespace aim {
 
 void free_ctx(Ctx* c) {
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
   if (c->dual) {
     free_ctx(c->dual);
     delete c->dual;
     c->dual = nullptr;
   }
   release_spectrum(c);
-  for (void* p : c->allocs) hipFree(p);
+  for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   free_gmres_work(c->gw);
 }

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_givens_batch(int ldh, int j0, int j1, c
     Ss[i] = s[i];
   }
   __syncthreads();
-  if (threadIdx.x < nc) {
+  if ((int)threadIdx.x < nc) {
     double2* col = Hs + (size_t)threadIdx.x * ldh;
     double2 a = col[0];
     int i = 0;
@@ -571,9 +571,9 @@ void free_gmres_work(GmresWork& w) {
   for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.Hu, (void*)w.hp, (void*)w.coef, (void*)w.g, (void*)w.cs,
                   (void*)w.sn, (void*)w.y, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm,
                   (void*)w.resid, (void*)w.npart, (void*)w.active})
-    if (p) hipFree(p);
-  if (w.host_resid) hipHostFree(w.host_resid);
-  if (w.pin) hipHostFree(w.pin);
+    if (p) (void)hipFree(p);
+  if (w.host_resid) (void)hipHostFree(w.host_resid);
+  if (w.pin) (void)hipHostFree(w.pin);
   w = GmresWork();
 }
 

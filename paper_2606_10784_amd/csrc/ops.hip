@@ -801,7 +801,7 @@ __global__ void k_dotu_cols(int N, const double2* a, const double2* b, double* o
   sy[threadIdx.x] = ay;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) { sx[threadIdx.x] += sx[threadIdx.x + s]; sy[threadIdx.x] += sy[threadIdx.x + s]; }
+    if ((int)threadIdx.x < s) { sx[threadIdx.x] += sx[threadIdx.x + s]; sy[threadIdx.x] += sy[threadIdx.x + s]; }
     __syncthreads();
   }
   if (threadIdx.x == 0) { out[2 * r] = sx[0]; out[2 * r + 1] = sy[0]; }
@@ -951,7 +951,7 @@ size_t cache_clear() {
 
 aim_status setup_device(Ctx* c) {
   HostTables& t = c->t;
-  const int N = t.N, n = t.n, m = t.m;
+  const int N = t.N, n = t.n;
   hipStream_t s = c->stream;
   TRY(upload(c, &c->d_vx, t.vx.data(), N * 8));
   TRY(upload(c, &c->d_vy, t.vy.data(), N * 8));
@@ -1014,41 +1014,57 @@ aim_status setup_device(Ctx* c) {
       gl.insert(gl.end(), x.begin(), x.end());
       gl.insert(gl.end(), w.begin(), w.end());
     }
+    // temporaries of the build, freed on every path
     int32_t *d_rows = nullptr, *d_anx = nullptr, *d_any = nullptr;
     double* d_gl = nullptr;
+    auto release = [&]() {
+      for (void* p : {(void*)d_rows, (void*)d_anx, (void*)d_any, (void*)d_gl})
+        if (p) (void)hipFree(p);
+    };
     bool ok = hipMalloc(&d_rows, std::max<int64_t>(nnz, 1) * 4) == hipSuccess;
     ok = ok && hipMalloc(&d_anx, N * 4) == hipSuccess && hipMalloc(&d_any, N * 4) == hipSuccess;
     ok = ok && hipMalloc(&d_gl, gl.size() * 8) == hipSuccess;
-    if (!ok) return AIM_E_OOM;
-    hipMemcpy(d_rows, rows.data(), nnz * 4, hipMemcpyHostToDevice);
-    hipMemcpy(d_anx, t.anc_x.data(), N * 4, hipMemcpyHostToDevice);
-    hipMemcpy(d_any, t.anc_y.data(), N * 4, hipMemcpyHostToDevice);
-    hipMemcpy(d_gl, gl.data(), gl.size() * 8, hipMemcpyHostToDevice);
+    if (!ok) {
+      release();
+      return AIM_E_OOM;
+    }
+    aim_status st = AIM_OK;
+    ok = hipMemcpy(d_rows, rows.data(), nnz * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(d_anx, t.anc_x.data(), N * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(d_any, t.anc_y.data(), N * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(d_gl, gl.data(), gl.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) st = AIM_E_HIP;
     NearGeo G{c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, N, t.k, d_gl};
-    if (nnz > 0) {
+    if (st == AIM_OK && nnz > 0) {
       const int nb = 128;
       hipLaunchKernelGGL(k_near_build, dim3((unsigned)((nnz + nb - 1) / nb)), dim3(nb), 0, s, G, t.basis, nnz,
                          d_rows, c->d_nr_col, d_anx, d_any, c->d_W[0], c->d_W[1], c->d_W[2], c->d_W[3],
                          c->d_ksmall, c->ks, c->d_CS, c->d_CN);
+      if (hipGetLastError() != hipSuccess) st = AIM_E_HIP;
     }
-    if (t.band_w >= 0 && nnz > 0) {
+    if (st == AIM_OK && t.band_w >= 0 && nnz > 0) {
       const size_t bb = (size_t)(t.band_w + 1) * N * sizeof(double2);
-      TRY(dev_alloc(c, (void**)&c->d_CSd, bb));
-      AIM_HIP_CHECK(hipMemsetAsync(c->d_CSd, 0, bb, s));
-      hipLaunchKernelGGL(k_near_to_band, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, N, t.band_w,
-                         d_rows, c->d_nr_col, c->d_CS, c->d_CSd);
-      if (t.basis == AIM_HAT) {
-        TRY(dev_alloc(c, (void**)&c->d_CNd, bb));
-        AIM_HIP_CHECK(hipMemsetAsync(c->d_CNd, 0, bb, s));
+      st = dev_alloc(c, (void**)&c->d_CSd, bb);
+      if (st == AIM_OK && t.basis == AIM_HAT) st = dev_alloc(c, (void**)&c->d_CNd, bb);
+      if (st == AIM_OK && hipMemsetAsync(c->d_CSd, 0, bb, s) != hipSuccess) st = AIM_E_HIP;
+      if (st == AIM_OK) {
         hipLaunchKernelGGL(k_near_to_band, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, N, t.band_w,
-                           d_rows, c->d_nr_col, c->d_CN, c->d_CNd);
+                           d_rows, c->d_nr_col, c->d_CS, c->d_CSd);
+        if (hipGetLastError() != hipSuccess) st = AIM_E_HIP;
+      }
+      if (st == AIM_OK && t.basis == AIM_HAT) {
+        if (hipMemsetAsync(c->d_CNd, 0, bb, s) != hipSuccess) st = AIM_E_HIP;
+        if (st == AIM_OK) {
+          hipLaunchKernelGGL(k_near_to_band, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, N,
+                             t.band_w, d_rows, c->d_nr_col, c->d_CN, c->d_CNd);
+          if (hipGetLastError() != hipSuccess) st = AIM_E_HIP;
+        }
       }
     }
-    hipError_t e = hipStreamSynchronize(s);
-    hipFree(d_rows);
-    hipFree(d_anx);
-    hipFree(d_any);
-    hipFree(d_gl);
+    // the temporaries are read by the kernels above: wait before freeing
+    const hipError_t e = hipStreamSynchronize(s);
+    release();
+    if (st != AIM_OK) return st;
     if (e != hipSuccess) return AIM_E_HIP;
   }
 
@@ -1443,7 +1459,7 @@ aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, d
     e = hipGetLastError();
   }
   const hipError_t es = hipStreamSynchronize(c->stream);
-  hipFree(d_phi);
+  (void)hipFree(d_phi);
   return e == hipSuccess && es == hipSuccess ? AIM_OK : AIM_E_HIP;
 }
 
@@ -1479,7 +1495,7 @@ __global__ __launch_bounds__(256) void k_mode_quotient(int N, const double2* __r
   ry[threadIdx.x] = sy;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
+    if ((int)threadIdx.x < st) {
       rx[threadIdx.x] += rx[threadIdx.x + st];
       ry[threadIdx.x] += ry[threadIdx.x + st];
     }
@@ -1530,10 +1546,11 @@ aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, doubl
   AIM_HIP_CHECK(hipMalloc(&d_out, nrhs * 16));
   hipLaunchKernelGGL(k_dotu_cols, dim3(nrhs), dim3(256), 0, c->stream, t.N, c->d_rhs, J, d_out);
   std::vector<double> h(2 * nrhs);
-  hipMemcpyAsync(h.data(), d_out, nrhs * 16, hipMemcpyDeviceToHost, c->stream);
-  hipError_t e = hipStreamSynchronize(c->stream);
-  hipFree(d_out);
-  if (e != hipSuccess) return AIM_E_HIP;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_out, nrhs * 16, hipMemcpyDeviceToHost, c->stream);
+  const hipError_t es = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_out);
+  if (e != hipSuccess || es != hipSuccess) return AIM_E_HIP;
   for (int r = 0; r < nrhs; ++r) sigma[r] = t.k * t.eta * t.eta / 4.0 * (h[2 * r] * h[2 * r] + h[2 * r + 1] * h[2 * r + 1]);
   return AIM_OK;
 }
