@@ -577,11 +577,10 @@ void free_gmres_work(GmresWork& w) {
   w = GmresWork();
 }
 
-static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
+// Allocates the workspace for (restart, nrhs) into an empty c->gw; on an
+// error the caller frees whatever was allocated.
+static aim_status alloc_work(Ctx* c, int restart, int nrhs) {
   GmresWork& w = c->gw;
-  if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
-  c->dev_bytes -= w.bytes;
-  free_gmres_work(w);
   const int N = c->t.N;
   const int ldh = restart + 1;
   w.restart = restart;
@@ -626,7 +625,23 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
             hipSuccess)
       return AIM_E_HIP;
   }
-  c->dev_bytes += tot;
+  return AIM_OK;
+}
+
+// The workspace of the context, grown when a solve needs a longer restart or
+// more right-hand sides.  A failed allocation leaves it empty, so a later
+// call allocates afresh instead of using a partial workspace.
+static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
+  GmresWork& w = c->gw;
+  if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
+  c->dev_bytes -= w.bytes;
+  free_gmres_work(w);
+  const aim_status st = alloc_work(c, restart, nrhs);
+  if (st != AIM_OK) {
+    free_gmres_work(w);
+    return st;
+  }
+  c->dev_bytes += w.bytes;
   return AIM_OK;
 }
 
