@@ -39,6 +39,7 @@ extern "C" {
 #endif
 
 typedef struct aim_ctx_s* aim_ctx;
+typedef struct aim_solver_s* aim_solver;   /* step-wise solve (aim_solver_begin) */
 
 typedef enum {
   AIM_OK = 0,
@@ -48,7 +49,8 @@ typedef enum {
   AIM_E_HIP = 4,      /* HIP runtime error                                     */
   AIM_E_STATE = 5,    /* call not valid in this context state                  */
   AIM_E_NOCONV = 6,   /* GMRES reached maxit; x holds the best iterate         */
-  AIM_E_NUMERIC = 7   /* NaN/Inf in a residual                                  */
+  AIM_E_NUMERIC = 7,  /* NaN/Inf in a residual                                  */
+  AIM_PENDING = 8     /* aim_solver_poll: the solve has not finished           */
 } aim_status;
 
 enum { AIM_PULSE = 0, AIM_HAT = 1 };
@@ -206,6 +208,42 @@ aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_ho
 aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                      const void* b_dev, void* x_dev, double tol, int32_t maxit,
                      int32_t restart, aim_solve_info* info_host);
+
+/* Step-wise solving for serving schedulers: a solver holds one FP64 GMRES
+   solve of the system of `form` (as aim_solve with precision AIM_FP64) and
+   advances it by Arnoldi steps, so one host thread can interleave the steps
+   of many requests, admit new requests between steps and retire finished
+   ones (iteration-level batching).  Each solver owns its Krylov workspace
+   (restart + 1 vectors per rhs), so several may share a context; the steps of
+   solvers on one context run in call order on its stream, solvers on
+   different contexts overlap on the device.  Apart from the host reads that
+   close each batch of 8 Arnoldi steps (and a cycle's first and last step),
+   steps are asynchronous.  A solve advanced to the end issues the same
+   kernels in the same order as aim_solve, so its result is bitwise the same.
+
+   aim_solver_begin: arguments as aim_solve; b_dev (caller-owned, N x nrhs)
+   must stay valid and unchanged until the solver ends; x_dev holds the
+   initial guess and receives the iterate at the end of every restart cycle
+   and the solution when the solve finishes.  Allocates the workspace, forms
+   the preconditioned right-hand side of the Calderon forms and takes the
+   norms of b (synchronises the stream).  Errors as aim_solve (AIM_E_ARG,
+   AIM_E_STATE, AIM_E_OOM, AIM_E_HIP); on error *out is unchanged.
+   aim_solver_step: one Arnoldi step for each unfinished solver of
+   group[0 .. count-1] (NULL entries and finished solvers are skipped); a
+   step that completes a batch also checks and restarts, and a step that
+   finishes the solve also computes the true FP64 residual.  Returns AIM_OK,
+   or the first error a solver met (that solver finishes with it).
+   aim_solver_poll: progress or result into info_host (nrhs entries, may be
+   NULL; resid_true is -1 until the solve finishes).  Returns AIM_PENDING
+   while the solve runs, then AIM_OK (converged), AIM_E_NOCONV (maxit
+   reached) or the error that ended it.  Does not touch the device.
+   aim_solver_end: waits for the solver's work on the stream, frees it.
+   End the solvers of a context before aim_destroy.                            */
+aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t nrhs, const void* b_dev, void* x_dev,
+                            double tol, int32_t maxit, int32_t restart, aim_solver* out);
+aim_status aim_solver_step(aim_solver* group, int32_t count);
+aim_status aim_solver_poll(aim_solver solver, aim_solve_info* info_host);
+aim_status aim_solver_end(aim_solver solver);
 
 /* Monostatic TM scattering width sigma(phi_i) = (k eta^2 / 4)
    |sum_j J_j <phi_j, e^{-jk khat_i.r}>|^2 for column i of j_dev (pulse basis,

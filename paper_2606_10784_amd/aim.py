@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libaim.so")
 
-AIM_OK, AIM_E_ARG, AIM_E_GEOM, AIM_E_OOM, AIM_E_HIP, AIM_E_STATE, AIM_E_NOCONV, AIM_E_NUMERIC = range(8)
+AIM_OK, AIM_E_ARG, AIM_E_GEOM, AIM_E_OOM, AIM_E_HIP, AIM_E_STATE, AIM_E_NOCONV, AIM_E_NUMERIC, AIM_PENDING = range(9)
 AIM_PULSE, AIM_HAT = 0, 1
 (AIM_OP_S, AIM_OP_S_ALPHA, AIM_OP_N, AIM_OP_GRAM_INV, AIM_OP_TM, AIM_OP_TE_CP, AIM_OP_TE_CP_UNF, AIM_OP_N_ALPHA,
  AIM_OP_TM_PC, AIM_OP_TM_PC_UNF, AIM_OP_TM_CP, AIM_OP_TM_CP_UNF) = range(12)
@@ -94,6 +94,12 @@ EXPORTS = {
     "aim_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "aim_profile_stop": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "aim_solver_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "aim_solver_step": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
+    "aim_solver_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimSolveInfo)]),
+    "aim_solver_end": (ctypes.c_int, [ctypes.c_void_p]),
     "aim_cache_clear": (ctypes.c_size_t, []),
     "aim_destroy": (None, [ctypes.c_void_p]),
     "aim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -283,6 +289,51 @@ def aim_solve(ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100, precisio
         for d in out:
             d['status'] = 'noconv'
     return x, out
+
+
+class Solver:
+    """A step-wise FP64 GMRES solve (aim_solver_begin): step() advances it by
+    one Arnoldi step, poll() reports (status, [info per rhs]).  Keeps b and
+    the context alive until end()."""
+
+    def __init__(self, ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100):
+        torch = _torch()
+        fc = FORMS[form] if isinstance(form, str) else int(form)
+        self.ctx = ctx
+        self.b, self.nrhs = _as_cols(b, ctx.N)
+        self.x = torch.zeros_like(self.b) if x0 is None else x0.clone()
+        h = ctypes.c_void_p()
+        _check(_lib().aim_solver_begin(ctx.handle, fc, self.nrhs, ctypes.c_void_p(self.b.data_ptr()),
+                                       ctypes.c_void_p(self.x.data_ptr()), float(tol), int(maxit), int(restart),
+                                       ctypes.byref(h)), "aim_solver_begin")
+        self.handle = h.value
+
+    def step(self):
+        return aim_solver_step([self])
+
+    def poll(self):
+        infos = (AimSolveInfo * self.nrhs)()
+        st = _lib().aim_solver_poll(self.handle, infos)
+        return st, [infos[i].as_dict() for i in range(self.nrhs)]
+
+    def end(self):
+        if self.handle:
+            st = _lib().aim_solver_end(self.handle)
+            self.handle = None
+            _check(st, "aim_solver_end")
+
+    def __del__(self):
+        try:
+            self.end()
+        except Exception:
+            pass
+
+
+def aim_solver_step(solvers):
+    """One Arnoldi step for each unfinished solver of the group; returns the
+    status (the first error any solver met)."""
+    arr = (ctypes.c_void_p * len(solvers))(*[s.handle for s in solvers])
+    return _lib().aim_solver_step(arr, len(solvers))
 
 
 def aim_rcs_monostatic(ctx, J, phis):

@@ -105,6 +105,7 @@ const char* aim_strerror(aim_status s) {
     case AIM_E_STATE: return "invalid context state";
     case AIM_E_NOCONV: return "GMRES did not converge";
     case AIM_E_NUMERIC: return "non-finite residual";
+    case AIM_PENDING: return "solve not finished";
   }
   return "unknown status";
 }
@@ -198,6 +199,19 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
   return solve(&ctx->c, form, precision, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart,
                info_host);
 }
+
+aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t nrhs, const void* b_dev, void* x_dev, double tol,
+                            int32_t maxit, int32_t restart, aim_solver* out) {
+  if (!ctx || !b_dev || !x_dev || b_dev == x_dev || !out) return AIM_E_ARG;
+  if (ctx->c.t.node_order != 0) return AIM_E_STATE;   // every system operator needs the near field
+  return solver_begin(&ctx->c, form, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart, out);
+}
+
+aim_status aim_solver_step(aim_solver* group, int32_t count) { return solver_step(group, count); }
+
+aim_status aim_solver_poll(aim_solver solver, aim_solve_info* info_host) { return solver_poll(solver, info_host); }
+
+aim_status aim_solver_end(aim_solver solver) { return solver_end(solver); }
 
 aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev, const double* phi_host,
                               double* sigma_host) {

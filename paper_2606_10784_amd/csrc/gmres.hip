@@ -26,8 +26,12 @@
 //
 // AIM_MIXED: iterative refinement  x <- x + d,  A_mixed d ~ b - A_64 x, where
 // A_mixed runs the grid part in complex FP32 and everything else in FP64.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
+#include <memory>
+#include <new>
 
 #include "aim_internal.h"
 
@@ -577,10 +581,9 @@ void free_gmres_work(GmresWork& w) {
   w = GmresWork();
 }
 
-// Allocates the workspace for (restart, nrhs) into an empty c->gw; on an
-// error the caller frees whatever was allocated.
-static aim_status alloc_work(Ctx* c, int restart, int nrhs) {
-  GmresWork& w = c->gw;
+// Allocates the workspace for (restart, nrhs) into the empty w; on an error
+// the caller frees whatever was allocated.
+static aim_status alloc_work(Ctx* c, GmresWork& w, int restart, int nrhs) {
   const int N = c->t.N;
   const int ldh = restart + 1;
   w.restart = restart;
@@ -636,7 +639,7 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
   if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
   c->dev_bytes -= w.bytes;
   free_gmres_work(w);
-  const aim_status st = alloc_work(c, restart, nrhs);
+  const aim_status st = alloc_work(c, w, restart, nrhs);
   if (st != AIM_OK) {
     free_gmres_work(w);
     return st;
@@ -652,8 +655,8 @@ static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
   } while (0)
 
 // squared norms of the columns of w into out (double2 .x), active columns only
-static aim_status norms(Ctx* c, int nrhs, const double2* w, int64_t ldw, const int* active, double2* out) {
-  GmresWork& g = c->gw;
+static aim_status norms(Ctx* c, GmresWork& g, int nrhs, const double2* w, int64_t ldw, const int* active,
+                        double2* out) {
   const int N = c->t.N;
   hipLaunchKernelGGL(k_sqnorm, dim3(g.nchunk, nrhs), dim3(256), 0, c->stream, N, w, ldw, active, g.npart, g.nchunk);
   hipLaunchKernelGGL(k_sqnorm_reduce, dim3((nrhs + 63) / 64), dim3(64), 0, c->stream, nrhs, g.nchunk, g.npart,
@@ -668,49 +671,85 @@ struct GmresResult {
   int matvecs = 0, restarts = 0;
 };
 
-// Solve op(x) = b for nrhs columns (b, x: N x nrhs contiguous) to rel. tol.
-static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, double tol, int maxit, int restart,
-                        GmresResult& res) {
-  TRY(ensure_work(c, restart, nrhs));
-  GmresWork& w = c->gw;
-  hipStream_t s = c->stream;
-  const int N = c->t.N;
-  const int ldh = restart + 1;
-  const int64_t ldv = (int64_t)ldh * N;
-  const dim3 gN((N + 255) / 256, nrhs);
-  int* d_all = w.active + w.nrhs;   // all-ones mask (set at allocation)
-  std::vector<int> act(nrhs, 1), jdone(nrhs, 0);
-  int* pin_act = w.pin;
-  int* pin_upd = w.pin + nrhs;
-  int* pin_jm = w.pin + 2 * nrhs;
-  auto put_mask = [&](int* dst, int* stage, const std::vector<int>& v) {
+// Restarted GMRES for op(x) = b (b, x: N x nrhs contiguous) to rel. tol, as
+// a state machine that advances by Arnoldi steps: a cycle starts with the
+// true residual of x (top), takes steps in batches of up to kCheckEvery,
+// closes each batch with its rotations and residual estimates (the one host
+// synchronisation), and ends with x += V y.  gmres() runs it to the end;
+// the step-wise solver API advances it a step at a time.  Both issue the
+// same kernels in the same order.
+struct GmresRun {
+  enum Phase { TOP, ARNOLDI, DONE };
+  Ctx* c;
+  GmresWork& w;
+  int op, nrhs;
+  const double2* b;
+  double2* x;
+  double tol;
+  int maxit, restart;
+  GmresResult& res;
+  hipStream_t s;
+  int N, ldh, gblk;
+  int64_t ldv;
+  dim3 gN;
+  int *d_all, *pin_act, *pin_upd, *pin_jm;
+  std::vector<int> act, jdone, cyc;
+  std::vector<double> bn;
+  int total = 0, j = 0, jfin = 0, jend = 0;
+  bool batch = false;
+  Phase phase = TOP;
+
+  GmresRun(Ctx* c_, GmresWork& w_, int op_, int nrhs_, const double2* b_, double2* x_, double tol_, int maxit_,
+           int restart_, GmresResult& res_)
+      : c(c_), w(w_), op(op_), nrhs(nrhs_), b(b_), x(x_), tol(tol_), maxit(maxit_), restart(restart_), res(res_) {
+    s = c->stream;
+    N = c->t.N;
+    ldh = restart + 1;
+    ldv = (int64_t)ldh * N;
+    gN = dim3((N + 255) / 256, nrhs);
+    gblk = (N + GV_ROWS - 1) / GV_ROWS;
+    d_all = w.active + w.nrhs;   // all-ones mask (set at allocation)
+    pin_act = w.pin;
+    pin_upd = w.pin + nrhs;
+    pin_jm = w.pin + 2 * nrhs;
+    act.assign(nrhs, 1);
+    jdone.assign(nrhs, 0);
+  }
+
+  hipError_t put_mask(int* dst, int* stage, const std::vector<int>& v) {
     std::copy(v.begin(), v.end(), stage);
     return hipMemcpyAsync(dst, stage, nrhs * 4, hipMemcpyHostToDevice, s);
-  };
-  // ||b||
-  TRY(norms(c, nrhs, b, N, d_all, w.nrm));
-  std::vector<double2> hb(nrhs);
-  AIM_HIP_CHECK(hipMemcpyAsync(hb.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
-  AIM_HIP_CHECK(hipStreamSynchronize(s));
-  std::vector<double> bn(nrhs);
-  for (int r = 0; r < nrhs; ++r) bn[r] = std::sqrt(hb[r].x);
-  res.iters.assign(nrhs, 0);
-  res.conv.assign(nrhs, 0);
-  res.est.assign(nrhs, 0.0);
-  for (int r = 0; r < nrhs; ++r)
-    if (bn[r] == 0.0) {   // zero right-hand side: x = 0
-      res.conv[r] = 1;
-      act[r] = 0;
-      AIM_HIP_CHECK(hipMemsetAsync(x + (size_t)r * N, 0, (size_t)N * 16, s));
-    }
-  int total = 0;
-  while (true) {
-    // r0 = b - A x for the unconverged columns (all columns computed)
+  }
+
+  // ||b||; zero right-hand sides give x = 0
+  aim_status start() {
+    TRY(norms(c, w, nrhs, b, N, d_all, w.nrm));
+    std::vector<double2> hb(nrhs);
+    AIM_HIP_CHECK(hipMemcpyAsync(hb.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
+    AIM_HIP_CHECK(hipStreamSynchronize(s));
+    bn.resize(nrhs);
+    for (int r = 0; r < nrhs; ++r) bn[r] = std::sqrt(hb[r].x);
+    res.iters.assign(nrhs, 0);
+    res.conv.assign(nrhs, 0);
+    res.est.assign(nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+      if (bn[r] == 0.0) {
+        res.conv[r] = 1;
+        act[r] = 0;
+        AIM_HIP_CHECK(hipMemsetAsync(x + (size_t)r * N, 0, (size_t)N * 16, s));
+      }
+    phase = TOP;
+    return AIM_OK;
+  }
+
+  // cycle start: r0 = b - A x for the unconverged columns (all columns
+  // computed), convergence check, first basis vector
+  aim_status top() {
     TRY(matvec(c, op, nrhs, x, N, w.W, N));
     res.matvecs++;
     hipLaunchKernelGGL(k_bminus, gN, dim3(256), 0, s, N, b, w.W);
     AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
-    TRY(norms(c, nrhs, w.W, N, w.active, w.nrm));
+    TRY(norms(c, w, nrhs, w.W, N, w.active, w.nrm));
     std::vector<double2> h0(nrhs);
     AIM_HIP_CHECK(hipMemcpyAsync(h0.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
     AIM_HIP_CHECK(hipStreamSynchronize(s));
@@ -723,76 +762,94 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
       if (rel <= tol) { act[r] = 0; res.conv[r] = 1; }
       else any = true;
     }
-    if (!any || total >= maxit) break;
+    if (!any || total >= maxit) {
+      phase = DONE;
+      return AIM_OK;
+    }
     AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
     hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, w.W, (int64_t)N, w.V, ldv, w.active);
     hipLaunchKernelGGL(k_set_g0, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, w.nrm, w.active, w.g);
     std::fill(jdone.begin(), jdone.end(), 0);
-    std::vector<int> cyc(act);
-    const int gblk = (N + GV_ROWS - 1) / GV_ROWS;
+    cyc = act;
     // Arnoldi step j finalises Hessenberg column j - 1; jfin columns are
     // final and rotated
-    int j = 0, jfin = 0;
-    while (j < restart && total < maxit) {
-      const int jend = std::min(std::min(restart, j + kCheckEvery), j + (maxit - total));
-      for (; j < jend; ++j) {
-        // w = A u_j
-        TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
-        res.matvecs++;
-        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
-                           j, w.V, ldv, w.W, (int64_t)N, w.active, w.part, w.nchunk, ldh, w.Hu, w.coef, w.hp);
-        hipLaunchKernelGGL(k_arnoldi_update, dim3(gblk, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk,
-                           ldh, w.part, w.V, ldv, w.W, (int64_t)N, w.active, w.Hu, w.H, w.hp, w.coef, 0);
-        AIM_HIP_CHECK(hipGetLastError());
-        total++;
-      }
-      // at the end of a cycle the last column is finalised by a reduction of
-      // u_j alone (no operator application)
-      const bool last = j >= restart || total >= maxit;
-      if (last) {
-        hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s, N,
-                           j, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.part, w.nchunk, ldh, w.Hu,
-                           w.coef, w.hp);
-        hipLaunchKernelGGL(k_arnoldi_update, dim3(1, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk, ldh,
-                           w.part, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.Hu, w.H, w.hp, w.coef,
-                           1);
-        AIM_HIP_CHECK(hipGetLastError());
-      }
-      const int c1 = last ? j : j - 1;
-      if (c1 <= jfin) continue;
-      // rotations for the newly final columns, then their residual estimates;
-      // in column groups whose LDS footprint fits one block (long restarts)
-      for (int a = jfin; a < c1;) {
-        int e = c1;
-        while (e > a + 1 && ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16 > w.lds_max) --e;
-        hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(256), ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16, s,
-                           ldh, a, e, w.active, w.H, w.cs, w.sn, w.g, w.resid);
-        AIM_HIP_CHECK(hipGetLastError());
-        a = e;
-      }
-      for (int r = 0; r < nrhs; ++r)
-        if (act[r])
-          AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jfin, w.resid + (size_t)r * restart + jfin,
-                                       (size_t)(c1 - jfin) * 8, hipMemcpyDeviceToHost, s));
-      AIM_HIP_CHECK(hipStreamSynchronize(s));
-      bool left = false, changed = false;
-      for (int r = 0; r < nrhs; ++r) {
-        if (!act[r]) continue;
-        for (int jj = jfin; jj < c1; ++jj) {
-          res.iters[r]++;
-          jdone[r] = jj + 1;
-          const double rel = w.host_resid[(size_t)r * restart + jj] / bn[r];
-          if (!std::isfinite(rel)) return AIM_E_NUMERIC;
-          res.est[r] = rel;
-          if (rel <= tol) { act[r] = 0; changed = true; break; }
-        }
-        if (act[r]) left = true;
-      }
-      jfin = c1;
-      if (!left) break;
-      if (changed) AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
+    j = 0;
+    jfin = 0;
+    batch = false;
+    phase = ARNOLDI;
+    return AIM_OK;
+  }
+
+  // one Arnoldi step: w = A u_j, reduction pass, update pass
+  aim_status arnoldi_step() {
+    TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
+    res.matvecs++;
+    hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s,
+                       N, j, w.V, ldv, w.W, (int64_t)N, w.active, w.part, w.nchunk, ldh, w.Hu, w.coef, w.hp);
+    hipLaunchKernelGGL(k_arnoldi_update, dim3(gblk, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk,
+                       ldh, w.part, w.V, ldv, w.W, (int64_t)N, w.active, w.Hu, w.H, w.hp, w.coef, 0);
+    AIM_HIP_CHECK(hipGetLastError());
+    total++;
+    ++j;
+    return AIM_OK;
+  }
+
+  // end of a batch: rotations of the newly final columns and their residual
+  // estimates; over = true when no column is left in this cycle
+  aim_status close_batch(bool& over) {
+    over = false;
+    // at the end of a cycle the last column is finalised by a reduction of
+    // u_j alone (no operator application)
+    const bool last = j >= restart || total >= maxit;
+    if (last) {
+      hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0,
+                         s, N, j, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.part, w.nchunk, ldh,
+                         w.Hu, w.coef, w.hp);
+      hipLaunchKernelGGL(k_arnoldi_update, dim3(1, nrhs), dim3(256), (size_t)(j + 1) * 48, s, N, j, w.nchunk, ldh,
+                         w.part, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.Hu, w.H, w.hp, w.coef,
+                         1);
+      AIM_HIP_CHECK(hipGetLastError());
     }
-    // x += V y for every column that took steps in this cycle
+    const int c1 = last ? j : j - 1;
+    if (c1 <= jfin) return AIM_OK;
+    // in column groups whose LDS footprint fits one block (long restarts)
+    for (int a = jfin; a < c1;) {
+      int e = c1;
+      while (e > a + 1 && ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16 > w.lds_max) --e;
+      hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(256), ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16, s,
+                         ldh, a, e, w.active, w.H, w.cs, w.sn, w.g, w.resid);
+      AIM_HIP_CHECK(hipGetLastError());
+      a = e;
+    }
+    for (int r = 0; r < nrhs; ++r)
+      if (act[r])
+        AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jfin, w.resid + (size_t)r * restart + jfin,
+                                     (size_t)(c1 - jfin) * 8, hipMemcpyDeviceToHost, s));
+    AIM_HIP_CHECK(hipStreamSynchronize(s));
+    bool left = false, changed = false;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      for (int jj = jfin; jj < c1; ++jj) {
+        res.iters[r]++;
+        jdone[r] = jj + 1;
+        const double rel = w.host_resid[(size_t)r * restart + jj] / bn[r];
+        if (!std::isfinite(rel)) return AIM_E_NUMERIC;
+        res.est[r] = rel;
+        if (rel <= tol) { act[r] = 0; changed = true; break; }
+      }
+      if (act[r]) left = true;
+    }
+    jfin = c1;
+    if (!left) {
+      over = true;
+      return AIM_OK;
+    }
+    if (changed) AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
+    return AIM_OK;
+  }
+
+  // cycle end: x += V y for every column that took steps in this cycle
+  aim_status end_cycle() {
     std::vector<int> upd(nrhs, 0);
     for (int r = 0; r < nrhs; ++r) upd[r] = (cyc[r] && jdone[r] > 0) ? 1 : 0;
     int* d_jm = (int*)w.part;   // scratch: jm then mask
@@ -817,7 +874,8 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
       TRY(matvec(c, op, nrhs, x, N, w.W, N));
       res.matvecs++;
       hipLaunchKernelGGL(k_bminus, gN, dim3(256), 0, s, N, b, w.W);
-      TRY(norms(c, nrhs, w.W, N, d_all, w.nrm));
+      TRY(norms(c, w, nrhs, w.W, N, d_all, w.nrm));
+      std::vector<double2> h0(nrhs);
       AIM_HIP_CHECK(hipMemcpyAsync(h0.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
       AIM_HIP_CHECK(hipStreamSynchronize(s));
       for (int r = 0; r < nrhs; ++r)
@@ -825,10 +883,51 @@ static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, 
           res.est[r] = std::sqrt(h0[r].x) / bn[r];
           res.conv[r] = res.est[r] <= tol;
         }
-      break;
+      phase = DONE;
+    } else {
+      phase = TOP;
     }
+    return AIM_OK;
   }
-  return AIM_OK;
+
+  // Runs until `steps` more Arnoldi steps have been taken or the solve is
+  // done.  The check that closes a batch runs right after the step that
+  // completes it.
+  aim_status advance(long steps) {
+    while (phase != DONE) {
+      if (phase == TOP) {
+        TRY(top());
+        continue;
+      }
+      if (!(j < restart && total < maxit)) {
+        TRY(end_cycle());
+        continue;
+      }
+      if (!batch) {
+        jend = std::min(std::min(restart, j + kCheckEvery), j + (maxit - total));
+        batch = true;
+      }
+      if (j < jend) {
+        if (steps <= 0) return AIM_OK;
+        TRY(arnoldi_step());
+        --steps;
+        if (j < jend) continue;
+      }
+      batch = false;
+      bool over = false;
+      TRY(close_batch(over));
+      if (over) TRY(end_cycle());
+    }
+    return AIM_OK;
+  }
+};
+
+static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, double tol, int maxit, int restart,
+                        GmresResult& res) {
+  TRY(ensure_work(c, restart, nrhs));
+  GmresRun run(c, c->gw, op, nrhs, b, x, tol, maxit, restart, res);
+  TRY(run.start());
+  return run.advance(std::numeric_limits<long>::max());
 }
 
 static int form_op(int form) {
@@ -843,14 +942,14 @@ static int form_op(int form) {
 }
 
 // relative true residuals ||b - op x|| / ||b|| (FP64 operator)
-static aim_status true_resid(Ctx* c, int op, int nrhs, const double2* b, const double2* x, std::vector<double>& out) {
-  GmresWork& w = c->gw;
+static aim_status true_resid(Ctx* c, GmresWork& w, int op, int nrhs, const double2* b, const double2* x,
+                             std::vector<double>& out) {
   const int N = c->t.N;
   int* d_all = w.active + w.nrhs;
   TRY(matvec(c, op, nrhs, x, N, w.W, N));
   hipLaunchKernelGGL(k_bminus, dim3((N + 255) / 256, nrhs), dim3(256), 0, c->stream, N, b, w.W);
-  TRY(norms(c, nrhs, w.W, N, d_all, w.nrm));
-  TRY(norms(c, nrhs, b, N, d_all, w.nrm + nrhs));
+  TRY(norms(c, w, nrhs, w.W, N, d_all, w.nrm));
+  TRY(norms(c, w, nrhs, b, N, d_all, w.nrm + nrhs));
   std::vector<double2> h(2 * nrhs);
   AIM_HIP_CHECK(hipMemcpyAsync(h.data(), w.nrm, 2 * nrhs * 16, hipMemcpyDeviceToHost, c->stream));
   AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -859,33 +958,50 @@ static aim_status true_resid(Ctx* c, int op, int nrhs, const double2* b, const d
   return AIM_OK;
 }
 
-aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol, int maxit,
-                 int restart, aim_solve_info* info) {
-  auto t0 = std::chrono::steady_clock::now();
+// Argument checks shared by aim_solve and the step-wise solver.
+static aim_status check_solve(Ctx* c, int form, int precision, int nrhs, double tol, int maxit, int restart) {
   const int op = form_op(form);
   if (op < 0 || nrhs < 1 || nrhs > c->max_rhs || !(tol > 0) || maxit < 1 || restart < 1 || restart > 1000)
     return AIM_E_ARG;
+  if (precision != AIM_FP64 && precision != AIM_MIXED) return AIM_E_ARG;
   if (precision == AIM_MIXED && c->precision != AIM_MIXED) return AIM_E_ARG;
   const bool tm = form == AIM_TM_EFIE || form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED;
   if (c->t.basis != (tm ? AIM_PULSE : AIM_HAT)) return AIM_E_ARG;
   if ((form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED) && !c->dual) return AIM_E_STATE;
+  return AIM_OK;
+}
+
+// The right-hand side of the iterated system: b itself for the TM EFIE, the
+// preconditioned one (into w.b2) for the Calderon forms.
+static aim_status system_rhs(Ctx* c, GmresWork& w, int form, int nrhs, const double2* b, const double2** rhs) {
+  const int N = c->t.N;
+  *rhs = b;
+  if (form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED) {
+    // preconditioned right-hand side G_pd^-T N'(alpha) G_pd^-1 b
+    TRY(matvec(c, form == AIM_TM_CALDERON ? AIM_OP_TM_PC : AIM_OP_TM_PC_UNF, nrhs, b, N, w.b2, N));
+    *rhs = w.b2;
+  } else if (form != AIM_TM_EFIE) {
+    // preconditioned right-hand side G^-1 S G^-1 b
+    TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, b, N, c->d_tmp1, N));
+    TRY(matvec(c, form == AIM_TE_CALDERON ? AIM_OP_S_ALPHA : AIM_OP_S, nrhs, c->d_tmp1, N, c->d_tmp2, N));
+    TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, c->d_tmp2, N, w.b2, N));
+    *rhs = w.b2;
+  }
+  return AIM_OK;
+}
+
+aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol, int maxit,
+                 int restart, aim_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  TRY(check_solve(c, form, precision, nrhs, tol, maxit, restart));
+  const int op = form_op(form);
   TRY(ensure_work(c, restart, nrhs));
   // keep nrm wide enough for true_resid (2 nrhs)
   GmresWork& w = c->gw;
   const int N = c->t.N;
   hipStream_t s = c->stream;
   const double2* rhs = b;
-  if (form == AIM_TM_CALDERON || form == AIM_TM_CALDERON_UNFILTERED) {
-    // preconditioned right-hand side G_pd^-T N'(alpha) G_pd^-1 b
-    TRY(matvec(c, form == AIM_TM_CALDERON ? AIM_OP_TM_PC : AIM_OP_TM_PC_UNF, nrhs, b, N, w.b2, N));
-    rhs = w.b2;
-  } else if (form != AIM_TM_EFIE) {
-    // preconditioned right-hand side G^-1 S G^-1 b
-    TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, b, N, c->d_tmp1, N));
-    TRY(matvec(c, form == AIM_TE_CALDERON ? AIM_OP_S_ALPHA : AIM_OP_S, nrhs, c->d_tmp1, N, c->d_tmp2, N));
-    TRY(matvec(c, AIM_OP_GRAM_INV, nrhs, c->d_tmp2, N, w.b2, N));
-    rhs = w.b2;
-  }
+  TRY(system_rhs(c, w, form, nrhs, b, &rhs));
   std::vector<int> iters(nrhs, 0), conv(nrhs, 0);
   std::vector<double> est(nrhs, 0.0);
   int matvecs = 0, restarts = 0, outer = 0;
@@ -906,7 +1022,7 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
     // level, and one more refinement step is cheaper than those steps.
     const double tin_min = std::min(1e-2, std::max(1e-5, 10.0 * tol));
     for (outer = 0; outer < 30; ++outer) {
-      TRY(true_resid(c, op, nrhs, rhs, x, rel));
+      TRY(true_resid(c, w, op, nrhs, rhs, x, rel));
       matvecs++;
       bool done = true;
       double worst = 0;
@@ -935,7 +1051,7 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
     }
   }
   std::vector<double> tr;
-  TRY(true_resid(c, op, nrhs, rhs, x, tr));
+  TRY(true_resid(c, w, op, nrhs, rhs, x, tr));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   bool all = true;
   for (int r = 0; r < nrhs; ++r) {
@@ -954,6 +1070,126 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
     }
   }
   return all ? AIM_OK : AIM_E_NOCONV;
+}
+
+// ---------------------------------------------------------------------------
+// Step-wise solver: one FP64 GMRES solve of a context's system that advances
+// by Arnoldi steps (serving schedulers interleave the steps of many requests).
+// It owns its workspace, so several solvers may share a context; their steps
+// then run in call order on the context's stream.
+// ---------------------------------------------------------------------------
+}  // namespace aim
+
+struct aim_solver_s {
+  aim::Ctx* c = nullptr;
+  int form = 0, op = 0, nrhs = 0;
+  double tol = 0;
+  double2* x = nullptr;
+  const double2* rhs = nullptr;
+  aim::GmresWork w;
+  aim::GmresResult res;
+  std::unique_ptr<aim::GmresRun> run;
+  aim_status status = AIM_PENDING;
+  std::vector<double> tr;
+  std::chrono::steady_clock::time_point t0;
+  double seconds = 0;
+};
+
+namespace aim {
+
+static void solver_free(aim_solver_s* sv) {
+  sv->c->dev_bytes -= sv->w.bytes;
+  free_gmres_work(sv->w);
+  delete sv;
+}
+
+aim_status solver_begin(Ctx* c, int form, int nrhs, const double2* b, double2* x, double tol, int maxit, int restart,
+                        aim_solver_s** out) {
+  TRY(check_solve(c, form, AIM_FP64, nrhs, tol, maxit, restart));
+  aim_solver_s* sv = new (std::nothrow) aim_solver_s();
+  if (!sv) return AIM_E_OOM;
+  sv->c = c;
+  sv->form = form;
+  sv->op = form_op(form);
+  sv->nrhs = nrhs;
+  sv->tol = tol;
+  sv->x = x;
+  sv->t0 = std::chrono::steady_clock::now();
+  aim_status st = alloc_work(c, sv->w, restart, nrhs);
+  if (st != AIM_OK) {
+    free_gmres_work(sv->w);
+    delete sv;
+    return st;
+  }
+  c->dev_bytes += sv->w.bytes;
+  st = system_rhs(c, sv->w, form, nrhs, b, &sv->rhs);
+  if (st == AIM_OK) {
+    sv->run.reset(new (std::nothrow) GmresRun(c, sv->w, sv->op, nrhs, sv->rhs, x, tol, maxit, restart, sv->res));
+    st = sv->run ? sv->run->start() : AIM_E_OOM;
+  }
+  if (st != AIM_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    solver_free(sv);
+    return st;
+  }
+  *out = sv;
+  return AIM_OK;
+}
+
+// the end of a solve: the true residual with the FP64 operator, as aim_solve
+static aim_status solver_finish(aim_solver_s* sv) {
+  TRY(true_resid(sv->c, sv->w, sv->op, sv->nrhs, sv->rhs, sv->x, sv->tr));
+  bool all = true;
+  for (int r = 0; r < sv->nrhs; ++r) {
+    if (!std::isfinite(sv->tr[r])) return AIM_E_NUMERIC;
+    all = all && sv->res.conv[r] && sv->tr[r] <= sv->tol * 1.5;
+  }
+  return all ? AIM_OK : AIM_E_NOCONV;
+}
+
+aim_status solver_step(aim_solver_s** group, int count) {
+  if (count < 0 || (count > 0 && !group)) return AIM_E_ARG;
+  aim_status first = AIM_OK;
+  for (int i = 0; i < count; ++i) {
+    aim_solver_s* sv = group[i];
+    if (!sv || sv->status != AIM_PENDING) continue;
+    aim_status st = sv->run->advance(1);
+    if (st == AIM_OK && sv->run->phase == GmresRun::DONE) st = solver_finish(sv);
+    else if (st == AIM_OK) continue;
+    sv->status = st;
+    sv->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+    if (st != AIM_OK && st != AIM_E_NOCONV && first == AIM_OK) first = st;
+  }
+  return first;
+}
+
+aim_status solver_poll(aim_solver_s* sv, aim_solve_info* info) {
+  if (!sv) return AIM_E_ARG;
+  if (info) {
+    const bool done = sv->status != AIM_PENDING;
+    const double secs =
+        done ? sv->seconds : std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+    const bool have = sv->res.iters.size() == (size_t)sv->nrhs;
+    for (int r = 0; r < sv->nrhs; ++r) {
+      info[r].iterations = have ? sv->res.iters[r] : 0;
+      info[r].matvecs = sv->res.matvecs;
+      info[r].restarts = sv->res.restarts;
+      info[r].outer = 0;
+      const bool fin = done && sv->tr.size() == (size_t)sv->nrhs;
+      info[r].converged = fin && sv->res.conv[r] && sv->tr[r] <= sv->tol * 1.5 ? 1 : 0;
+      info[r].resid_est = have ? sv->res.est[r] : 0.0;
+      info[r].resid_true = fin ? sv->tr[r] : -1.0;
+      info[r].seconds = secs;
+    }
+  }
+  return sv->status;
+}
+
+aim_status solver_end(aim_solver_s* sv) {
+  if (!sv) return AIM_E_ARG;
+  const hipError_t e = hipStreamSynchronize(sv->c->stream);
+  solver_free(sv);
+  return e == hipSuccess ? AIM_OK : AIM_E_HIP;
 }
 
 }  // namespace aim

@@ -82,3 +82,16 @@ def test_batch_size_bounded_on_the_host():
     for bad in (0, aim.AIM_MAX_RHS + 1):
         p, _keep = aim.make_params(xy, wl.K0, wl.ETA0, 0, 64, 0.05, max_rhs=bad)
         assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+
+
+def test_solver_calls_checked_on_the_host():
+    """The step-wise solver's host-side argument checks (no device needed)."""
+    lib = aim._lib()
+    assert lib.aim_strerror(aim.AIM_PENDING) == b"solve not finished"
+    assert lib.aim_solver_step(None, 0) == aim.AIM_OK
+    assert lib.aim_solver_step(None, 1) == aim.AIM_E_ARG
+    assert lib.aim_solver_step(None, -1) == aim.AIM_E_ARG
+    assert lib.aim_solver_poll(None, None) == aim.AIM_E_ARG
+    assert lib.aim_solver_end(None) == aim.AIM_E_ARG
+    h = ctypes.c_void_p()
+    assert lib.aim_solver_begin(None, 0, 1, None, None, 1e-6, 10, 10, ctypes.byref(h)) == aim.AIM_E_ARG
