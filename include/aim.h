@@ -209,17 +209,17 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                      const void* b_dev, void* x_dev, double tol, int32_t maxit,
                      int32_t restart, aim_solve_info* info_host);
 
-/* Step-wise solving for serving schedulers: a solver holds one FP64 GMRES
-   solve of the system of `form` (as aim_solve with precision AIM_FP64) and
-   advances it by Arnoldi steps, so one host thread can interleave the steps
-   of many requests, admit new requests between steps and retire finished
-   ones (iteration-level batching).  Each solver owns its Krylov workspace
+/* Step-wise solving for serving schedulers: a solver holds one solve of
+   aim_solve (any form, FP64 or AIM_MIXED refinement) and advances it by
+   Arnoldi steps (inner steps for AIM_MIXED), so one host thread can
+   interleave the steps of many requests, admit new requests between steps
+   and retire finished ones (iteration-level batching).  Each solver owns its Krylov workspace
    (restart + 1 vectors per rhs), so several may share a context; the steps of
    solvers on one context run in call order on its stream, solvers on
    different contexts overlap on the device.  Apart from the host reads that
    close each batch of 8 Arnoldi steps (and a cycle's first and last step),
-   steps are asynchronous.  A solve advanced to the end issues the same
-   kernels in the same order as aim_solve, so its result is bitwise the same.
+   steps are asynchronous.  aim_solve is the same machinery run to the end,
+   so a solver's result is bitwise that of aim_solve.
 
    aim_solver_begin: arguments as aim_solve; b_dev (caller-owned, N x nrhs)
    must stay valid and unchanged until the solver ends; x_dev holds the
@@ -231,7 +231,9 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
    aim_solver_step: one Arnoldi step for each unfinished solver of
    group[0 .. count-1] (NULL entries and finished solvers are skipped); a
    step that completes a batch also checks and restarts, and a step that
-   finishes the solve also computes the true FP64 residual.  Returns AIM_OK,
+   finishes the solve also computes the true FP64 residual.  For AIM_MIXED
+   the refinement's outer checks (true FP64 residual) run inside the step
+   that ends an inner solve.  Returns AIM_OK,
    or the first error a solver met (that solver finishes with it).
    aim_solver_poll: progress or result into info_host (nrhs entries, may be
    NULL; resid_true is -1 until the solve finishes).  Returns AIM_PENDING
@@ -239,8 +241,8 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
    reached) or the error that ended it.  Does not touch the device.
    aim_solver_end: waits for the solver's work on the stream, frees it.
    End the solvers of a context before aim_destroy.                            */
-aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t nrhs, const void* b_dev, void* x_dev,
-                            double tol, int32_t maxit, int32_t restart, aim_solver* out);
+aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev,
+                            void* x_dev, double tol, int32_t maxit, int32_t restart, aim_solver* out);
 aim_status aim_solver_step(aim_solver* group, int32_t count);
 aim_status aim_solver_poll(aim_solver solver, aim_solve_info* info_host);
 aim_status aim_solver_end(aim_solver solver);

@@ -94,9 +94,9 @@ EXPORTS = {
     "aim_profile_start": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "aim_profile_stop": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
-    "aim_solver_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                        ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "aim_solver_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "aim_solver_step": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
     "aim_solver_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimSolveInfo)]),
     "aim_solver_end": (ctypes.c_int, [ctypes.c_void_p]),
@@ -292,18 +292,18 @@ def aim_solve(ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100, precisio
 
 
 class Solver:
-    """A step-wise FP64 GMRES solve (aim_solver_begin): step() advances it by
-    one Arnoldi step, poll() reports (status, [info per rhs]).  Keeps b and
-    the context alive until end()."""
+    """A step-wise solve (aim_solver_begin): step() advances it by one Arnoldi
+    step, poll() reports (status, [info per rhs]).  Keeps b and the context
+    alive until end()."""
 
-    def __init__(self, ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100):
+    def __init__(self, ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100, precision=AIM_FP64):
         torch = _torch()
         fc = FORMS[form] if isinstance(form, str) else int(form)
         self.ctx = ctx
         self.b, self.nrhs = _as_cols(b, ctx.N)
         self.x = torch.zeros_like(self.b) if x0 is None else x0.clone()
         h = ctypes.c_void_p()
-        _check(_lib().aim_solver_begin(ctx.handle, fc, self.nrhs, ctypes.c_void_p(self.b.data_ptr()),
+        _check(_lib().aim_solver_begin(ctx.handle, fc, int(precision), self.nrhs, ctypes.c_void_p(self.b.data_ptr()),
                                        ctypes.c_void_p(self.x.data_ptr()), float(tol), int(maxit), int(restart),
                                        ctypes.byref(h)), "aim_solver_begin")
         self.handle = h.value

@@ -200,11 +200,12 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                info_host);
 }
 
-aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t nrhs, const void* b_dev, void* x_dev, double tol,
-                            int32_t maxit, int32_t restart, aim_solver* out) {
+aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev,
+                            void* x_dev, double tol, int32_t maxit, int32_t restart, aim_solver* out) {
   if (!ctx || !b_dev || !x_dev || b_dev == x_dev || !out) return AIM_E_ARG;
   if (ctx->c.t.node_order != 0) return AIM_E_STATE;   // every system operator needs the near field
-  return solver_begin(&ctx->c, form, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart, out);
+  return solver_begin(&ctx->c, form, precision, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart,
+                      out);
 }
 
 aim_status aim_solver_step(aim_solver* group, int32_t count) { return solver_step(group, count); }

@@ -990,107 +990,206 @@ static aim_status system_rhs(Ctx* c, GmresWork& w, int form, int nrhs, const dou
   return AIM_OK;
 }
 
-aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol, int maxit,
-                 int restart, aim_solve_info* info) {
-  auto t0 = std::chrono::steady_clock::now();
-  TRY(check_solve(c, form, precision, nrhs, tol, maxit, restart));
-  const int op = form_op(form);
-  TRY(ensure_work(c, restart, nrhs));
-  // keep nrm wide enough for true_resid (2 nrhs)
-  GmresWork& w = c->gw;
-  const int N = c->t.N;
-  hipStream_t s = c->stream;
-  const double2* rhs = b;
-  TRY(system_rhs(c, w, form, nrhs, b, &rhs));
-  std::vector<int> iters(nrhs, 0), conv(nrhs, 0);
-  std::vector<double> est(nrhs, 0.0);
+// The whole solve of aim_solve as a state machine that advances by Arnoldi
+// steps: FP64 GMRES on the system of `form`, or (AIM_MIXED) iterative
+// refinement whose outer checks take the FP64 true residual and whose inner
+// solves are FP32-grid GMRES runs; then the final true residual.  aim_solve
+// runs it to the end on the context's workspace, a step-wise solver on its
+// own one.
+struct SolveRun {
+  enum Phase { FP64_RUN, MIX_CHECK, MIX_INNER, FINAL, DONE };
+  Ctx* c;
+  GmresWork& w;
+  int form, precision, op, nrhs;
+  const double2* b;
+  double2* x;
+  double tol;
+  int maxit, restart;
+  const double2* rhs = nullptr;
+  std::vector<int> iters, conv;
+  std::vector<double> est, tr;
   int matvecs = 0, restarts = 0, outer = 0;
-  if (precision == AIM_FP64) {
-    GmresResult gr;
-    TRY(gmres(c, op, nrhs, rhs, x, tol, maxit, restart, gr));
-    iters = gr.iters;
-    conv = gr.conv;
-    est = gr.est;
-    matvecs = gr.matvecs;
-    restarts = gr.restarts;
-  } else {
-    // iterative refinement: FP64 residual, FP32-grid inner GMRES
-    std::vector<double> rel;
+  double tin_min = 0;
+  GmresResult gr;
+  std::unique_ptr<GmresRun> run;
+  Phase phase = FINAL;
+  aim_status status = AIM_OK;   // result once DONE
+
+  SolveRun(Ctx* c_, GmresWork& w_, int form_, int precision_, int nrhs_, const double2* b_, double2* x_,
+           double tol_, int maxit_, int restart_)
+      : c(c_), w(w_), form(form_), precision(precision_), op(form_op(form_)), nrhs(nrhs_), b(b_), x(x_),
+        tol(tol_), maxit(maxit_), restart(restart_) {
+    iters.assign(nrhs, 0);
+    conv.assign(nrhs, 0);
+    est.assign(nrhs, 0.0);
     // Inner solves stop no lower than 1e-5 relative (and no lower than
     // 10 tol): the FP32 grid product is accurate to ~1e-6 relative, the
     // inner Krylov convergence slows as the inner residual approaches that
     // level, and one more refinement step is cheaper than those steps.
-    const double tin_min = std::min(1e-2, std::max(1e-5, 10.0 * tol));
-    for (outer = 0; outer < 30; ++outer) {
-      TRY(true_resid(c, w, op, nrhs, rhs, x, rel));
-      matvecs++;
-      bool done = true;
-      double worst = 0;
-      for (int r = 0; r < nrhs; ++r) {
-        if (!std::isfinite(rel[r])) return AIM_E_NUMERIC;
-        if (rel[r] > tol) done = false;
-        worst = std::max(worst, rel[r]);
-        est[r] = rel[r];
-        conv[r] = rel[r] <= tol;
-      }
-      int tot_it = 0;
-      for (int r = 0; r < nrhs; ++r) tot_it = std::max(tot_it, iters[r]);
-      if (done || tot_it >= maxit) break;
-      // r = b - A x (left in w.W by true_resid), d = 0
-      AIM_HIP_CHECK(hipMemcpyAsync(w.r, w.W, (size_t)N * nrhs * 16, hipMemcpyDeviceToDevice, s));
-      AIM_HIP_CHECK(hipMemsetAsync(w.d, 0, (size_t)N * nrhs * 16, s));
-      const double tin = std::max(tin_min, 0.5 * tol / worst);
-      GmresResult gr;
-      // inner solve works on its own copy of the residual (gmres reads b, writes d)
-      TRY(gmres(c, op | AIM_OP_GRID_FP32, nrhs, w.r, w.d, std::min(tin, 0.5), maxit - tot_it, restart, gr));
-      for (int r = 0; r < nrhs; ++r) iters[r] += gr.iters[r];
-      matvecs += gr.matvecs;
-      restarts += gr.restarts;
-      hipLaunchKernelGGL(k_axpy, dim3((N + 255) / 256, nrhs), dim3(256), 0, s, N, w.d, x);
-      AIM_HIP_CHECK(hipGetLastError());
-    }
+    tin_min = std::min(1e-2, std::max(1e-5, 10.0 * tol));
   }
-  std::vector<double> tr;
-  TRY(true_resid(c, w, op, nrhs, rhs, x, tr));
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  bool all = true;
-  for (int r = 0; r < nrhs; ++r) {
-    if (!std::isfinite(tr[r])) return AIM_E_NUMERIC;
-    const bool cv = precision == AIM_FP64 ? (conv[r] && tr[r] <= tol * 1.5) : (tr[r] <= tol);
-    all = all && cv;
-    if (info) {
-      info[r].iterations = iters[r];
-      info[r].matvecs = matvecs;
-      info[r].restarts = restarts;
+
+  aim_status begin() {
+    TRY(system_rhs(c, w, form, nrhs, b, &rhs));
+    if (precision == AIM_FP64) {
+      run.reset(new (std::nothrow) GmresRun(c, w, op, nrhs, rhs, x, tol, maxit, restart, gr));
+      if (!run) return AIM_E_OOM;
+      TRY(run->start());
+      phase = FP64_RUN;
+    } else {
+      phase = MIX_CHECK;
+    }
+    return AIM_OK;
+  }
+
+  // refinement: FP64 residual, FP32-grid inner GMRES on it
+  aim_status mix_check() {
+    if (outer >= 30) {
+      phase = FINAL;
+      return AIM_OK;
+    }
+    const int N = c->t.N;
+    hipStream_t s = c->stream;
+    std::vector<double> rel;
+    TRY(true_resid(c, w, op, nrhs, rhs, x, rel));
+    matvecs++;
+    bool done = true;
+    double worst = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(rel[r])) return AIM_E_NUMERIC;
+      if (rel[r] > tol) done = false;
+      worst = std::max(worst, rel[r]);
+      est[r] = rel[r];
+      conv[r] = rel[r] <= tol;
+    }
+    int tot_it = 0;
+    for (int r = 0; r < nrhs; ++r) tot_it = std::max(tot_it, iters[r]);
+    if (done || tot_it >= maxit) {
+      phase = FINAL;
+      return AIM_OK;
+    }
+    // r = b - A x (left in w.W by true_resid), d = 0; the inner solve works on
+    // its own copy of the residual (it reads w.r, writes w.d)
+    AIM_HIP_CHECK(hipMemcpyAsync(w.r, w.W, (size_t)N * nrhs * 16, hipMemcpyDeviceToDevice, s));
+    AIM_HIP_CHECK(hipMemsetAsync(w.d, 0, (size_t)N * nrhs * 16, s));
+    const double tin = std::max(tin_min, 0.5 * tol / worst);
+    gr = GmresResult();
+    run.reset(new (std::nothrow) GmresRun(c, w, op | AIM_OP_GRID_FP32, nrhs, w.r, w.d, std::min(tin, 0.5),
+                                          maxit - tot_it, restart, gr));
+    if (!run) return AIM_E_OOM;
+    TRY(run->start());
+    phase = MIX_INNER;
+    return AIM_OK;
+  }
+
+  aim_status mix_inner_done() {
+    const int N = c->t.N;
+    for (int r = 0; r < nrhs; ++r) iters[r] += gr.iters[r];
+    matvecs += gr.matvecs;
+    restarts += gr.restarts;
+    hipLaunchKernelGGL(k_axpy, dim3((N + 255) / 256, nrhs), dim3(256), 0, c->stream, N, w.d, x);
+    AIM_HIP_CHECK(hipGetLastError());
+    ++outer;
+    phase = MIX_CHECK;
+    return AIM_OK;
+  }
+
+  aim_status finish() {
+    TRY(true_resid(c, w, op, nrhs, rhs, x, tr));
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(tr[r])) return AIM_E_NUMERIC;
+      all = all && converged(r);
+    }
+    status = all ? AIM_OK : AIM_E_NOCONV;
+    phase = DONE;
+    return AIM_OK;
+  }
+
+  bool converged(int r) const {
+    if (tr.size() != (size_t)nrhs) return false;
+    return precision == AIM_FP64 ? (conv[r] && tr[r] <= tol * 1.5) : (tr[r] <= tol);
+  }
+
+  // Runs until `steps` more Arnoldi steps have been taken or the solve is
+  // done; an error ends the solve with that status.
+  aim_status advance(long steps) {
+    while (phase != DONE) {
+      aim_status st = AIM_OK;
+      if (phase == FP64_RUN || phase == MIX_INNER) {
+        const int before = run->total;
+        st = run->advance(steps);
+        steps -= run->total - before;
+        if (st == AIM_OK && run->phase == GmresRun::DONE) {
+          if (phase == FP64_RUN) {
+            iters = gr.iters;
+            conv = gr.conv;
+            est = gr.est;
+            matvecs = gr.matvecs;
+            restarts = gr.restarts;
+            phase = FINAL;
+          } else {
+            st = mix_inner_done();
+          }
+        } else if (st == AIM_OK) {
+          return AIM_OK;   // the step budget is spent
+        }
+      } else if (phase == MIX_CHECK) {
+        st = mix_check();
+      } else {
+        st = finish();
+      }
+      if (st != AIM_OK) {
+        status = st;
+        phase = DONE;
+        return st;
+      }
+    }
+    return AIM_OK;
+  }
+
+  void fill(aim_solve_info* info, double secs) const {
+    const bool fin = phase == DONE && tr.size() == (size_t)nrhs;
+    for (int r = 0; r < nrhs; ++r) {
+      // a running FP64 solve reports the live counts of its GMRES
+      const bool live = phase == FP64_RUN && gr.iters.size() == (size_t)nrhs;
+      info[r].iterations = live ? gr.iters[r] : iters[r] + (phase == MIX_INNER && gr.iters.size() ==
+                                                             (size_t)nrhs ? gr.iters[r] : 0);
+      info[r].matvecs = (phase == FP64_RUN || phase == MIX_INNER) ? matvecs + gr.matvecs : matvecs;
+      info[r].restarts = (phase == FP64_RUN || phase == MIX_INNER) ? restarts + gr.restarts : restarts;
       info[r].outer = outer;
-      info[r].converged = cv ? 1 : 0;
-      info[r].resid_est = est[r];
-      info[r].resid_true = tr[r];
+      info[r].converged = fin && converged(r) ? 1 : 0;
+      info[r].resid_est = live ? gr.est[r] : est[r];
+      info[r].resid_true = fin ? tr[r] : -1.0;
       info[r].seconds = secs;
     }
   }
-  return all ? AIM_OK : AIM_E_NOCONV;
+};
+
+aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol, int maxit,
+                 int restart, aim_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  TRY(check_solve(c, form, precision, nrhs, tol, maxit, restart));
+  TRY(ensure_work(c, restart, nrhs));
+  SolveRun sr(c, c->gw, form, precision, nrhs, b, x, tol, maxit, restart);
+  TRY(sr.begin());
+  TRY(sr.advance(std::numeric_limits<long>::max()));
+  if (info) sr.fill(info, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  return sr.status;
 }
 
 // ---------------------------------------------------------------------------
-// Step-wise solver: one FP64 GMRES solve of a context's system that advances
-// by Arnoldi steps (serving schedulers interleave the steps of many requests).
-// It owns its workspace, so several solvers may share a context; their steps
-// then run in call order on the context's stream.
+// Step-wise solver: one solve of aim_solve (a SolveRun) on its own workspace,
+// advanced by Arnoldi steps (serving schedulers interleave the steps of many
+// requests).  Several solvers may share a context; their steps then run in
+// call order on the context's stream.
 // ---------------------------------------------------------------------------
 }  // namespace aim
 
 struct aim_solver_s {
   aim::Ctx* c = nullptr;
-  int form = 0, op = 0, nrhs = 0;
-  double tol = 0;
-  double2* x = nullptr;
-  const double2* rhs = nullptr;
   aim::GmresWork w;
-  aim::GmresResult res;
-  std::unique_ptr<aim::GmresRun> run;
-  aim_status status = AIM_PENDING;
-  std::vector<double> tr;
+  std::unique_ptr<aim::SolveRun> run;
   std::chrono::steady_clock::time_point t0;
   double seconds = 0;
 };
@@ -1098,22 +1197,18 @@ struct aim_solver_s {
 namespace aim {
 
 static void solver_free(aim_solver_s* sv) {
+  sv->run.reset();
   sv->c->dev_bytes -= sv->w.bytes;
   free_gmres_work(sv->w);
   delete sv;
 }
 
-aim_status solver_begin(Ctx* c, int form, int nrhs, const double2* b, double2* x, double tol, int maxit, int restart,
-                        aim_solver_s** out) {
-  TRY(check_solve(c, form, AIM_FP64, nrhs, tol, maxit, restart));
+aim_status solver_begin(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
+                        int maxit, int restart, aim_solver_s** out) {
+  TRY(check_solve(c, form, precision, nrhs, tol, maxit, restart));
   aim_solver_s* sv = new (std::nothrow) aim_solver_s();
   if (!sv) return AIM_E_OOM;
   sv->c = c;
-  sv->form = form;
-  sv->op = form_op(form);
-  sv->nrhs = nrhs;
-  sv->tol = tol;
-  sv->x = x;
   sv->t0 = std::chrono::steady_clock::now();
   aim_status st = alloc_work(c, sv->w, restart, nrhs);
   if (st != AIM_OK) {
@@ -1122,11 +1217,8 @@ aim_status solver_begin(Ctx* c, int form, int nrhs, const double2* b, double2* x
     return st;
   }
   c->dev_bytes += sv->w.bytes;
-  st = system_rhs(c, sv->w, form, nrhs, b, &sv->rhs);
-  if (st == AIM_OK) {
-    sv->run.reset(new (std::nothrow) GmresRun(c, sv->w, sv->op, nrhs, sv->rhs, x, tol, maxit, restart, sv->res));
-    st = sv->run ? sv->run->start() : AIM_E_OOM;
-  }
+  sv->run.reset(new (std::nothrow) SolveRun(c, sv->w, form, precision, nrhs, b, x, tol, maxit, restart));
+  st = sv->run ? sv->run->begin() : AIM_E_OOM;
   if (st != AIM_OK) {
     (void)hipStreamSynchronize(c->stream);
     solver_free(sv);
@@ -1136,53 +1228,27 @@ aim_status solver_begin(Ctx* c, int form, int nrhs, const double2* b, double2* x
   return AIM_OK;
 }
 
-// the end of a solve: the true residual with the FP64 operator, as aim_solve
-static aim_status solver_finish(aim_solver_s* sv) {
-  TRY(true_resid(sv->c, sv->w, sv->op, sv->nrhs, sv->rhs, sv->x, sv->tr));
-  bool all = true;
-  for (int r = 0; r < sv->nrhs; ++r) {
-    if (!std::isfinite(sv->tr[r])) return AIM_E_NUMERIC;
-    all = all && sv->res.conv[r] && sv->tr[r] <= sv->tol * 1.5;
-  }
-  return all ? AIM_OK : AIM_E_NOCONV;
-}
-
 aim_status solver_step(aim_solver_s** group, int count) {
   if (count < 0 || (count > 0 && !group)) return AIM_E_ARG;
   aim_status first = AIM_OK;
   for (int i = 0; i < count; ++i) {
     aim_solver_s* sv = group[i];
-    if (!sv || sv->status != AIM_PENDING) continue;
-    aim_status st = sv->run->advance(1);
-    if (st == AIM_OK && sv->run->phase == GmresRun::DONE) st = solver_finish(sv);
-    else if (st == AIM_OK) continue;
-    sv->status = st;
-    sv->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
-    if (st != AIM_OK && st != AIM_E_NOCONV && first == AIM_OK) first = st;
+    if (!sv || sv->run->phase == SolveRun::DONE) continue;
+    const aim_status st = sv->run->advance(1);
+    if (sv->run->phase == SolveRun::DONE)
+      sv->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+    if (st != AIM_OK && first == AIM_OK) first = st;
   }
   return first;
 }
 
 aim_status solver_poll(aim_solver_s* sv, aim_solve_info* info) {
   if (!sv) return AIM_E_ARG;
-  if (info) {
-    const bool done = sv->status != AIM_PENDING;
-    const double secs =
-        done ? sv->seconds : std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
-    const bool have = sv->res.iters.size() == (size_t)sv->nrhs;
-    for (int r = 0; r < sv->nrhs; ++r) {
-      info[r].iterations = have ? sv->res.iters[r] : 0;
-      info[r].matvecs = sv->res.matvecs;
-      info[r].restarts = sv->res.restarts;
-      info[r].outer = 0;
-      const bool fin = done && sv->tr.size() == (size_t)sv->nrhs;
-      info[r].converged = fin && sv->res.conv[r] && sv->tr[r] <= sv->tol * 1.5 ? 1 : 0;
-      info[r].resid_est = have ? sv->res.est[r] : 0.0;
-      info[r].resid_true = fin ? sv->tr[r] : -1.0;
-      info[r].seconds = secs;
-    }
-  }
-  return sv->status;
+  const bool done = sv->run->phase == SolveRun::DONE;
+  if (info)
+    sv->run->fill(info, done ? sv->seconds
+                             : std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count());
+  return done ? sv->run->status : AIM_PENDING;
 }
 
 aim_status solver_end(aim_solver_s* sv) {

@@ -94,4 +94,4 @@ def test_solver_calls_checked_on_the_host():
     assert lib.aim_solver_poll(None, None) == aim.AIM_E_ARG
     assert lib.aim_solver_end(None) == aim.AIM_E_ARG
     h = ctypes.c_void_p()
-    assert lib.aim_solver_begin(None, 0, 1, None, None, 1e-6, 10, 10, ctypes.byref(h)) == aim.AIM_E_ARG
+    assert lib.aim_solver_begin(None, 0, 0, 1, None, None, 1e-6, 10, 10, ctypes.byref(h)) == aim.AIM_E_ARG

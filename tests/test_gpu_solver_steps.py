@@ -1,9 +1,9 @@
 """Step-wise solving (aim_solver_begin / step / poll / end), the serving
 extension of the solve: a solver advanced by single Arnoldi steps, alone or
-interleaved with others on the same and on other contexts, ends bitwise at
-the result of aim_solve (same kernels in the same order, each solver on its
-own Krylov workspace); poll reports AIM_PENDING until the end and then the
-status aim_solve would return."""
+interleaved with others on the same and on other contexts, FP64 or mixed
+refinement, ends bitwise at the result of aim_solve (aim_solve runs the same
+state machine to the end; each solver has its own Krylov workspace); poll
+reports AIM_PENDING until the end and then the status aim_solve returns."""
 import math
 
 import numpy as np
@@ -25,7 +25,7 @@ ETA = wl.ETA0
 
 @pytest.fixture(scope="module")
 def ctxs():
-    cyl = aim.Context(wl.circle(1.0, 500), K, ETA, 0, 64, 0.1, max_rhs=2)
+    cyl = aim.Context(wl.circle(1.0, 500), K, ETA, 0, 64, 0.1, max_rhs=2, precision=aim.AIM_MIXED)
     cyl.filter(wl.alpha_half_bins(0.1))
     star = aim.Context(wl.star5(0.6, 256), K, ETA, 1, 64, 0.05, max_rhs=1)
     star.filter(wl.alpha_half_bins(0.05))
@@ -69,7 +69,7 @@ def test_interleaved_group_each_equals_its_solo_solve(ctxs):
     b1 = cyl.rhs_planewave(0.3)
     b2 = cyl.rhs_planewave([2.0, 4.0])
     b3 = star.rhs_planewave(0.7)
-    jobs = [(cyl, "TM", b1, dict(tol=1e-7, restart=24)),
+    jobs = [(cyl, "TM", b1, dict(tol=1e-7, restart=24, precision=aim.AIM_MIXED)),
             (cyl, "TM", b2, dict(tol=1e-9, restart=40)),
             (star, "TE_CP_UNF", b3, dict(tol=1e-8, restart=30))]
     refs = [c.solve(f, b, **kw) for c, f, b, kw in jobs]
@@ -81,6 +81,23 @@ def test_interleaved_group_each_equals_its_solo_solve(ctxs):
         assert torch.equal(sv.x, x_ref)
         assert [d["iterations"] for d in info] == [d["iterations"] for d in info_ref]
         sv.end()
+
+
+def test_stepwise_mixed_refinement_equals_aim_solve(ctxs):
+    cyl, _ = ctxs
+    b = cyl.rhs_planewave([0.5, 2.5])
+    kw = dict(tol=1e-8, restart=20, maxit=2000, precision=aim.AIM_MIXED)
+    x_ref, info_ref = cyl.solve("TM", b, **kw)
+    sv = aim.Solver(cyl, "TM", b, **kw)
+    _run([sv])
+    st, info = sv.poll()
+    print("mixed: outer", info[0]["outer"], "inner steps", [d["iterations"] for d in info])
+    assert st == aim.AIM_OK and info[0]["outer"] >= 2
+    assert torch.equal(sv.x, x_ref)
+    for d, e in zip(info, info_ref):
+        assert (d["iterations"], d["matvecs"], d["outer"], d["resid_true"]) == \
+            (e["iterations"], e["matvecs"], e["outer"], e["resid_true"])
+    sv.end()
 
 
 def test_maxit_reports_noconv_like_aim_solve(ctxs):
