@@ -78,9 +78,19 @@ def serving(n_req, slots=4, budget=96 << 30):
     reqs = wl.serving_stream(n_req, rate=rate)
     srv = serve.Server(exe, hbm_budget=budget, slots=slots)
     out = serve.summarize(srv.run(reqs, realtime=True), srv.wall)
+    # iteration-level batching: one host thread steps every admitted request's
+    # solver once per round (aim_solver_step), same requests and rate
+    eng = serve.GpuStepEngine(restart=1000)
+    reqs = wl.serving_stream(n_req, rate=0.0)
+    srv = serve.StepServer(eng, hbm_budget=budget, slots=2 * slots)
+    scap = serve.summarize(srv.run(reqs, realtime=False), srv.wall)
+    reqs = wl.serving_stream(n_req, rate=rate)
+    srv = serve.StepServer(eng, hbm_budget=budget, slots=2 * slots)
+    sout = serve.summarize(srv.run(reqs, realtime=True), srv.wall)
     return {"stream": f"{n_req} TM requests, random stars ka~logU[10,400], 1-16 rhs, FP64/mixed, "
                       f"{slots} slots, HBM budget {budget >> 30} GiB",
-            "closed_loop": cap, "poisson_rate_per_s": rate, "poisson": out}
+            "closed_loop": cap, "poisson_rate_per_s": rate, "poisson": out,
+            "step_server": {"slots": 2 * slots, "closed_loop": scap, "poisson": sout}}
 
 
 def kernel_bytes(kid, inf, nch=1, nrhs=1, b=16):

@@ -186,6 +186,176 @@ class Server:
         return [results[r.rid] for r in reqs]
 
 
+class GpuStepEngine:
+    """Step-wise requests for StepServer: set-up (context, right-hand sides,
+    aim solver) on the request's own stream, one Arnoldi step per round for
+    every running solver in one aim_solver_step call, retirement (monostatic
+    RCS, release)."""
+
+    def __init__(self, restart=1000, maxit=4000, keep_solution=False):
+        self.restart = restart
+        self.maxit = maxit
+        self.keep = keep_solution
+
+    def footprint(self, req):
+        return gpu_footprint(req, self.restart)
+
+    def prepare(self, req):
+        import torch
+        from . import aim
+        stream = torch.cuda.Stream()            # default priority
+        prec = aim.AIM_MIXED if req.precision else aim.AIM_FP64
+        ctx = aim.Context(req.xy, req.k, req.eta, req.basis, req.m, req.eps, precision=prec,
+                          max_rhs=len(req.phis), stream=stream)
+        try:
+            with torch.cuda.stream(stream):
+                b = ctx.rhs_planewave(np.asarray(req.phis, dtype=float))
+            solver = aim.Solver(ctx, "TM", b, tol=req.tol, maxit=self.maxit, restart=self.restart, precision=prec)
+        except Exception:
+            stream.synchronize()
+            ctx.close()
+            raise
+        return {"ctx": ctx, "stream": stream, "solver": solver}
+
+    def step(self, jobs):
+        from . import aim
+        aim.aim_solver_step([j["solver"] for j in jobs])
+
+    def done(self, job):
+        from . import aim
+        return job["solver"].poll()[0] != aim.AIM_PENDING
+
+    def finish(self, req, job, res: ServeResult):
+        from . import aim
+        import torch
+        ctx, solver = job["ctx"], job["solver"]
+        try:
+            st, info = solver.poll()
+            solver.end()                         # the stream has drained
+            if st not in (aim.AIM_OK, aim.AIM_E_NOCONV):
+                raise aim.AimError(st, "solver")
+            with torch.cuda.stream(job["stream"]):
+                res.sigma = ctx.rcs(solver.x, req.phis)
+            res.iterations = max(d["iterations"] for d in info)
+            res.matvecs = max(d["matvecs"] for d in info)
+            res.resid = max(d["resid_true"] for d in info)
+            res.status = "ok" if st == aim.AIM_OK else "noconv"
+            if self.keep:
+                res.x = solver.x.cpu().numpy()
+        finally:
+            job["stream"].synchronize()
+            ctx.close()
+        res.n, res.m, res.nrhs, res.precision = len(req.xy), req.m, len(req.phis), req.precision
+
+    def discard(self, job):
+        job["solver"].end()
+        job["stream"].synchronize()
+        job["ctx"].close()
+
+
+class StepServer:
+    """Iteration-level continuous batching on one host thread.  Requests are
+    admitted first-come first-served while a slot is free and their footprint
+    fits the HBM budget; a small pool of set-up threads prepares each admitted
+    request; every round gives each prepared, unfinished request one Arnoldi
+    step, then retires the finished ones, so a request that arrives while
+    others run starts stepping with them at the next round."""
+
+    def __init__(self, engine, hbm_budget: int, slots: int = 8, setup_workers: int = 2):
+        self.eng = engine
+        self.budget = int(hbm_budget)
+        self.slots = int(slots)
+        self.setup_workers = int(setup_workers)
+        self.max_reserved = 0
+        self.max_active = 0
+        self.rounds = 0
+
+    def run(self, requests, realtime: bool = True):
+        from concurrent.futures import ThreadPoolExecutor
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        byid = {r.rid: r for r in reqs}
+        results = {r.rid: ServeResult(r.rid, r.arrival) for r in reqs}
+        pool = ThreadPoolExecutor(max_workers=self.setup_workers)
+        pending = deque()
+        setting_up = {}                      # rid -> future
+        running = {}                         # rid -> job
+        fp = {}
+        reserved = 0
+        nxt = 0
+        finished = 0
+        t0 = time.perf_counter()
+        offset = 0.0 if realtime else None
+
+        def release(rid, status=None):
+            nonlocal reserved, finished
+            reserved -= fp[rid]
+            finished += 1
+            if status is not None:
+                results[rid].status = status
+            results[rid].finish = time.perf_counter() - t0
+
+        try:
+            while finished < len(reqs):
+                now = time.perf_counter() - t0
+                idle = not pending and not setting_up and not running
+                if not realtime and nxt < len(reqs) and idle:
+                    offset = reqs[nxt].arrival - now     # skip idle gaps in simulated time
+                eff = now + (offset or 0.0)
+                while nxt < len(reqs) and reqs[nxt].arrival <= eff:
+                    r = reqs[nxt]
+                    fp[r.rid] = self.eng.footprint(r)
+                    results[r.rid].footprint = fp[r.rid]
+                    if fp[r.rid] > self.budget:
+                        results[r.rid].status = "rejected"
+                        results[r.rid].finish = now
+                        finished += 1
+                    else:
+                        pending.append(r)
+                    nxt += 1
+                while pending and len(setting_up) + len(running) < self.slots and \
+                        reserved + fp[pending[0].rid] <= self.budget:
+                    r = pending.popleft()
+                    reserved += fp[r.rid]
+                    results[r.rid].admit = time.perf_counter() - t0
+                    setting_up[r.rid] = pool.submit(self.eng.prepare, r)
+                    self.max_reserved = max(self.max_reserved, reserved)
+                    self.max_active = max(self.max_active, len(setting_up) + len(running))
+                for rid in [rid for rid, f in setting_up.items() if f.done()]:
+                    f = setting_up.pop(rid)
+                    try:
+                        running[rid] = f.result()
+                    except Exception as e:               # failure is recorded, the loop goes on
+                        release(rid, f"error: {e}")
+                if running:
+                    rids = list(running)
+                    self.eng.step([running[rid] for rid in rids])
+                    self.rounds += 1
+                    for rid in rids:
+                        if self.eng.done(running[rid]):
+                            job = running.pop(rid)
+                            try:
+                                self.eng.finish(byid[rid], job, results[rid])
+                            except Exception as e:
+                                results[rid].status = f"error: {e}"
+                            release(rid)
+                else:
+                    wait = 0.001
+                    if nxt < len(reqs) and realtime:
+                        wait = max(0.0, min(wait, reqs[nxt].arrival - (time.perf_counter() - t0)))
+                    time.sleep(wait)
+        finally:
+            for f in setting_up.values():
+                try:
+                    self.eng.discard(f.result())
+                except Exception:
+                    pass
+            for job in running.values():
+                self.eng.discard(job)
+            pool.shutdown(wait=True)
+        self.wall = time.perf_counter() - t0
+        return [results[r.rid] for r in reqs]
+
+
 def summarize(results, wall):
     ok = [r for r in results if r.status == "ok"]
     lat = sorted(r.latency for r in ok)

@@ -108,3 +108,107 @@ def test_result_identical_alone_and_in_mix():
         assert np.array_equal(out.x, a.x), out.rid
         assert np.array_equal(out.sigma, a.sigma)
         assert out.resid <= 1.0000001 * reqs[out.rid].tol
+
+
+class FakeStepEngine:
+    """Step-wise stand-in: request rid needs steps[rid] rounds."""
+
+    def __init__(self, fps, steps, fail_prepare=(), fail_finish=()):
+        self.fps = fps
+        self.steps = steps
+        self.fail_prepare = set(fail_prepare)
+        self.fail_finish = set(fail_finish)
+        self.order = []
+        self.peak = 0
+        self.discarded = 0
+
+    def footprint(self, req):
+        return self.fps[req.rid]
+
+    def prepare(self, req):
+        if req.rid in self.fail_prepare:
+            raise RuntimeError("setup failed")
+        return {"rid": req.rid, "left": self.steps[req.rid]}
+
+    def step(self, jobs):
+        self.peak = max(self.peak, len(jobs))
+        for j in jobs:
+            j["left"] -= 1
+        time.sleep(2e-4)      # a device step takes time and releases the GIL
+
+    def done(self, job):
+        return job["left"] <= 0
+
+    def finish(self, req, job, res):
+        if req.rid in self.fail_finish:
+            raise RuntimeError("retire failed")
+        self.order.append(req.rid)
+        res.status = "ok"
+        res.nrhs = len(req.phis)
+        res.matvecs = self.steps[req.rid]
+
+    def discard(self, job):
+        self.discarded += 1
+
+
+def test_step_server_admission_budget_slots_fifo():
+    reqs = _reqs([0.0] * 7)
+    fps = {0: 40, 1: 40, 2: 40, 3: 10, 4: 90, 5: 10, 6: 200}
+    eng = FakeStepEngine(fps, {i: 20 for i in fps})
+    srv = serve.StepServer(eng, hbm_budget=100, slots=3, setup_workers=2)
+    res = srv.run(reqs, realtime=False)
+    st = {r.rid: r.status for r in res}
+    assert st[6] == "rejected" and all(st[i] == "ok" for i in range(6))
+    assert srv.max_reserved <= 100 and srv.max_active <= 3 and eng.peak <= 3
+    admits = [r.admit for r in res if r.status == "ok"]
+    assert admits == sorted(admits)
+
+
+def test_step_server_short_request_overtakes_long_one():
+    """Interleaving at step granularity: a short request admitted after a long
+    one finishes first, and the long one keeps stepping meanwhile."""
+    reqs = _reqs([0.0, 0.0])
+    eng = FakeStepEngine({0: 1, 1: 1}, {0: 400, 1: 5})
+    srv = serve.StepServer(eng, hbm_budget=10, slots=2, setup_workers=1)
+    res = srv.run(reqs, realtime=False)
+    assert all(r.status == "ok" for r in res)
+    assert eng.order == [1, 0] and eng.peak == 2
+    assert srv.rounds >= 400
+
+
+def test_step_server_failures_recorded():
+    reqs = _reqs([0.0, 0.0, 0.0, 0.0])
+    eng = FakeStepEngine({i: 1 for i in range(4)}, {i: 3 for i in range(4)}, fail_prepare={1}, fail_finish={2})
+    res = serve.StepServer(eng, hbm_budget=10, slots=4).run(reqs, realtime=False)
+    st = [r.status for r in res]
+    assert st[0] == "ok" and st[3] == "ok"
+    assert st[1].startswith("error: setup") and st[2].startswith("error: retire")
+
+
+@pytest.mark.gpu
+def test_step_server_results_identical_alone_in_mix_and_threaded():
+    """Each request's result is bitwise the same solved alone, interleaved
+    step by step with the others, and by the thread-per-request server."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    reqs = wl.serving_stream(5, rate=0.0, seed=11, ka_range=(10.0, 40.0), max_rhs=3)
+    eng = serve.GpuStepEngine(restart=200, keep_solution=True)
+    alone = {}
+    for r in reqs:
+        out = serve.StepServer(eng, hbm_budget=64 << 30, slots=1).run([r], realtime=False)[0]
+        assert out.status == "ok", out.status
+        alone[r.rid] = out
+    srv = serve.StepServer(eng, hbm_budget=64 << 30, slots=8)
+    mix = srv.run(reqs, realtime=False)
+    assert srv.max_active >= 2
+    threaded = serve.Server(serve.GpuExecutor(restart=200, keep_solution=True), hbm_budget=64 << 30,
+                            slots=4).run(reqs, realtime=False)
+    th = {o.rid: o for o in threaded}
+    for out in mix:
+        assert out.status == "ok"
+        a = alone[out.rid]
+        assert np.array_equal(out.x, a.x), out.rid
+        assert np.array_equal(out.sigma, a.sigma)
+        assert np.array_equal(th[out.rid].x, a.x) and np.array_equal(th[out.rid].sigma, a.sigma)
+        assert out.resid <= 1.0000001 * reqs[out.rid].tol
