@@ -209,19 +209,21 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                      const void* b_dev, void* x_dev, double tol, int32_t maxit,
                      int32_t restart, aim_solve_info* info_host);
 
-/* Step-wise solving for serving schedulers: a solver holds one solve of
+/* Step-wise solving for serving schedulers.  A solver holds one solve of
    aim_solve (any form, FP64 or AIM_MIXED refinement) and advances it by
    Arnoldi steps (inner steps for AIM_MIXED), so one host thread can
    interleave the steps of many requests, admit new requests between steps
-   and retire finished ones (iteration-level batching).  Each solver owns its Krylov workspace
-   (restart + 1 vectors per rhs), so several may share a context; the steps of
-   solvers on one context run in call order on its stream, solvers on
-   different contexts overlap on the device.  Apart from the host reads that
-   close each batch of 8 Arnoldi steps (and a cycle's first and last step),
-   steps are asynchronous.  aim_solve is the same machinery run to the end,
-   so a solver's result is bitwise that of aim_solve.
+   and retire finished ones (iteration-level batching).  Each solver owns its
+   Krylov workspace (restart + 1 vectors per rhs), so several may share a
+   context: their steps run in call order on its stream, while solvers on
+   different contexts overlap on the device.  A step synchronises the stream
+   only where the solve reads results on the host: when it closes a batch of
+   8 Arnoldi steps, at a restart cycle's first step (true residual), and at
+   a refinement check of AIM_MIXED; other steps only enqueue work.
+   aim_solve is the same machinery run to the end, so a solver's result is
+   bitwise that of aim_solve.
 
-   aim_solver_begin: arguments as aim_solve; b_dev (caller-owned, N x nrhs)
+   aim_solver_begin: arguments as aim_solve.  b_dev (caller-owned, N x nrhs)
    must stay valid and unchanged until the solver ends; x_dev holds the
    initial guess and receives the iterate at the end of every restart cycle
    and the solution when the solve finishes.  Allocates the workspace, forms
@@ -229,18 +231,17 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
    norms of b (synchronises the stream).  Errors as aim_solve (AIM_E_ARG,
    AIM_E_STATE, AIM_E_OOM, AIM_E_HIP); on error *out is unchanged.
    aim_solver_step: one Arnoldi step for each unfinished solver of
-   group[0 .. count-1] (NULL entries and finished solvers are skipped); a
-   step that completes a batch also checks and restarts, and a step that
-   finishes the solve also computes the true FP64 residual.  For AIM_MIXED
-   the refinement's outer checks (true FP64 residual) run inside the step
-   that ends an inner solve.  Returns AIM_OK,
-   or the first error a solver met (that solver finishes with it).
+   group[0 .. count-1]; NULL entries and finished solvers are skipped.  A
+   step that completes a batch also checks and restarts, the step that ends
+   an AIM_MIXED inner solve also runs the refinement check, and the step
+   that finishes the solve also computes the true FP64 residual.  Returns
+   AIM_OK, or the first error a solver met (that solver finishes with it).
    aim_solver_poll: progress or result into info_host (nrhs entries, may be
    NULL; resid_true is -1 until the solve finishes).  Returns AIM_PENDING
    while the solve runs, then AIM_OK (converged), AIM_E_NOCONV (maxit
    reached) or the error that ended it.  Does not touch the device.
-   aim_solver_end: waits for the solver's work on the stream, frees it.
-   End the solvers of a context before aim_destroy.                            */
+   aim_solver_end: waits for the solver's work on the stream and frees it.
+   End the solvers of a context before aim_destroy.                          */
 aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev,
                             void* x_dev, double tol, int32_t maxit, int32_t restart, aim_solver* out);
 aim_status aim_solver_step(aim_solver* group, int32_t count);
