@@ -72,21 +72,26 @@ def serving(n_req, slots=4, budget=96 << 30):
     from paper_2606_10784_amd import workloads as wl
     exe = serve.GpuExecutor(restart=1000)
     reqs = wl.serving_stream(n_req, rate=0.0)
+    def done(what, summ):
+        print(f"[bench] serving {what}: {summ['completed']}/{summ['requests']} in {summ['wall_s']:.1f} s, "
+              f"p50 {summ['latency_s']['p50']:.3f} s", file=sys.stderr, flush=True)
+        return summ
+
     srv = serve.Server(exe, hbm_budget=budget, slots=slots)
-    cap = serve.summarize(srv.run(reqs, realtime=False), srv.wall)
+    cap = done("threads closed loop", serve.summarize(srv.run(reqs, realtime=False), srv.wall))
     rate = 0.7 * cap["requests_per_s"]
     reqs = wl.serving_stream(n_req, rate=rate)
     srv = serve.Server(exe, hbm_budget=budget, slots=slots)
-    out = serve.summarize(srv.run(reqs, realtime=True), srv.wall)
+    out = done("threads poisson", serve.summarize(srv.run(reqs, realtime=True), srv.wall))
     # iteration-level batching: one host thread steps every admitted request's
     # solver once per round (aim_solver_step), same requests and rate
     eng = serve.GpuStepEngine(restart=1000)
     reqs = wl.serving_stream(n_req, rate=0.0)
     srv = serve.StepServer(eng, hbm_budget=budget, slots=2 * slots)
-    scap = serve.summarize(srv.run(reqs, realtime=False), srv.wall)
+    scap = done("steps closed loop", serve.summarize(srv.run(reqs, realtime=False), srv.wall))
     reqs = wl.serving_stream(n_req, rate=rate)
     srv = serve.StepServer(eng, hbm_budget=budget, slots=2 * slots)
-    sout = serve.summarize(srv.run(reqs, realtime=True), srv.wall)
+    sout = done("steps poisson", serve.summarize(srv.run(reqs, realtime=True), srv.wall))
     return {"stream": f"{n_req} TM requests, random stars ka~logU[10,400], 1-16 rhs, FP64/mixed, "
                       f"{slots} slots, HBM budget {budget >> 30} GiB",
             "closed_loop": cap, "poisson_rate_per_s": rate, "poisson": out,
