@@ -13,6 +13,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import weakref
 
 import numpy as np
 
@@ -191,13 +192,18 @@ class Context:
         self.basis = basis
         self.max_rhs = max_rhs
         self.precision = precision
+        self._solvers = weakref.WeakSet()      # live step-wise solvers on this context
 
     @property
     def handle(self):
         return self._h
 
     def close(self):
+        """Ends the context's live solvers (the library requires it), then
+        destroys the context."""
         if getattr(self, "_h", None):
+            for sv in list(getattr(self, "_solvers", ())):
+                sv.end()
             _lib().aim_destroy(self._h)
             self._h = None
 
@@ -307,6 +313,7 @@ class Solver:
                                        ctypes.c_void_p(self.x.data_ptr()), float(tol), int(maxit), int(restart),
                                        ctypes.byref(h)), "aim_solver_begin")
         self.handle = h.value
+        ctx._solvers.add(self)
 
     def step(self):
         return aim_solver_step([self])

@@ -123,3 +123,14 @@ def test_solver_arguments_rejected(ctxs):
         aim.Solver(cyl, "TE_CP", b)                      # hat form on a pulse context
     with pytest.raises(aim.AimError):
         aim.Solver(star, "TM", star.rhs_planewave(0.0))  # pulse form on a hat context
+
+
+def test_closing_a_context_ends_its_solvers():
+    ctx = aim.Context(wl.circle(1.0, 200), K, ETA, 0, 64, 0.1, max_rhs=1)
+    b = ctx.rhs_planewave(0.0)
+    sv = aim.Solver(ctx, "TM", b, tol=1e-8, restart=20)
+    for _ in range(5):
+        sv.step()
+    ctx.close()                                      # ends the running solver first
+    assert sv.handle is None
+    sv.end()                                         # a second end is a no-op
