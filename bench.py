@@ -468,6 +468,17 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     mv32_ms = e0.elapsed_time(e1) / args.matvecs
+    # per-matvec distribution: 100 matvecs, each between its own event pair
+    def spread(op):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+        for a, z in evs:
+            a.record()
+            ctx.matvec(op, xprobe, yprobe)
+            z.record()
+        torch.cuda.synchronize()
+        t = np.sort([a.elapsed_time(z) for a, z in evs])
+        return {"p10": float(t[9]), "p50": float(np.median(t)), "p90": float(t[89])}
+    mv_spread = {"fp64": spread("TM"), "fp32_grid": spread(aim.AIM_OP_TM | aim.AIM_OP_GRID_FP32)}
 
     # mixed-precision solve at the same accuracy (reported beside value)
     tm0 = time.perf_counter()
@@ -518,7 +529,7 @@ def main():
         "iterations": its,
         "resid_true": max(res),
         "matvec_only": {"fp64_ms": mv_ms, "fp64_per_s": 1e3 / mv_ms, "fp32_grid_ms": mv32_ms,
-                        "fp32_grid_per_s": 1e3 / mv32_ms},
+                        "fp32_grid_per_s": 1e3 / mv32_ms, "each_ms": mv_spread},
         "mixed_solve": {"seconds": t_mixed, "iterations": infm[0]["iterations"], "outer": infm[0]["outer"],
                         "resid_true": infm[0]["resid_true"], "rel_diff_vs_fp64": dx,
                         "speedup_vs_fp64": (t_total / args.steps) / t_mixed},
