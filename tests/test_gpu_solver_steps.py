@@ -134,3 +134,23 @@ def test_closing_a_context_ends_its_solvers():
     ctx.close()                                      # ends the running solver first
     assert sv.handle is None
     sv.end()                                         # a second end is a no-op
+
+
+def test_stepwise_tm_calderon_equals_aim_solve():
+    """The TM Calderon form (dual hat space, preconditioned right-hand side
+    formed at begin), FP64 and mixed."""
+    ctx = aim.Context(wl.circle(1.0, 96), K, ETA, 0, 64, 0.1, max_rhs=1, precision=aim.AIM_MIXED, dual=1)
+    try:
+        b = ctx.rhs_planewave(0.4)
+        for prec in (aim.AIM_FP64, aim.AIM_MIXED):
+            kw = dict(tol=1e-8, restart=16, maxit=500, precision=prec)
+            x_ref, info_ref = ctx.solve("TM_CP_UNF", b, **kw)
+            sv = aim.Solver(ctx, "TM_CP_UNF", b, **kw)
+            _run([sv])
+            st, info = sv.poll()
+            assert st == aim.AIM_OK
+            assert torch.equal(sv.x, x_ref)
+            assert info[0]["iterations"] == info_ref[0]["iterations"]
+            sv.end()
+    finally:
+        ctx.close()
