@@ -675,8 +675,8 @@ struct GmresResult {
 // a state machine that advances by Arnoldi steps: a cycle starts with the
 // true residual of x (top), takes steps in batches of up to kCheckEvery,
 // closes each batch with its rotations and residual estimates (the one host
-// synchronisation), and ends with x += V y.  gmres() runs it to the end;
-// the step-wise solver API advances it a step at a time.  Both issue the
+// synchronisation), and ends with x += V y.  SolveRun drives it: to the end
+// for aim_solve, a step at a time for the step-wise solver; both issue the
 // same kernels in the same order.
 struct GmresRun {
   enum Phase { TOP, ARNOLDI, DONE };
@@ -921,14 +921,6 @@ struct GmresRun {
     return AIM_OK;
   }
 };
-
-static aim_status gmres(Ctx* c, int op, int nrhs, const double2* b, double2* x, double tol, int maxit, int restart,
-                        GmresResult& res) {
-  TRY(ensure_work(c, restart, nrhs));
-  GmresRun run(c, c->gw, op, nrhs, b, x, tol, maxit, restart, res);
-  TRY(run.start());
-  return run.advance(std::numeric_limits<long>::max());
-}
 
 static int form_op(int form) {
   switch (form) {
