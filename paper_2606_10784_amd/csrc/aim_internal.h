@@ -246,6 +246,7 @@ aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, doubl
 aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host, double2* lambda_host);
 aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
                  int maxit, int restart, aim_solve_info* info);
+size_t gmres_work_bytes(size_t N, size_t restart, size_t nrhs);
 aim_status solver_begin(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
                         int maxit, int restart, aim_solver_s** out);
 aim_status solver_step(aim_solver_s** group, int count);

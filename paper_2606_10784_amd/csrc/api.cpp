@@ -73,20 +73,36 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
     S = side * side * (p->basis == AIM_HAT ? 2 : 1);
   }
   const size_t nact = t ? t->n_act : S * N;
-  const size_t near = t ? t->nr_col.size()
-                        : (p->node_order > 0 ? 0 : N * (size_t)((2 * p->near_radius + 1) * 3));
+  // near pairs: a basis pairs with the bases whose anchors lie in the
+  // (2R+1)^2-cell box around its own; the contour inside that box is at most
+  // its diagonal, (2R+1) sqrt(2) eps, long for a curve smooth on the box's
+  // scale, holding that length over the mean segment length of bases (+4)
+  size_t near = 0;
+  if (t) {
+    near = t->nr_col.size();
+  } else if (p->node_order == 0 && p->xy && N > 0) {
+    double len = 0;
+    for (size_t i = 0; i < N; ++i) {
+      const size_t i1 = (i + 1) % N;
+      len += std::hypot(p->xy[2 * i1] - p->xy[2 * i], p->xy[2 * i1 + 1] - p->xy[2 * i + 1]);
+    }
+    const double per = (2 * p->near_radius + 1) * std::sqrt(2.0) * p->eps / (len / N) + 4;
+    near = N * (size_t)std::ceil(std::min(per, (double)N));
+  }
+  const size_t nvals = p->basis == AIM_HAT ? 2 : 1;             // S (and N for hats) per near pair
   size_t b = 0;
   b += nch * R * ((size_t)tile_rows((int)nr) * n + 2 * nact) * 16;   // U, T, V
   b += 2 * H * spec_row_len((int)n) * 16 * (p->precision == AIM_MIXED ? 1.5 : 1.0);
-  b += near * (4 + 16 * (p->basis == AIM_HAT ? 2 : 1));
-  if (t && t->band_w >= 0) b += (size_t)(t->band_w + 1) * N * 16 * (p->basis == AIM_HAT ? 2 : 1);
+  b += near * (4 + 4 + 16 * nvals) + (N + 1) * 4;               // CSR (+ row of each entry)
+  if (t && t->band_w >= 0) b += (size_t)(t->band_w + 1) * N * 16 * nvals;
+  else if (!t) b += near * 16 * nvals;                           // the band form, kept only when smaller
   b += N * S * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
-  b += 3 * N * R * 16;
-  b += (size_t)R * (restart + 1) * N * 16 + (size_t)5 * R * N * 16;
+  b += 3 * N * R * 16 + std::max<size_t>(5 * N, 64) * R * 8;    // tmp1, tmp2, rhs, reductions
+  b += gmres_work_bytes(N, restart, R);
   if (p->dual && p->basis == AIM_PULSE && p->xy) {   // the dual hat context (no Krylov space)
     const std::vector<double> rxy = refined_xy(p);
     const aim_params q = dual_params(p, rxy);
-    b += footprint(&q, 1, nullptr) - (size_t)R * 2 * q.n_vertices * 16 - (size_t)5 * R * q.n_vertices * 16;
+    b += footprint(&q, 1, nullptr) - gmres_work_bytes(q.n_vertices, 1, R);
   }
   return b;
 }

@@ -581,6 +581,15 @@ void free_gmres_work(GmresWork& w) {
   w = GmresWork();
 }
 
+// Device bytes of the workspace alloc_work allocates (its allocation list).
+size_t gmres_work_bytes(size_t N, size_t restart, size_t nrhs) {
+  const size_t ldh = restart + 1, nchunk = (N + RED_CHUNK - 1) / RED_CHUNK;
+  const size_t c16 = nrhs * 16;
+  return c16 * (ldh * N + N + ldh * restart + ldh * ldh + 2 * ldh + (2 * ldh + 2) + ldh + 3 * restart +
+                ldh * nchunk * 2 + 3 * N + 2) +
+         nrhs * restart * 8 + nrhs * nchunk * 8 + nrhs * 4 * 2;
+}
+
 // Allocates the workspace for (restart, nrhs) into the empty w; on an error
 // the caller frees whatever was allocated.
 static aim_status alloc_work(Ctx* c, GmresWork& w, int restart, int nrhs) {

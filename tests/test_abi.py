@@ -25,8 +25,16 @@ def test_strerror_and_footprint_are_host_only():
     fp = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=1)
     # T intermediate alone: nr x n x 16 bytes, nr <= m
     assert 1024 * 2048 * 16 < fp < 2e9
+    # affine in the batch size: per-rhs buffers (intermediates, Krylov space)
+    # on top of the per-context tables
+    fp2 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=2)
     fp8 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=8)
-    assert fp8 > 4 * fp
+    assert fp2 > fp and fp8 - fp == 7 * (fp2 - fp)
+    # the Krylov space grows with the restart length, its Hessenberg part
+    # quadratically
+    f100 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, restart=100)
+    f1000 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, restart=1000)
+    assert f1000 - f100 > 900 * 16384 * 16 + (1001 ** 2 - 101 ** 2) * 16
 
 
 def test_setup_rejects_bad_arguments_without_device():
