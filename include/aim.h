@@ -153,8 +153,12 @@ typedef struct {
   double seconds;        /* wall time of the call                                */
 } aim_solve_info;
 
-/* Device bytes aim_setup would allocate for these parameters (host-only
-   estimate used for admission control; no device call).                      */
+/* Upper estimate of the device bytes a context with these parameters holds
+   after aim_setup and a solve with this restart length: its tables and
+   buffers, the GMRES workspace (exact) and its grid-kernel spectrum in the
+   shared cache; near-field pairs are bounded from the geometry (eps over the
+   mean segment length).  Host-only, for admission control; 0 for invalid
+   parameters.                                                                 */
 size_t aim_footprint_bytes(const aim_params* p, int32_t restart);
 
 /* Build a context: host geometry, Gauss-Legendre nodes (eq. (7)), stencil
