@@ -102,7 +102,8 @@ enum { AIM_FP64 = 0, AIM_MIXED = 1 };
 #define AIM_MAX_RHS 4096
 
 typedef struct {
-  int32_t n_vertices;     /* N >= 3: closed polygon, CCW, segment j = v_j -> v_{j+1} */
+  int32_t n_vertices;     /* N >= 8: closed polygon, CCW, segment j = v_j -> v_{j+1},
+                             each at most one wavelength long (k h <= 2 pi)     */
   const double* xy;       /* host, 2N interleaved (x, y); copied during aim_setup   */
   double k;               /* wavenumber (rad / length unit), > 0                    */
   double eta;             /* medium impedance (ohm)                                 */
@@ -110,7 +111,7 @@ typedef struct {
   int32_t m;              /* grid points per side (power of two, 16..2048)          */
   double eps;             /* grid step; grid centred at 0, L = (m-1) eps / 2        */
   int32_t quad;           /* Gauss-Legendre nodes per segment in the stencils (>=1) */
-  int32_t near_radius;    /* anchor Chebyshev radius of the near zone (>= 3)        */
+  int32_t near_radius;    /* anchor Chebyshev radius of the near zone, 3..m-4       */
   int32_t precision;      /* AIM_FP64 or AIM_MIXED (also builds the FP32 grid data) */
   int32_t max_rhs;        /* largest nrhs of later calls (1..AIM_MAX_RHS)           */
   void* stream;           /* hipStream_t for all device work (NULL: default stream) */

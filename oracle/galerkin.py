@@ -21,7 +21,9 @@ entries; here they are integrated properly):
   * identical segments: with delta = |tau - sigma| the double integral
     collapses to int_0^1 g(h delta) Q_uv(delta) d delta, Q_uv a polynomial.
     g = -(1/2pi) J0(kR) ln R + F(R); the J0 ln part is integrated exactly
-    term by term of the J0 power series, F by Gauss-Legendre;
+    term by term of the J0 power series, F by Gauss-Legendre (24 series
+    terms: accurate to FP64 rounding for k h up to one wavelength per
+    segment, k h <= 2 pi; past a few wavelengths the terms cancel);
   * segments sharing a vertex: polar coordinates (rho, psi) about the shared
     vertex; the rho integral of rho^q (ln rho + ln r(psi)) is exact term by
     term, psi by Gauss-Legendre on the two sub-ranges split at the rectangle

@@ -103,7 +103,7 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
   if (m < 16 || m > 2048 || (m & (m - 1))) { err = "m must be a power of two in [16, 2048]"; return AIM_E_ARG; }
   if (!(p->eps > 0) || !(p->k > 0) || !(p->eta > 0)) { err = "eps, k, eta must be positive"; return AIM_E_ARG; }
   if (p->quad < 1 || p->quad > 64) { err = "quad must be in [1, 64]"; return AIM_E_ARG; }
-  if (p->near_radius < 0 || p->near_radius + 3 > m - 1) { err = "near_radius out of range"; return AIM_E_ARG; }
+  if (p->near_radius < 3 || p->near_radius + 3 > m - 1) { err = "near_radius out of range"; return AIM_E_ARG; }
   if (p->basis != AIM_PULSE && p->basis != AIM_HAT) { err = "basis"; return AIM_E_ARG; }
   if (p->max_rhs < 1 || p->max_rhs > AIM_MAX_RHS) { err = "max_rhs"; return AIM_E_ARG; }
   const int P = p->node_order;
@@ -135,6 +135,10 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
     double dx = t.vx[j1] - t.vx[j], dy = t.vy[j1] - t.vy[j];
     double h = std::hypot(dx, dy);
     if (!(h > 0)) { err = "degenerate segment"; return AIM_E_ARG; }
+    // The singular near-field moments sum the J0 power series in k h; past
+    // one wavelength per segment its terms cancel beyond FP64 accuracy (and a
+    // Galerkin mesh that coarse does not resolve the current anyway).
+    if (!(p->k * h <= 2.0 * 3.141592653589793)) { err = "segment longer than a wavelength"; return AIM_E_ARG; }
     t.h[j] = h;
     t.tx[j] = dx / h;
     t.ty[j] = dy / h;

@@ -45,6 +45,13 @@ def test_setup_rejects_bad_arguments_without_device():
     assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
     p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, 16, 0.1)   # contour leaves grid
     assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_GEOM
+    p, _keep = aim.make_params(wl.circle(0.4, 8), 4 * wl.K0, wl.ETA0, 0, 16, 0.1)  # k h > 2 pi
+    assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+    p, _keep = aim.make_params(wl.circle(0.4, 7), wl.K0, wl.ETA0, 0, 16, 0.1)    # fewer than 8 vertices
+    assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+    for bad in (2, 61):                                                           # near_radius outside 3..m-4
+        p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, 64, 0.05, near_radius=bad)
+        assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
     assert lib.aim_filter(None, 1.0) == aim.AIM_E_ARG
     assert lib.aim_matvec(None, 0, 1, None, None) == aim.AIM_E_ARG
 
