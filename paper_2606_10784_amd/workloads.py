@@ -104,6 +104,21 @@ def random_star(rng: np.random.Generator, a: float, n: int, mmax: int = 8,
     return equal_arc_polygon(r, dr, n)
 
 
+def irregular_polygon(rng: np.random.Generator, a: float, n: int, depth: float = 0.35,
+                      modes: int = 5, jitter: float = 0.45) -> np.ndarray:
+    """A simple, star-shaped, generally non-convex CCW polygon with unequal
+    segments: vertex angles theta_i = 2 pi (i + u_i) / n with u_i ~ U(-jitter,
+    jitter), radii r = a (1 + sum_m c_m cos(m theta + phi_m)) with
+    sum |c_m| <= depth < 1, so r > 0 and the sorted angles give a simple polygon."""
+    th = 2.0 * np.pi * (np.arange(n) + rng.uniform(-jitter, jitter, size=n)) / n
+    c = rng.uniform(0.0, 1.0, size=modes)
+    c *= depth / max(c.sum(), 1e-300)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=modes)
+    mm = np.arange(1, modes + 1)[:, None]
+    r = a * (1.0 + np.sum(c[:, None] * np.cos(mm * th[None, :] + ph[:, None]), axis=0))
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
 # --------------------------------------------------------------------------
 # workload configurations
 # --------------------------------------------------------------------------
