@@ -92,3 +92,44 @@ def _term_scale(orc, op, X):
         return max(np.max(np.abs(orc.gram_inv(outer(orc.gram_inv(t)))))
                    for t in (orc.op_N(X, near=False), orc.near_apply("N", X)))
     return 0.0
+
+
+SOLVE_CASES = [c for c in CASES if c[0] in (3, 4, 8, 9)]
+
+
+@pytest.mark.parametrize("case", SOLVE_CASES, ids=[f"g{c[0]}_{'hat' if c[2] else 'pulse'}_N{c[3].shape[0]}"
+                                                    for c in SOLVE_CASES])
+def test_irregular_polygon_solves(case):
+    """GMRES on the irregular polygons: TM EFIE (pulses; FP64 and mixed) and
+    the unfiltered TE Calderon system (hats) against a direct solve of the
+    oracle's operator, assembled column by column.  The residual of the
+    returned current under the oracle's operator meets the tolerance, and
+    the current is within cond(A) tol of the direct solution."""
+    from oracle import excitation
+    i, m, basis, xy, k, quad, radius, _ = case
+    n = xy.shape[0]
+    print(f"irregular polygon solve {i}: m={m} basis={basis} N={n}", flush=True)
+    ctx = aim.Context(xy, k, wl.ETA0, basis, m, EPS, quad=quad, near_radius=radius, precision=aim.AIM_MIXED)
+    orc = oaim.AimOracle(xy, k, wl.ETA0, basis, m, EPS, p=quad, near_radius=radius)
+    if basis == 0:
+        form, b = "TM", excitation.rhs_tm(xy, 0, k, 0.7, p=quad)
+        sys_b = b
+    else:
+        form, b = "TE_CP_UNF", excitation.rhs_te(xy, 1, k, wl.ETA0, 0.7, p=quad)
+        sys_b = orc.gram_inv(orc.op_S(orc.gram_inv(b)))
+    A = orc.apply(form, np.eye(n, dtype=complex))
+    x_dir = np.linalg.solve(A, sys_b)
+    kappa = np.linalg.cond(A)
+    bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
+    for prec, tol in ((aim.AIM_FP64, 1e-10), (aim.AIM_MIXED, 1e-8)):
+        if basis == 1 and prec == aim.AIM_MIXED:
+            continue
+        x, info = ctx.solve(form, bt, tol=tol, maxit=2000, restart=200, precision=prec)
+        xs = x.cpu().numpy()
+        res = np.linalg.norm(sys_b - A @ xs) / np.linalg.norm(sys_b)
+        err = np.linalg.norm(xs - x_dir) / np.linalg.norm(x_dir)
+        print(f"{form} prec={prec} steps={info[0]['iterations']} resid={res:.2e} err={err:.2e} cond={kappa:.1e}",
+              flush=True)
+        assert info[0]["converged"] == 1
+        assert res < 1.5 * tol
+        assert err < 2.0 * kappa * tol
