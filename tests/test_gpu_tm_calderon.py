@@ -35,7 +35,9 @@ def _cols(x):
 
 
 CASES = [("circle40", wl.circle(0.5, 40), 0.05),       # T^-1 over all N offsets
-         ("star96", wl.star5(1.0, 96), 0.08)]          # banded T^-1
+         ("star96", wl.star5(1.0, 96), 0.08),          # banded T^-1
+         # unequal segments (ratios up to ~4) on a non-convex contour
+         ("irregular48", wl.irregular_polygon(np.random.default_rng(48), 0.5, 48, depth=0.2, jitter=0.25), 0.05)]
 
 
 @pytest.mark.parametrize("name,xy,eps", CASES, ids=[c[0] for c in CASES])
