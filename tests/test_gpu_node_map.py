@@ -142,3 +142,32 @@ def test_node_map_fig2_follows_the_analytic_filter(paper_node):
     assert dNB.max() < 0.25 * gN.max()
     above = NUS >= 1.2 * ALPHAP
     assert np.max(np.abs(lN[above])) < 1e-6 * np.abs(lN[0])
+
+
+@pytest.mark.parametrize("basis,order", [(0, 6), (1, 10)])
+def test_node_map_irregular_polygon(basis, order):
+    """Per-node stencils on a non-convex contour with unequal segments
+    (0.18 to 1.6 times the mean, 1.1 to 9.9 grid steps): nodes of one basis fall in cells
+    spread over several stencil widths, so the union rows differ in length."""
+    xy = wl.irregular_polygon(np.random.default_rng(40), 0.5, 40)
+    h = np.linalg.norm(np.roll(xy, -1, axis=0) - xy, axis=1)
+    eps = float(np.mean(h)) / 6.24
+    m = wl.grid_side_for(xy, eps, margin_cells=8)
+    alpha = 8 * K
+    print(f"node map irregular basis={basis} P={order} m={m} h/eps {h.min() / eps:.2f}-{h.max() / eps:.2f}",
+          flush=True)
+    ctx = aim.Context(xy, K, wl.ETA0, basis, m, eps, precision=aim.AIM_MIXED, max_rhs=2, node_order=order)
+    ctx.filter(alpha)
+    orc = oaim.AimOracle(xy, K, wl.ETA0, basis, m, eps, alpha=alpha, node_order=order)
+    assert ctx.info()["map_points"] == orc.W['phi'].shape[1] and ctx.info()["n_active"] == orc.act.size
+    x = np.random.default_rng(12).standard_normal((40, 2)) + 1j * np.random.default_rng(13).standard_normal((40, 2))
+    xt = torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+    for op in ("S_ALPHA",) + (("N_ALPHA",) if basis == 1 else ()):
+        ref = orc.apply(op, x)
+        y = ctx.matvec(op, xt).cpu().numpy().T
+        yf = ctx.matvec(aim.OPS[op] | aim.AIM_OP_GRID_FP32, xt).cpu().numpy().T
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        errf = np.max(np.abs(yf - ref)) / np.max(np.abs(ref))
+        print(op, "fp64", err, "fp32 grid", errf)
+        assert err < 1e-12
+        assert errf < 1e-5
