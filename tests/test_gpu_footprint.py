@@ -33,10 +33,16 @@ def _cases():
         out.append((r.xy, r.k, r.eta, 0, r.m, r.eps, r.precision, len(r.phis), 0))
     out.append((wl.circle(2.0, 4096), wl.K0, wl.ETA0, 0, 256, 1 / 40, 1, 1, 1))
     out.append((wl.star5(2.0, 2048), wl.K0, wl.ETA0, 1, 256, 1 / 40, 0, 2, 0))
+    # non-convex contours with unequal segments: near pairs per basis vary
+    # along the contour (55 on average, up to 79, against the bound's 74)
+    irr = wl.irregular_polygon(np.random.default_rng(7), 2.0, 2048)
+    out.append((irr, wl.K0, wl.ETA0, 0, 256, 1 / 40, 0, 1, 0))
+    out.append((wl.irregular_polygon(np.random.default_rng(9), 2.0, 4096, depth=0.2), wl.K0, wl.ETA0, 1, 256,
+                1 / 40, 1, 3, 0))
     return out
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_footprint_bounds_device_bytes(case):
     xy, k, eta, basis, m, eps, prec, R, dual = _cases()[case]
     restart = 120
