@@ -17,7 +17,11 @@ operator of eq. (2); its sign is fixed by the circle eigenvalue
 
 Quadrature (eq. (7) is "to be understood in a formal sense" for the singular
 entries; here they are integrated properly):
-  * disjoint segments: tensor Gauss-Legendre with p points per segment;
+  * disjoint segments: tensor Gauss-Legendre with p points per segment; a
+    pair closer than half its longer length is first split recursively (the
+    longer piece halved) until every piece pair is at least half its longer
+    piece length apart, so the nearly singular kernel stays resolved next to
+    a short segment;
   * identical segments: with delta = |tau - sigma| the double integral
     collapses to int_0^1 g(h delta) Q_uv(delta) d delta, Q_uv a polynomial.
     g = -(1/2pi) J0(kR) ln R + F(R); the J0 ln part is integrated exactly
@@ -27,11 +31,19 @@ entries; here they are integrated properly):
   * segments sharing a vertex: polar coordinates (rho, psi) about the shared
     vertex; the rho integral of rho^q (ln rho + ln r(psi)) is exact term by
     term, psi by Gauss-Legendre on the two sub-ranges split at the rectangle
-    diagonal; F by tensor Gauss-Legendre.
+    diagonal; F by tensor Gauss-Legendre.  At an acute vertex the two
+    segments fold towards each other and ln r(psi) is nearly singular at
+    psi = pi/4 (r^2 = 1 - c + 2 c t^2 + ..., t = psi - pi/4, c the cosine of
+    the vertex angle), with complex poles at t = +-i delta,
+    delta = sqrt((1 - c) / (2 c)); the psi panels are then graded towards
+    pi/4 at pi/4 +- delta 2^j.
 
-Pinned by: tests/test_oracle_galerkin.py (self/adjacent moments vs mpmath
-adaptive quadrature, circle eigenvalues of S and N, Calderon S*N -> 1/4,
-symmetry S = S^T, N = N^T, Gram closed form vs quadrature).
+Pinned by: tests/test_oracle_galerkin.py (self, adjacent and close disjoint
+moments vs adaptive QUADPACK, with the logarithm taken by QUADPACK's
+log-weighted rule, over k h up to 2 pi, unequal lengths, acute vertices and
+gaps down to 1/50 of the segment length; circle eigenvalues of S and N,
+Calderon S*N -> 1/4, symmetry S = S^T, N = N^T, Gram closed form vs
+quadrature).
 """
 from __future__ import annotations
 
@@ -48,9 +60,79 @@ TWO_PI = 2.0 * math.pi
 # --------------------------------------------------------------------------
 # segment-pair moments
 # --------------------------------------------------------------------------
+def _seg_dist(P0, P1, Q0, Q1):
+    """Distance between two segments that do not cross: the smallest of the
+    four endpoint-to-segment distances."""
+    def pt(P, A, B):
+        d = B - A
+        L2 = float(d @ d)
+        t = 0.0 if L2 == 0.0 else min(1.0, max(0.0, float((P - A) @ d) / L2))
+        return float(np.hypot(*(P - (A + t * d))))
+    return min(pt(P0, Q0, Q1), pt(P1, Q0, Q1), pt(Q0, P0, P1), pt(Q1, P0, P1))
+
+
+def _seg_dist_arr(P0, P1, Q0, Q1):
+    """_seg_dist for arrays of segment pairs, (P, 2) each."""
+    def pt(P, A, B):
+        d = B - A
+        L2 = np.sum(d * d, axis=1)
+        t = np.clip(np.sum((P - A) * d, axis=1) / np.where(L2 > 0, L2, 1.0), 0.0, 1.0)
+        e = P - (A + t[:, None] * d)
+        return np.hypot(e[:, 0], e[:, 1])
+    return np.minimum(np.minimum(pt(P0, Q0, Q1), pt(P1, Q0, Q1)), np.minimum(pt(Q0, P0, P1), pt(Q1, P0, P1)))
+
+
+def disjoint_pieces(A0, A1, B0, B1, eta=0.5, max_depth=40):
+    """Parameter boxes (t0, t1, s0, s1) covering [0, 1]^2 for a pair of
+    disjoint segments: a box whose pieces lie closer than eta times the
+    longer piece length is split by halving its longer piece."""
+    A0, A1, B0, B1 = (np.asarray(v, dtype=float) for v in (A0, A1, B0, B1))
+    ha = float(np.hypot(*(A1 - A0)))
+    hb = float(np.hypot(*(B1 - B0)))
+    out = []
+    stack = [(0.0, 1.0, 0.0, 1.0, 0)]
+    while stack:
+        t0, t1, s0, s1, dep = stack.pop()
+        la, lb = ha * (t1 - t0), hb * (s1 - s0)
+        d = _seg_dist(A0 + (A1 - A0) * t0, A0 + (A1 - A0) * t1, B0 + (B1 - B0) * s0, B0 + (B1 - B0) * s1)
+        if d >= eta * max(la, lb) or dep >= max_depth:
+            out.append((t0, t1, s0, s1))
+        elif la >= lb:
+            tm = 0.5 * (t0 + t1)
+            stack += [(tm, t1, s0, s1, dep + 1), (t0, tm, s0, s1, dep + 1)]
+        else:
+            sm = 0.5 * (s0 + s1)
+            stack += [(t0, t1, sm, s1, dep + 1), (t0, t1, s0, sm, dep + 1)]
+    return out
+
+
+def _moments_boxes(A0, A1, B0, B1, k, p, boxes):
+    """Tensor Gauss-Legendre moments of one segment pair summed over
+    parameter boxes (t0, t1, s0, s1), (2, 2) complex."""
+    x, w = gauss_legendre01(p)
+    bx = np.asarray(boxes, dtype=float)
+    tau = bx[:, 0:1] + (bx[:, 1:2] - bx[:, 0:1]) * x[None, :]        # (nb, p)
+    sig = bx[:, 2:3] + (bx[:, 3:4] - bx[:, 2:3]) * x[None, :]
+    wt = (bx[:, 1:2] - bx[:, 0:1]) * w[None, :]
+    ws = (bx[:, 3:4] - bx[:, 2:3]) * w[None, :]
+    ra = A0[None, None, :] + (A1 - A0)[None, None, :] * tau[..., None]   # (nb, p, 2)
+    rb = B0[None, None, :] + (B1 - B0)[None, None, :] * sig[..., None]
+    d = ra[:, :, None, :] - rb[:, None, :, :]
+    G = green(np.hypot(d[..., 0], d[..., 1]), k) * wt[:, :, None] * ws[:, None, :]
+    f = float(np.hypot(*(A1 - A0)) * np.hypot(*(B1 - B0)))
+    out = np.empty((2, 2), dtype=complex)
+    out[0, 0] = G.sum() * f
+    out[1, 0] = np.einsum('bij,bi->', G, tau) * f
+    out[0, 1] = np.einsum('bij,bj->', G, sig) * f
+    out[1, 1] = np.einsum('bij,bi,bj->', G, tau, sig) * f
+    return out
+
+
 def _moments_disjoint(A0, A1, B0, B1, k, p):
-    """Tensor Gauss-Legendre moments for arrays of segment pairs.
-    A0, A1, B0, B1: (P, 2).  Returns (P, 2, 2) complex."""
+    """Tensor Gauss-Legendre moments for arrays of disjoint segment pairs.
+    A0, A1, B0, B1: (P, 2).  Returns (P, 2, 2) complex.  Pairs closer than
+    half their longer length are integrated over the boxes of
+    disjoint_pieces."""
     tau, w = gauss_legendre01(p)
     ha = np.hypot(*(A1 - A0).T)
     hb = np.hypot(*(B1 - B0).T)
@@ -68,6 +150,8 @@ def _moments_disjoint(A0, A1, B0, B1, k, p):
         out[e, 1, 0] = np.einsum('cij,i->c', G, tau) * f[:, 0, 0]
         out[e, 0, 1] = np.einsum('cij,j->c', G, tau) * f[:, 0, 0]
         out[e, 1, 1] = np.einsum('cij,i,j->c', G, tau, tau) * f[:, 0, 0]
+    for i in np.nonzero(_seg_dist_arr(A0, A1, B0, B1) < 0.5 * np.maximum(ha, hb))[0]:
+        out[i] = _moments_boxes(A0[i], A1[i], B0[i], B1[i], k, p, disjoint_pieces(A0[i], A1[i], B0[i], B1[i]))
     return out
 
 
@@ -102,6 +186,37 @@ def moments_self(h, k, nq=24, nterms=24):
     return out
 
 
+def psi_panels(psid, cab):
+    """Panels of the polar angle psi in [0, pi/2] about a shared vertex:
+    split at the rectangle diagonal psid = atan(h_b / h_a).  Beyond it the
+    radial limit h_b / sin(psi) has its pole at psi = 0, before it h_a /
+    cos(psi) at pi/2: for unequal lengths the panels are graded away from
+    psid at psid 2^j and pi/2 - (pi/2 - psid) 2^j.  At an acute vertex
+    (cab > 0, the cosine of the angle between the two segments) also at pi/4
+    and at pi/4 +- delta 2^j, delta = sqrt((1 - cab) / (2 cab)), the distance
+    of the complex poles of ln r(psi) from the real axis."""
+    q = 0.25 * math.pi
+    bps = {0.0, psid, 0.5 * math.pi}
+    j = 1
+    while psid * 2.0 ** j < 0.5 * math.pi and j < 48:
+        bps.add(psid * 2.0 ** j)
+        j += 1
+    j = 1
+    while 0.5 * math.pi - (0.5 * math.pi - psid) * 2.0 ** j > 0.0 and j < 48:
+        bps.add(0.5 * math.pi - (0.5 * math.pi - psid) * 2.0 ** j)
+        j += 1
+    if cab > 0.0:
+        delta = max(math.sqrt(max(1.0 - cab, 0.0) / (2.0 * cab)), 1e-12)
+        bps.add(q)
+        j = 0
+        while delta * 2.0 ** j < q and j < 48:
+            bps.add(q - delta * 2.0 ** j)
+            bps.add(q + delta * 2.0 ** j)
+            j += 1
+    bps = sorted(bps)
+    return [(a, b) for a, b in zip(bps[:-1], bps[1:]) if b > a]
+
+
 def moments_adjacent(A0, A1, B0, B1, k, nq=32, nterms=24, pf=16):
     """Moments M_uv for two segments sharing exactly one vertex.
 
@@ -134,10 +249,11 @@ def moments_adjacent(A0, A1, B0, B1, k, nq=32, nterms=24, pf=16):
     cm = j0_series_coeffs(k, nterms)
     psid = math.atan2(hb, ha)
     out = np.empty((2, 2), dtype=complex)
-    # psi quadrature on [0, psid] and [psid, pi/2]
+    # psi quadrature on [0, psid] and [psid, pi/2], each graded towards
+    # pi/4 at an acute vertex
     xg, wg = gauss_legendre01(nq)
-    segs = [(0.0, psid, lambda ps: ha / np.cos(ps)),
-            (psid, 0.5 * math.pi, lambda ps: hb / np.sin(ps))]
+    segs = [(lo, hi, (lambda ps: ha / np.cos(ps)) if hi <= psid else (lambda ps: hb / np.sin(ps)))
+            for lo, hi in psi_panels(psid, cab)]
     # smooth part: tensor GL on the rectangle in (s, s')
     xs, ws = gauss_legendre01(pf)
     S, Sp = np.meshgrid(xs * ha, xs * hb, indexing='ij')

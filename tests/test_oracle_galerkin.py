@@ -57,6 +57,119 @@ def test_adjacent_moments_vs_adaptive_quadrature(uv):
     assert np.max(np.abs(Mt - M.T)) < 1e-15 * np.max(np.abs(M)) * 10
 
 
+# --------------------------------------------------------------------------
+# references with the logarithm taken by QUADPACK's log-weighted rule (QAWS),
+# the Bessel functions by SciPy: valid over the whole accepted range k h <= 2 pi
+# --------------------------------------------------------------------------
+_EG = 0.57721566490153286060651209
+
+
+def _F(R):
+    """g(R) + (1/2 pi) J0(kR) ln R from SciPy's Hankel function."""
+    if R == 0.0:
+        return -0.25j - (math.log(K / 2.0) + _EG) / (2.0 * math.pi)
+    return _g(R) + special.j0(K * R) * math.log(R) / (2.0 * math.pi)
+
+
+def _q(f, a, b, **kw):
+    return integrate.quad(f, a, b, epsabs=1e-17, epsrel=2e-14, limit=400, **kw)[0]
+
+
+def _cq(f, a, b, **kw):
+    return _q(lambda x: f(x).real, a, b, **kw) + 1j * _q(lambda x: f(x).imag, a, b, **kw)
+
+
+def _self_ref(h, u, v):
+    """h^2 int_0^1 tau^u int_0^1 g(h |tau - sigma|) sigma^v dsigma dtau, the
+    inner integral split at sigma = tau with ln|tau - sigma| as the weight."""
+    def inner(t):
+        flog = lambda s: -special.j0(K * h * abs(t - s)) / (2.0 * math.pi) * s ** v
+        r = 0.0
+        if t < 1.0:
+            r += _q(flog, t, 1.0, weight='alg-loga', wvar=(0, 0))
+        if t > 0.0:
+            r += _q(flog, 0.0, t, weight='alg-logb', wvar=(0, 0))
+        rest = lambda s: (-special.j0(K * h * abs(t - s)) * math.log(h) / (2.0 * math.pi)
+                          + _F(h * abs(t - s))) * s ** v
+        return (r + _cq(rest, 0.0, 1.0, points=[t])) * t ** u
+    return h * h * _cq(inner, 0.0, 1.0)
+
+
+def _adjacent_ref(A0, V, B1, u, v):
+    """Moments of segments A0 -> V and V -> B1 (tau along the first, sigma
+    along the second) in polar coordinates about V: s = rho cos psi along the
+    first segment, s' = rho sin psi along the second, R = rho r(psi); the
+    rho integral with ln rho as the weight, psi adaptive."""
+    A0, V, B1 = (np.asarray(p, float) for p in (A0, V, B1))
+    ha, hb = np.linalg.norm(A0 - V), np.linalg.norm(B1 - V)
+    cab = float((A0 - V) @ (B1 - V)) / (ha * hb)
+    psid = math.atan2(hb, ha)
+
+    def radial(ps):
+        c, s = math.cos(ps), math.sin(ps)
+        r = math.sqrt(1.0 - 2.0 * c * s * cab)
+        pm = min(ha / c if c > 0 else np.inf, hb / s if s > 0 else np.inf)
+        poly = lambda rho: (1.0 - rho * c / ha) ** u * (rho * s / hb) ** v * rho
+        flog = lambda rho: -special.j0(K * rho * r) / (2.0 * math.pi) * poly(rho)
+        rest = lambda rho: (-special.j0(K * rho * r) * math.log(r) / (2.0 * math.pi) + _F(rho * r)) * poly(rho)
+        return _q(flog, 0.0, pm, weight='alg-loga', wvar=(0, 0)) + _cq(rest, 0.0, pm)
+    pts = [0.25 * math.pi] if 0.0 < 0.25 * math.pi < psid else None
+    pts2 = [0.25 * math.pi] if psid < 0.25 * math.pi else None
+    return _cq(radial, 0.0, psid, points=pts) + _cq(radial, psid, 0.5 * math.pi, points=pts2)
+
+
+@pytest.mark.parametrize("kh", [math.pi, 2.0 * math.pi])
+@pytest.mark.parametrize("uv", [(0, 0), (1, 0), (1, 1)])
+def test_self_moments_full_range(kh, uv):
+    """Self moments up to the longest segment aim_setup accepts (k h = 2 pi)."""
+    h = kh / K
+    M = galerkin.moments_self(h, K)
+    assert abs(M[uv] - _self_ref(h, *uv)) < 1e-12 * np.max(np.abs(M))
+
+
+def _ray(V, L, ang):
+    return [V[0] + L * math.cos(ang), V[1] + L * math.sin(ang)]
+
+
+# (length of the first segment, length of the second, direction of the second
+# segment relative to the continuation of the first): straight-ish, unequal
+# lengths at the longest accepted segment, acute vertices down to 0.05 rad
+_ADJ_CASES = [
+    (1.0, 0.5, 0.4),                  # k h = 2 pi and pi, gentle bend
+    (1.0, 0.05, 1.2),                 # length ratio 20
+    (0.5, 0.1, math.pi - 0.2),        # acute vertex: 0.2 rad between the segments
+    (1.0, 1.0, math.pi - 0.05),       # k h = 2 pi, 0.05 rad between the segments
+    (0.05, 0.5, -(math.pi - 0.3)),    # acute, clockwise, short first segment
+]
+
+
+@pytest.mark.parametrize("case", range(len(_ADJ_CASES)))
+def test_adjacent_moments_full_range(case):
+    ha, hb, turn = _ADJ_CASES[case]
+    A0, V = [0.0, 0.0], [ha, 0.0]
+    B1 = _ray(V, hb, turn)
+    M = galerkin.moments_adjacent(A0, V, V, B1, K)
+    for uv in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        assert abs(M[uv] - _adjacent_ref(A0, V, B1, *uv)) < 1e-12 * np.max(np.abs(M)), uv
+
+
+@pytest.mark.parametrize("gap,turn", [(0.1, 0.0), (0.02, 0.0), (0.02, 0.6)])
+def test_close_disjoint_moments(gap, turn):
+    """Segments a and a+2 around a short middle segment (gap / h down to
+    1/50): the nearly singular kernel needs the recursive subdivision."""
+    A0, A1 = np.array([-1.0, 0.0]), np.array([0.0, 0.0])
+    B0 = A1 + gap * np.array([math.cos(turn), math.sin(turn)])
+    B1 = B0 + np.array([math.cos(2 * turn), math.sin(2 * turn)])
+    pairs = np.array([[0, 2]])
+    xy = np.array([A0, A1, B0, B1, [0.0, -1.0]])
+    M = galerkin.segment_pair_moments(xy, pairs, K)[0]
+    assert len(galerkin.disjoint_pieces(A0, A1, B0, B1)) > 1
+    for u in (0, 1):
+        for v in (0, 1):
+            ref = _brute_pair(A0, A1, B0, B1, u, v)
+            assert abs(M[u, v] - ref) < 1e-12 * np.max(np.abs(M)), (u, v)
+
+
 def _circle_eigs(N, basis, op, ns, a=1.0):
     xy = wl.circle(a, N)
     pairs = np.stack([np.zeros(N, int), np.arange(N)], 1)
