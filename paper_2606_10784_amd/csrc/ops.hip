@@ -250,6 +250,49 @@ __device__ void moments_self(const NearGeo& G, double h, double2 M[2][2]) {
   M[1][1] = make_double2(hh * (-kInv2Pi * L11 + F11.x), hh * F11.y);
 }
 
+// Breakpoints (sorted, distinct) of the polar-angle panels about a shared
+// vertex, psi in [0, pi/2]: the rectangle diagonal psid = atan(h_b / h_a);
+// geometric grading away from it towards the poles of the radial limits
+// (h_b / sin psi at 0, used beyond psid: psid 2^j; h_a / cos psi at pi/2,
+// before psid: pi/2 - (pi/2 - psid) 2^j); and at an acute vertex (cab > 0)
+// pi/4 and pi/4 +- delta 2^j, where ln r(psi), r^2 = 1 - sin(2 psi) cab, has
+// complex poles at distance delta = sqrt((1 - cab) / (2 cab)).
+static constexpr int kMaxPsiBreaks = 128;
+__device__ int psi_breaks(double psid, double cab, double* bp) {
+  const double hp = 0.5 * kPi, q = 0.25 * kPi;
+  int n = 0;
+  auto add = [&](double v) {
+    if (!(v > 0.0 && v < hp) || n >= kMaxPsiBreaks - 2) return;
+    int i = n;
+    while (i > 0 && bp[i - 1] > v) {
+      bp[i] = bp[i - 1];
+      --i;
+    }
+    if (i > 0 && bp[i - 1] == v) {   // already present: undo the shift
+      for (int k = i; k < n; ++k) bp[k] = bp[k + 1];
+      return;
+    }
+    bp[i] = v;
+    ++n;
+  };
+  add(psid);
+  for (int j = 1; j < 48 && psid * exp2((double)j) < hp; ++j) add(psid * exp2((double)j));
+  for (int j = 1; j < 48 && hp - (hp - psid) * exp2((double)j) > 0.0; ++j) add(hp - (hp - psid) * exp2((double)j));
+  if (cab > 0.0) {
+    const double delta = fmax(sqrt(fmax(1.0 - cab, 0.0) / (2.0 * cab)), 1e-12);
+    add(q);
+    for (int j = 0; j < 48 && delta * exp2((double)j) < q; ++j) {
+      add(q - delta * exp2((double)j));
+      add(q + delta * exp2((double)j));
+    }
+  }
+  // ends
+  for (int k = n; k > 0; --k) bp[k] = bp[k - 1];
+  bp[0] = 0.0;
+  bp[n + 1] = hp;
+  return n + 2;
+}
+
 // segments a and b share a vertex; a_first: a ends where b starts
 __device__ void moments_adjacent(const NearGeo& G, int a, int b, bool a_first, double2 M[2][2]) {
   const int N = G.N;
@@ -273,13 +316,17 @@ __device__ void moments_adjacent(const NearGeo& G, int a, int b, bool a_first, d
   const double ebx = (Pbx - Vx) / hb, eby = (Pby - Vy) / hb;
   const double cab = eax * ebx + eay * eby;
   const double k = G.k;
-  // polar log part: B_ij = int int J0(kR) ln R s^i s'^j ds ds'
+  // polar log part: B_ij = int int J0(kR) ln R s^i s'^j ds ds', psi over
+  // the graded panels of psi_breaks
   double B[2][2] = {{0, 0}, {0, 0}};
   const double* x32 = G.gl + 80;
   const double* w32 = G.gl + 112;
   const double psid = atan2(hb, ha);
-  for (int half = 0; half < 2; ++half) {
-    const double lo = half ? psid : 0.0, hi = half ? 0.5 * kPi : psid;
+  double bp[kMaxPsiBreaks];
+  const int nbp = psi_breaks(psid, cab, bp);
+  for (int pnl = 0; pnl + 1 < nbp; ++pnl) {
+    const double lo = bp[pnl], hi = bp[pnl + 1];
+    const bool upper = lo >= psid;   // radial limit h_b / sin(psi) beyond the diagonal
     const double len = hi - lo;
     for (int q = 0; q < 32; ++q) {
       const double ps = lo + len * x32[q];
@@ -288,7 +335,7 @@ __device__ void moments_adjacent(const NearGeo& G, int a, int b, bool a_first, d
       sincos(ps, &sp, &cp);
       const double r2 = 1.0 - 2.0 * cp * sp * cab;
       const double lnr = 0.5 * log(r2);
-      const double P = half ? hb / sp : ha / cp;
+      const double P = upper ? hb / sp : ha / cp;
       const double lnP = log(P);
       const double zz = 0.25 * k * k * r2 * P * P;
       // sum over m for total degree d = i + j in {0,1,2}
@@ -345,35 +392,83 @@ __device__ void moments_adjacent(const NearGeo& G, int a, int b, bool a_first, d
     }
 }
 
+// distance between two segments that do not cross: the smallest of the
+// four endpoint-to-segment distances
+__device__ double pt_seg_dist(double px, double py, double ax, double ay, double bx, double by) {
+  const double dx = bx - ax, dy = by - ay;
+  const double L2 = dx * dx + dy * dy;
+  const double t = L2 > 0.0 ? fmin(1.0, fmax(0.0, ((px - ax) * dx + (py - ay) * dy) / L2)) : 0.0;
+  const double ex = px - (ax + t * dx), ey = py - (ay + t * dy);
+  return sqrt(ex * ex + ey * ey);
+}
+__device__ double seg_seg_dist(double p0x, double p0y, double p1x, double p1y, double q0x, double q0y, double q1x,
+                               double q1y) {
+  return fmin(fmin(pt_seg_dist(p0x, p0y, q0x, q0y, q1x, q1y), pt_seg_dist(p1x, p1y, q0x, q0y, q1x, q1y)),
+              fmin(pt_seg_dist(q0x, q0y, p0x, p0y, p1x, p1y), pt_seg_dist(q1x, q1y, p0x, p0y, p1x, p1y)));
+}
+
+// Disjoint segments: 16 x 16 Gauss-Legendre over parameter boxes
+// [t0, t1] x [s0, s1] of the unit square.  A box whose two pieces lie closer
+// than half the longer piece is split by halving the longer piece (depth at
+// most 40), so next to a short segment the nearly singular kernel is still
+// resolved; distant pairs are one box.
 __device__ void moments_disjoint(const NearGeo& G, int a, int b, double2 M[2][2]) {
   const int N = G.N;
   const int a1 = (a + 1) % N, b1 = (b + 1) % N;
   const double ax = G.vx[a], ay = G.vy[a], adx = G.vx[a1] - ax, ady = G.vy[a1] - ay;
   const double bx = G.vx[b], by = G.vy[b], bdx = G.vx[b1] - bx, bdy = G.vy[b1] - by;
+  const double ha = G.h[a], hb = G.h[b];
   const double* x16 = G.gl;
   const double* w16 = G.gl + 16;
   double2 acc[2][2];
   for (int u = 0; u < 2; ++u)
     for (int v = 0; v < 2; ++v) acc[u][v] = make_double2(0, 0);
-  for (int i = 0; i < 16; ++i) {
-    const double ti = x16[i];
-    const double px = ax + adx * ti, py = ay + ady * ti;
-    double2 r0 = make_double2(0, 0), r1 = make_double2(0, 0);
-    for (int j = 0; j < 16; ++j) {
-      const double sj = x16[j];
-      const double dx = px - (bx + bdx * sj), dy = py - (by + bdy * sj);
-      const double2 g = green(sqrt(dx * dx + dy * dy), G.k);
-      const double w = w16[j];
-      r0.x += w * g.x; r0.y += w * g.y;
-      r1.x += w * sj * g.x; r1.y += w * sj * g.y;
+  constexpr int kStack = 48;
+  double st[kStack][4];
+  int dep[kStack];
+  int top = 0;
+  st[0][0] = 0.0; st[0][1] = 1.0; st[0][2] = 0.0; st[0][3] = 1.0;
+  dep[0] = 0;
+  top = 1;
+  while (top > 0) {
+    --top;
+    const double t0 = st[top][0], t1 = st[top][1], s0 = st[top][2], s1 = st[top][3];
+    const int d = dep[top];
+    const double la = ha * (t1 - t0), lb = hb * (s1 - s0);
+    const double dist = seg_seg_dist(ax + adx * t0, ay + ady * t0, ax + adx * t1, ay + ady * t1, bx + bdx * s0,
+                                     by + bdy * s0, bx + bdx * s1, by + bdy * s1);
+    if (!(dist >= 0.5 * fmax(la, lb) || d >= 40 || top + 2 > kStack)) {
+      // split the longer piece; the first half is taken next
+      const bool sa = la >= lb;
+      const double m = sa ? 0.5 * (t0 + t1) : 0.5 * (s0 + s1);
+      st[top][0] = sa ? m : t0; st[top][1] = t1; st[top][2] = sa ? s0 : m; st[top][3] = s1;
+      dep[top] = d + 1;
+      st[top + 1][0] = t0; st[top + 1][1] = sa ? m : t1; st[top + 1][2] = s0; st[top + 1][3] = sa ? s1 : m;
+      dep[top + 1] = d + 1;
+      top += 2;
+      continue;
     }
-    const double wi = w16[i];
-    acc[0][0].x += wi * r0.x; acc[0][0].y += wi * r0.y;
-    acc[0][1].x += wi * r1.x; acc[0][1].y += wi * r1.y;
-    acc[1][0].x += wi * ti * r0.x; acc[1][0].y += wi * ti * r0.y;
-    acc[1][1].x += wi * ti * r1.x; acc[1][1].y += wi * ti * r1.y;
+    const double wt = t1 - t0, ws = s1 - s0;
+    for (int i = 0; i < 16; ++i) {
+      const double ti = t0 + wt * x16[i];
+      const double px = ax + adx * ti, py = ay + ady * ti;
+      double2 r0 = make_double2(0, 0), r1 = make_double2(0, 0);
+      for (int j = 0; j < 16; ++j) {
+        const double sj = s0 + ws * x16[j];
+        const double dx = px - (bx + bdx * sj), dy = py - (by + bdy * sj);
+        const double2 g = green(sqrt(dx * dx + dy * dy), G.k);
+        const double w = ws * w16[j];
+        r0.x += w * g.x; r0.y += w * g.y;
+        r1.x += w * sj * g.x; r1.y += w * sj * g.y;
+      }
+      const double wi = wt * w16[i];
+      acc[0][0].x += wi * r0.x; acc[0][0].y += wi * r0.y;
+      acc[0][1].x += wi * r1.x; acc[0][1].y += wi * r1.y;
+      acc[1][0].x += wi * ti * r0.x; acc[1][0].y += wi * ti * r0.y;
+      acc[1][1].x += wi * ti * r1.x; acc[1][1].y += wi * ti * r1.y;
+    }
   }
-  const double s = G.h[a] * G.h[b];
+  const double s = ha * hb;
   for (int u = 0; u < 2; ++u)
     for (int v = 0; v < 2; ++v) M[u][v] = make_double2(s * acc[u][v].x, s * acc[u][v].y);
 }
