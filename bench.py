@@ -43,6 +43,7 @@ def parse():
                     help="matvec: set-up plus --matvecs FP64 matvecs only (short runs for counters)")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the serving stream (0: skip the serving measurement)")
+    ap.add_argument("--serve-log-dir", default=None, help="directory of the per-request JSONL logs")
     return ap.parse_args()
 
 
@@ -65,37 +66,58 @@ def measured_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def serving(n_req, slots=4, budget=96 << 30):
-    """Closed-loop capacity of the continuous-batching server on the serving
-    stream, then Poisson arrivals at 0.7 of that capacity."""
+def serving(n_req, slots=4, budget=96 << 30, log_dir=None):
+    """The serving stream through three schedulers: iteration-level batching
+    with grouped column passes (StepServer, aim_solver_step over all running
+    requests: requests that share a grid-kernel spectrum run their column
+    pass as one launch), the same without grouping (one aim_solver_step call
+    per request) and a thread per request (Server).  Each: closed-loop
+    capacity, then Poisson arrivals at fractions of that capacity (0.5, 0.7,
+    0.9 for the grouped scheduler, 0.7 for the others).  Every run writes a
+    JSONL line per request to log_dir."""
     from paper_2606_10784_amd import serve
     from paper_2606_10784_amd import workloads as wl
-    exe = serve.GpuExecutor(restart=1000)
-    reqs = wl.serving_stream(n_req, rate=0.0)
+    import tempfile
+    log_dir = log_dir or tempfile.gettempdir()
+
     def done(what, summ):
         print(f"[bench] serving {what}: {summ['completed']}/{summ['requests']} in {summ['wall_s']:.1f} s, "
-              f"p50 {summ['latency_s']['p50']:.3f} s", file=sys.stderr, flush=True)
+              f"p50 {summ['latency_s']['p50']:.3f} s p99 {summ['latency_s']['p99']:.3f} s",
+              file=sys.stderr, flush=True)
         return summ
 
-    srv = serve.Server(exe, hbm_budget=budget, slots=slots)
-    cap = done("threads closed loop", serve.summarize(srv.run(reqs, realtime=False), srv.wall))
-    rate = 0.7 * cap["requests_per_s"]
-    reqs = wl.serving_stream(n_req, rate=rate)
-    srv = serve.Server(exe, hbm_budget=budget, slots=slots)
-    out = done("threads poisson", serve.summarize(srv.run(reqs, realtime=True), srv.wall))
-    # iteration-level batching: one host thread steps every admitted request's
-    # solver once per round (aim_solver_step), same requests and rate
-    eng = serve.GpuStepEngine(restart=1000)
-    reqs = wl.serving_stream(n_req, rate=0.0)
-    srv = serve.StepServer(eng, hbm_budget=budget, slots=2 * slots)
-    scap = done("steps closed loop", serve.summarize(srv.run(reqs, realtime=False), srv.wall))
-    reqs = wl.serving_stream(n_req, rate=rate)
-    srv = serve.StepServer(eng, hbm_budget=budget, slots=2 * slots)
-    sout = done("steps poisson", serve.summarize(srv.run(reqs, realtime=True), srv.wall))
-    return {"stream": f"{n_req} TM requests, random stars ka~logU[10,400], 1-16 rhs, FP64/mixed, "
-                      f"{slots} slots, HBM budget {budget >> 30} GiB",
-            "closed_loop": cap, "poisson_rate_per_s": rate, "poisson": out,
-            "step_server": {"slots": 2 * slots, "closed_loop": scap, "poisson": sout}}
+    def run(name, make, rate):
+        path = os.path.join(log_dir, f"serve_{name}.jsonl")
+        srv = make(path)
+        reqs = wl.serving_stream(n_req, rate=rate)
+        summ = serve.summarize(srv.run(reqs, realtime=rate > 0), srv.wall)
+        summ["log"] = path
+        if hasattr(srv, "rounds"):
+            summ["rounds"] = srv.rounds
+        return done(name, summ)
+
+    out = {"stream": f"{n_req} TM requests, random stars ka~logU[10,400], 1-16 rhs, FP64/mixed, "
+                     f"HBM budget {budget >> 30} GiB"}
+    grp = serve.GpuStepEngine(restart=1000, group=True)
+    mk = lambda path: serve.StepServer(grp, hbm_budget=budget, slots=2 * slots, log_path=path)
+    cap = run("steps_grouped_closed", mk, 0.0)
+    out["steps_grouped"] = {"slots": 2 * slots, "closed_loop": cap}
+    for f in (0.5, 0.7, 0.9):
+        rate = f * cap["requests_per_s"]
+        out["steps_grouped"][f"poisson_{f}"] = dict(run(f"steps_grouped_poisson_{f}", mk, rate), rate_per_s=rate)
+    solo = serve.GpuStepEngine(restart=1000, group=False)
+    mk = lambda path: serve.StepServer(solo, hbm_budget=budget, slots=2 * slots, log_path=path)
+    cap2 = run("steps_ungrouped_closed", mk, 0.0)
+    rate = 0.7 * cap2["requests_per_s"]
+    out["steps_ungrouped"] = {"slots": 2 * slots, "closed_loop": cap2,
+                              "poisson_0.7": dict(run("steps_ungrouped_poisson_0.7", mk, rate), rate_per_s=rate)}
+    exe = serve.GpuExecutor(restart=1000)
+    mk = lambda path: serve.Server(exe, hbm_budget=budget, slots=slots, log_path=path)
+    cap3 = run("threads_closed", mk, 0.0)
+    rate = 0.7 * cap3["requests_per_s"]
+    out["threads"] = {"slots": slots, "closed_loop": cap3,
+                      "poisson_0.7": dict(run("threads_poisson_0.7", mk, rate), rate_per_s=rate)}
+    return out
 
 
 def kernel_bytes(kid, inf, nch=1, nrhs=1, b=16):
@@ -170,7 +192,7 @@ def star_te(args):
     from paper_2606_10784_amd import aim
     from paper_2606_10784_amd import workloads as wl
     w = wl.star_large()
-    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1)
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1, max_restart=300)
     ctx.filter(w.alpha)
     inf = ctx.info()
     b = ctx.rhs_planewave(0.0)
@@ -210,7 +232,8 @@ def tm_calderon(args):
     from paper_2606_10784_amd import workloads as wl
     w = wl.cylinder_large()
     t0 = time.perf_counter()
-    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1, dual=1)
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1, dual=1,
+                      max_restart=args.restart)
     ctx.filter(w.alpha)
     torch.cuda.synchronize()
     inf = ctx.info()
@@ -258,7 +281,8 @@ def batched_360(args):
     w = wl.cylinder_large()
     R = 360
     phis = np.deg2rad(np.arange(R))
-    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=R)
+    ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=R,
+                      max_restart=args.restart)
     B = ctx.rhs_planewave(phis)
     out = {"workload": w.name + "_360rhs", "nrhs": R, "solves": {}}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -304,7 +328,7 @@ def spectrum(args):
         nus = np.arange(0, N // 2 + 1)
         nmax = N // 2
         t0 = time.perf_counter()
-        ctx = aim.Context(w.xy, w.k, w.eta, basis, w.m, w.eps, quad=w.quad, max_rhs=64, dual=dual)
+        ctx = aim.Context(w.xy, w.k, w.eta, basis, w.m, w.eps, quad=w.quad, max_rhs=64, dual=dual, max_restart=0)
         ctx.filter(w.alpha)
         t_setup = time.perf_counter() - t0
         for op in ops:
@@ -328,7 +352,8 @@ def spectrum(args):
     N = w.n_unknowns
     nus = np.arange(0, N // 2 + 1)
     t0 = time.perf_counter()
-    ctx = aim.Context(w.xy, w.k, w.eta, wl.PULSE, w.m, w.eps, quad=w.quad, max_rhs=64, node_order=10)
+    ctx = aim.Context(w.xy, w.k, w.eta, wl.PULSE, w.m, w.eps, quad=w.quad, max_rhs=64, node_order=10,
+                      max_restart=0)
     ctx.filter(w.alpha)
     t_setup = time.perf_counter() - t0
     inf = ctx.info()
@@ -388,7 +413,7 @@ def main():
     stream = torch.cuda.current_stream()
     t_setup = time.perf_counter()
     ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, quad=w.quad, near_radius=w.near_radius,
-                      precision=aim.AIM_MIXED, max_rhs=1, stream=stream)
+                      precision=aim.AIM_MIXED, max_rhs=1, stream=stream, max_restart=args.restart)
     ctx.filter(w.alpha)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
@@ -545,7 +570,7 @@ def main():
     ctx.close()
     if args.serve_requests > 0:
         print("[bench] serving stream ...", file=sys.stderr, flush=True)
-        out["serving"] = serving(args.serve_requests)
+        out["serving"] = serving(args.serve_requests, log_dir=args.serve_log_dir)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

@@ -19,8 +19,14 @@
  *    N x nrhs (column r starts at element r*N).  All *_dev pointers are HIP
  *    device pointers owned by the caller; *_host pointers are host memory.
  *  - The library owns everything inside an aim_ctx (grid tables, spectra,
- *    near field, work buffers); it allocates only in aim_setup / aim_solve
- *    set-up, never inside aim_matvec.
+ *    near field, work buffers).  It allocates device memory in aim_setup and
+ *    in the set-up calls aim_filter / aim_filter_analytic (a filtered
+ *    spectrum) and aim_fourier_spectrum (its mode buffers, first call);
+ *    never in aim_matvec, aim_solve, the step-wise solver calls,
+ *    aim_rhs_planewave or aim_rcs_monostatic.  Krylov workspaces are
+ *    caller-owned device memory (aim_params.workspace, the workspace of
+ *    aim_solver_begin) sized by aim_workspace_bytes; the context's own one
+ *    is allocated in aim_setup only when the caller passes none.
  *  - Every call returns an aim_status; on error the outputs are untouched
  *    (except AIM_E_NOCONV, which returns the best iterate and its info).
  *  - Calls are asynchronous on the context's stream except aim_setup, the
@@ -127,6 +133,17 @@ typedef struct {
   int32_t dual;           /* pulse basis only: 1 also sets up the dual hat space
                              of the TM Calderon operators (a hat context on the
                              refined polygon, 2N vertices, same grid)           */
+  int32_t max_restart;    /* longest restart aim_solve accepts on this context
+                             (0..1000): its Krylov workspace, for max_rhs
+                             right-hand sides, is bound in aim_setup.  0: no
+                             aim_solve (AIM_E_STATE); step-wise solvers bring
+                             their own workspace                               */
+  void* workspace;        /* device memory for that workspace, owned by the
+                             caller and valid until aim_destroy: 256-byte
+                             aligned, at least aim_workspace_bytes(n_vertices,
+                             max_rhs, max_restart) bytes.  NULL: aim_setup
+                             allocates it (freed by aim_destroy)               */
+  size_t workspace_bytes; /* size of workspace (ignored when it is NULL)        */
 } aim_params;
 
 typedef struct {
@@ -154,13 +171,22 @@ typedef struct {
   double seconds;        /* wall time of the call                                */
 } aim_solve_info;
 
-/* Upper estimate of the device bytes a context with these parameters holds
-   after aim_setup and a solve with this restart length: its tables and
-   buffers, the GMRES workspace (exact) and its grid-kernel spectrum in the
-   shared cache; near-field pairs are bounded from the geometry (eps over the
-   mean segment length).  Host-only, for admission control; 0 for invalid
-   parameters.                                                                 */
+/* Upper estimate of the device bytes a context with these parameters needs:
+   its tables and buffers, one Krylov workspace (exact) for max_rhs
+   right-hand sides and the longer of `restart` (a step-wise solver's) and
+   p->max_restart (aim_solve's), whether the caller or the library owns it,
+   and its grid-kernel spectrum in the shared cache; near-field pairs are
+   bounded from the geometry (eps over the mean segment length).  Host-only,
+   for admission control; 0 for invalid parameters.                            */
 size_t aim_footprint_bytes(const aim_params* p, int32_t restart);
+
+/* Device bytes of a GMRES(restart) Krylov workspace for nrhs right-hand sides
+   of an n_unknowns system: restart + 1 basis vectors, the Hessenberg matrix
+   and rotations, reduction partials and refinement vectors per rhs.  The
+   memory passed as aim_params.workspace or to aim_solver_begin must hold at
+   least this many bytes.  Host-only; 0 for invalid sizes (restart outside
+   1..1000, nrhs outside 1..AIM_MAX_RHS).                                      */
+size_t aim_workspace_bytes(int32_t n_unknowns, int32_t nrhs, int32_t restart);
 
 /* Build a context: host geometry, Gauss-Legendre nodes (eq. (7)), stencil
    weights and near-zone pairs; on the device the grid kernel samples with
@@ -206,10 +232,12 @@ aim_status aim_rhs_planewave(aim_ctx ctx, int32_t nrhs, const double* phi_inc_ho
    residual estimate of that system is <= tol ||b||).  x_dev holds the
    initial guess on entry and the solution on exit.  precision AIM_MIXED
    runs FP64 iterative refinement around an inner GMRES whose grid part is
-   FP32.  restart: 1..1000 Krylov vectors per cycle.  info_host: nrhs
-   entries (may be NULL).  Synchronous.  Errors: AIM_E_ARG, AIM_E_NOCONV,
-   AIM_E_NUMERIC, AIM_E_OOM, AIM_E_STATE (per-node context: every system
-   operator needs the near-field correction).                                  */
+   FP32.  restart: 1..max_restart Krylov vectors per cycle (the context's
+   workspace; nothing is allocated).  info_host: nrhs entries (may be NULL).
+   Synchronous.  Errors: AIM_E_ARG (also restart > max_restart or nrhs >
+   max_rhs), AIM_E_NOCONV, AIM_E_NUMERIC, AIM_E_STATE (max_restart = 0, or a
+   per-node context: every system operator needs the near-field
+   correction).                                                                */
 aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
                      const void* b_dev, void* x_dev, double tol, int32_t maxit,
                      int32_t restart, aim_solve_info* info_host);
@@ -218,9 +246,9 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
    aim_solve (any form, FP64 or AIM_MIXED refinement) and advances it by
    Arnoldi steps (inner steps for AIM_MIXED), so one host thread can
    interleave the steps of many requests, admit new requests between steps
-   and retire finished ones (iteration-level batching).  Each solver owns its
-   Krylov workspace (restart + 1 vectors per rhs), so several may share a
-   context: their steps run in call order on its stream, while solvers on
+   and retire finished ones (iteration-level batching).  Each solver has its
+   own Krylov workspace (restart + 1 vectors per rhs, in caller memory), so
+   several may share a context: their steps run in call order on its stream, while solvers on
    different contexts overlap on the device.  A step synchronises the stream
    only where the solve reads results on the host: when it closes a batch of
    8 Arnoldi steps, at a restart cycle's first step (true residual), and at
@@ -228,13 +256,18 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
    aim_solve is the same machinery run to the end, so a solver's result is
    bitwise that of aim_solve.
 
-   aim_solver_begin: arguments as aim_solve.  b_dev (caller-owned, N x nrhs)
-   must stay valid and unchanged until the solver ends; x_dev holds the
-   initial guess and receives the iterate at the end of every restart cycle
-   and the solution when the solve finishes.  Allocates the workspace, forms
-   the preconditioned right-hand side of the Calderon forms and takes the
-   norms of b (synchronises the stream).  Errors as aim_solve (AIM_E_ARG,
-   AIM_E_STATE, AIM_E_OOM, AIM_E_HIP); on error *out is unchanged.
+   aim_solver_begin: arguments as aim_solve, plus the solver's Krylov
+   workspace: device memory of at least aim_workspace_bytes(N, nrhs,
+   restart) bytes, 256-byte aligned, owned by the caller and left untouched
+   by it until aim_solver_end (restart up to 1000).  b_dev (caller-owned,
+   N x nrhs) must stay valid and unchanged until the solver ends; x_dev
+   holds the initial guess and receives the iterate at the end of every
+   restart cycle and the solution when the solve finishes.  Clears the
+   workspace, forms the preconditioned right-hand side of the Calderon forms
+   and takes the norms of b (synchronises the stream); allocates no device
+   memory.  Errors as aim_solve (AIM_E_ARG, also for a missing, misaligned
+   or short workspace; AIM_E_STATE, AIM_E_HIP); on error *out is
+   unchanged.
    aim_solver_step: one Arnoldi step for each unfinished solver of
    group[0 .. count-1]; NULL entries and finished solvers are skipped.  A
    step that completes a batch also checks and restarts, the step that ends
@@ -245,10 +278,12 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
    NULL; resid_true is -1 until the solve finishes).  Returns AIM_PENDING
    while the solve runs, then AIM_OK (converged), AIM_E_NOCONV (maxit
    reached) or the error that ended it.  Does not touch the device.
-   aim_solver_end: waits for the solver's work on the stream and frees it.
-   End the solvers of a context before aim_destroy.                          */
+   aim_solver_end: waits for the solver's work on the stream and frees its
+   host state; the workspace returns to the caller.  End the solvers of a
+   context before aim_destroy.                                               */
 aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev,
-                            void* x_dev, double tol, int32_t maxit, int32_t restart, aim_solver* out);
+                            void* x_dev, double tol, int32_t maxit, int32_t restart, void* workspace_dev,
+                            size_t workspace_bytes, aim_solver* out);
 aim_status aim_solver_step(aim_solver* group, int32_t count);
 aim_status aim_solver_poll(aim_solver solver, aim_solve_info* info_host);
 aim_status aim_solver_end(aim_solver solver);

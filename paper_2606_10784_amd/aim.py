@@ -49,7 +49,8 @@ class AimParams(ctypes.Structure):
                 ("m", ctypes.c_int32), ("eps", ctypes.c_double), ("quad", ctypes.c_int32),
                 ("near_radius", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_rhs", ctypes.c_int32), ("stream", ctypes.c_void_p), ("node_order", ctypes.c_int32),
-                ("dual", ctypes.c_int32)]
+                ("dual", ctypes.c_int32), ("max_restart", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class AimCtxInfo(ctypes.Structure):
@@ -74,6 +75,7 @@ _LIB = None
 
 EXPORTS = {
     "aim_footprint_bytes": (ctypes.c_size_t, [ctypes.POINTER(AimParams), ctypes.c_int32]),
+    "aim_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "aim_setup": (ctypes.c_int, [ctypes.POINTER(AimParams), ctypes.POINTER(ctypes.c_void_p)]),
     "aim_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "aim_filter_analytic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
@@ -97,7 +99,8 @@ EXPORTS = {
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "aim_solver_begin": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
-                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
     "aim_solver_step": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
     "aim_solver_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimSolveInfo)]),
     "aim_solver_end": (ctypes.c_int, [ctypes.c_void_p]),
@@ -138,6 +141,32 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _join_in_stream(s):
+    torch = _torch()
+    cur = torch.cuda.current_stream()
+    if s.cuda_stream != cur.cuda_stream:
+        s.wait_stream(cur)
+    return cur, s
+
+
+def _join_in(ctx):
+    """Orders the library's work after the caller's: the context's stream
+    waits for torch's current stream, where the caller (and this binding)
+    queued the inputs.  Returns (current stream, context stream)."""
+    return _join_in_stream(ctx._stream_obj)
+
+
+def _join_out(streams, *tensors):
+    """The caller's current stream waits for the library's asynchronous
+    work; tensors used on the context's stream are recorded there so the
+    caching allocator does not hand their memory out before it finished."""
+    cur, s = streams
+    if s.cuda_stream != cur.cuda_stream:
+        cur.wait_stream(s)
+        for t in tensors:
+            t.record_stream(s)
+
+
 def _as_cols(x, N):
     """(N,) or (nrhs, N) complex128 CUDA tensor -> (tensor, nrhs)."""
     torch = _torch()
@@ -154,8 +183,23 @@ def _as_cols(x, N):
     return x, x.shape[0]
 
 
+def aim_workspace_bytes(n_unknowns, nrhs, restart):
+    return int(_lib().aim_workspace_bytes(int(n_unknowns), int(nrhs), int(restart)))
+
+
+def _workspace(nbytes):
+    """Caller-owned device memory for a Krylov workspace (a torch tensor,
+    256-byte aligned)."""
+    torch = _torch()
+    if nbytes <= 0:
+        raise ValueError("invalid workspace size")
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-t.data_ptr()) % 256
+    return t, t.data_ptr() + off
+
+
 def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1, stream=None,
-                node_order=0, dual=0):
+                node_order=0, dual=0, max_restart=0, workspace=None, workspace_bytes=0):
     arr = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
     p = AimParams()
     p.n_vertices = arr.shape[0]
@@ -165,28 +209,47 @@ def make_params(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM
     p.stream = stream
     p.node_order = int(node_order)
     p.dual = int(dual)
+    p.max_restart = int(max_restart)
+    p.workspace = workspace
+    p.workspace_bytes = int(workspace_bytes)
     return p, arr
 
 
 def aim_footprint_bytes(xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
-                        restart=100, node_order=0, dual=0):
-    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None, node_order, dual)
+                        restart=100, node_order=0, dual=0, max_restart=0):
+    p, _keep = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs, None, node_order, dual,
+                           max_restart)
     return int(_lib().aim_footprint_bytes(ctypes.byref(p), int(restart)))
 
 
 class Context:
-    """Owns one aim_ctx (geometry, grid tables, spectra, near field)."""
+    """Owns one aim_ctx (geometry, grid tables, spectra, near field) and the
+    torch tensor that holds aim_solve's Krylov workspace (GMRES restarts up to
+    max_restart for max_rhs right-hand sides; max_restart = 0 leaves solves
+    to step-wise solvers)."""
 
     def __init__(self, xy, k, eta, basis, m, eps, quad=10, near_radius=6, precision=AIM_FP64, max_rhs=1,
-                 stream=None, node_order=0, dual=0):
+                 stream=None, node_order=0, dual=0, max_restart=100):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libaim needs a HIP device")
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
+        N = np.asarray(xy).reshape(-1, 2).shape[0]
+        if node_order != 0:
+            max_restart = 0                     # no solves on a per-node context
+        self._ws, ws_ptr, ws_bytes = None, None, 0
+        if max_restart > 0:
+            ws_bytes = aim_workspace_bytes(N, max_rhs, max_restart)
+            self._ws, ws_ptr = _workspace(ws_bytes)
         p, self._xy = make_params(xy, k, eta, basis, m, eps, quad, near_radius, precision, max_rhs,
-                                  _stream_handle(self._stream_obj), node_order, dual)
+                                  _stream_handle(self._stream_obj), node_order, dual, max_restart, ws_ptr, ws_bytes)
+        self.max_restart = max_restart
         h = ctypes.c_void_p()
+        # the workspace tensor is filled on the context's stream (set-up)
+        _join_in_stream(self._stream_obj)
         _check(_lib().aim_setup(ctypes.byref(p), ctypes.byref(h)), "aim_setup")
+        if self._ws is not None and self._stream_obj.cuda_stream != torch.cuda.current_stream().cuda_stream:
+            self._ws.record_stream(self._stream_obj)
         self._h = h
         self.N = p.n_vertices
         self.basis = basis
@@ -265,8 +328,10 @@ def aim_matvec(ctx, op, x, y=None):
     if y is None:
         y = torch.empty_like(x)
     _as_cols(y, ctx.N)
-    _check(_lib().aim_matvec(ctx.handle, opc, nrhs, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())),
-           "aim_matvec")
+    ss = _join_in(ctx)
+    st = _lib().aim_matvec(ctx.handle, opc, nrhs, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()))
+    _join_out(ss, x, y)
+    _check(st, "aim_matvec")
     return y
 
 
@@ -274,8 +339,11 @@ def aim_rhs_planewave(ctx, phis, amp=1.0):
     torch = _torch()
     ph = np.ascontiguousarray(np.atleast_1d(np.asarray(phis, dtype=np.float64)))
     b = torch.empty((ph.size, ctx.N), dtype=torch.complex128, device="cuda")
-    _check(_lib().aim_rhs_planewave(ctx.handle, ph.size, ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                    float(amp), ctypes.c_void_p(b.data_ptr())), "aim_rhs_planewave")
+    ss = _join_in(ctx)
+    st = _lib().aim_rhs_planewave(ctx.handle, ph.size, ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  float(amp), ctypes.c_void_p(b.data_ptr()))
+    _join_out(ss, b)
+    _check(st, "aim_rhs_planewave")
     return b[0] if np.ndim(phis) == 0 else b
 
 
@@ -286,8 +354,10 @@ def aim_solve(ctx, form, b, x0=None, tol=1e-6, maxit=5000, restart=100, precisio
     b, nrhs = _as_cols(b, ctx.N)
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     infos = (AimSolveInfo * nrhs)()
+    ss = _join_in(ctx)                      # x0 is queued on the current stream
     st = _lib().aim_solve(ctx.handle, fc, int(precision), nrhs, ctypes.c_void_p(b.data_ptr()),
                           ctypes.c_void_p(x.data_ptr()), float(tol), int(maxit), int(restart), infos)
+    _join_out(ss, b, x)
     out = [infos[i].as_dict() for i in range(nrhs)]
     if st not in (AIM_OK, AIM_E_NOCONV):
         raise AimError(st, "aim_solve")
@@ -308,10 +378,16 @@ class Solver:
         self.ctx = ctx
         self.b, self.nrhs = _as_cols(b, ctx.N)
         self.x = torch.zeros_like(self.b) if x0 is None else x0.clone()
+        # the solver's Krylov workspace: caller-owned device memory
+        ws_bytes = aim_workspace_bytes(ctx.N, self.nrhs, restart) if 1 <= int(restart) <= 1000 else 0
+        self._ws, ws_ptr = _workspace(ws_bytes) if ws_bytes > 0 else (None, None)
         h = ctypes.c_void_p()
-        _check(_lib().aim_solver_begin(ctx.handle, fc, int(precision), self.nrhs, ctypes.c_void_p(self.b.data_ptr()),
-                                       ctypes.c_void_p(self.x.data_ptr()), float(tol), int(maxit), int(restart),
-                                       ctypes.byref(h)), "aim_solver_begin")
+        ss = _join_in(ctx)                  # b and x0 are queued on the current stream
+        st = _lib().aim_solver_begin(ctx.handle, fc, int(precision), self.nrhs, ctypes.c_void_p(self.b.data_ptr()),
+                                     ctypes.c_void_p(self.x.data_ptr()), float(tol), int(maxit), int(restart),
+                                     ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes), ctypes.byref(h))
+        _join_out(ss, self.b, self.x, *([self._ws] if self._ws is not None else []))
+        _check(st, "aim_solver_begin")
         self.handle = h.value
         ctx._solvers.add(self)
 
@@ -349,6 +425,7 @@ def aim_rcs_monostatic(ctx, J, phis):
     if ph.size != nrhs:
         raise ValueError("one angle per current column")
     sig = np.zeros(nrhs)
+    _join_in(ctx)                            # synchronous: nothing to join afterwards
     _check(_lib().aim_rcs_monostatic(ctx.handle, nrhs, ctypes.c_void_p(J.data_ptr()),
                                      ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "aim_rcs_monostatic")
@@ -369,8 +446,10 @@ def aim_eval_green(ctx, R):
     torch = _torch()
     R = R.contiguous()
     out = torch.empty(R.shape, dtype=torch.complex128, device="cuda")
-    _check(_lib().aim_eval_green(ctx.handle, R.numel(), ctypes.c_void_p(R.data_ptr()),
-                                 ctypes.c_void_p(out.data_ptr())), "aim_eval_green")
+    ss = _join_in(ctx)
+    st = _lib().aim_eval_green(ctx.handle, R.numel(), ctypes.c_void_p(R.data_ptr()), ctypes.c_void_p(out.data_ptr()))
+    _join_out(ss, R, out)
+    _check(st, "aim_eval_green")
     return out
 
 

@@ -131,6 +131,7 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+struct Ctx;
 struct GmresWork {
   int restart = 0, nrhs = 0;
   // V: restart + 1 basis slots per rhs; H: Hessenberg (rotated in place by the
@@ -142,13 +143,14 @@ struct GmresWork {
           *sn = nullptr, *y = nullptr, *part = nullptr, *r = nullptr, *d = nullptr, *b2 = nullptr, *nrm = nullptr;
   double *resid = nullptr, *npart = nullptr;
   int* active = nullptr;
-  double* host_resid = nullptr;   // pinned
-  int* pin = nullptr;             // pinned mask staging
+  std::vector<double> host_resid; // host copy of the residual estimates (restart per rhs)
   int nchunk = 0;
   size_t lds_max = 65536;         // LDS bytes one block may use on this device
   size_t bytes = 0;
 };
-void free_gmres_work(GmresWork& w);
+// Binds a (restart, nrhs) GMRES workspace to caller- or context-owned device
+// memory (256-byte aligned, at least gmres_work_bytes); allocates nothing.
+aim_status bind_gmres_work(Ctx* c, GmresWork& w, void* base, size_t bytes, int restart, int nrhs);
 
 struct Ctx {
   HostTables t;
@@ -196,6 +198,8 @@ struct Ctx {
   void *d_U = nullptr, *d_T = nullptr, *d_V = nullptr;
   double2 *d_tmp1 = nullptr, *d_tmp2 = nullptr;   // N x max_rhs each
   double2* d_rhs = nullptr;
+  double* d_phi = nullptr;     // AIM_MAX_RHS incidence angles (aim_rhs_planewave)
+  double2* d_dot = nullptr;    // max_rhs column sums, then max_rhs values (aim_rcs_monostatic)
   double2* d_spec = nullptr;   // Fourier-spectrum work (modes, products, quotients), on first use
   double* d_red = nullptr;
   size_t dev_bytes = 0;
@@ -240,15 +244,31 @@ void release_spectrum(Ctx* c);
 size_t cache_clear();
 // y(:, r) = op x(:, r), column strides ldx / ldy (elements), FP64 vectors
 aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy);
+// The column pass of a split matvec: tile sets of `pairs` pairs at `tiles`
+// (pair stride n / CB tiles of ldt x CB values), spectrum Cq, twiddles tw.
+struct ColsJob {
+  const void* Cq = nullptr;
+  const void* tw = nullptr;
+  void* tiles = nullptr;
+  int n = 0, nr = 0, ldt = 0, pairs = 0;
+  bool f32 = false;
+};
+static constexpr int kColBatchMax = 32;   // tile sets per grouped column-pass launch
+bool matvec_splits(Ctx* c, int op);
+aim_status matvec_pre(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, ColsJob* job);
+aim_status matvec_post(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy);
+aim_status launch_cols_jobs(const ColsJob* jobs, int count, hipStream_t s);
 aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b);
 aim_status eval_green(Ctx* c, int n, const double* R, double2* out);
 aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma);
+aim_status rcs_into(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma_host, double* phi_dev,
+                    double2* b_dev, double2* dot_dev, double* sig_dev);
 aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host, double2* lambda_host);
 aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
                  int maxit, int restart, aim_solve_info* info);
 size_t gmres_work_bytes(size_t N, size_t restart, size_t nrhs);
 aim_status solver_begin(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
-                        int maxit, int restart, aim_solver_s** out);
+                        int maxit, int restart, void* workspace, size_t workspace_bytes, aim_solver_s** out);
 aim_status solver_step(aim_solver_s** group, int count);
 aim_status solver_poll(aim_solver_s* sv, aim_solve_info* info);
 aim_status solver_end(aim_solver_s* sv);

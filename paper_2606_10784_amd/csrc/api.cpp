@@ -25,7 +25,7 @@ void free_ctx(Ctx* c) {
   release_spectrum(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
-  free_gmres_work(c->gw);
+  c->gw = GmresWork();
 }
 
 // the refined polygon of the dual hat space: v_j at 2j, midpoints at 2j+1
@@ -49,6 +49,9 @@ static aim_params dual_params(const aim_params* p, const std::vector<double>& rx
   q.basis = AIM_HAT;
   q.node_order = 0;
   q.dual = 0;
+  q.max_restart = 0;      // solves run on the pulse context
+  q.workspace = nullptr;
+  q.workspace_bytes = 0;
   return q;
 }
 
@@ -98,11 +101,16 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   else if (!t) b += near * 16 * nvals;                           // the band form, kept only when smaller
   b += N * S * (8 + 4) * (p->basis == AIM_HAT ? 4 : 1) * 2;
   b += 3 * N * R * 16 + std::max<size_t>(5 * N, 64) * R * 8;    // tmp1, tmp2, rhs, reductions
-  b += gmres_work_bytes(N, restart, R);
+  b += (size_t)AIM_MAX_RHS * 8 + R * 24;                        // angles, column sums and values of rhs / rcs
+  // the Krylov space: the context's own (max_restart) or a step-wise
+  // solver's (restart), whichever is longer
+  const int rs = std::max(restart, p->max_restart);
+  if (rs > 0) b += gmres_work_bytes(N, rs, R);
   if (p->dual && p->basis == AIM_PULSE && p->xy) {   // the dual hat context (no Krylov space)
     const std::vector<double> rxy = refined_xy(p);
-    const aim_params q = dual_params(p, rxy);
-    b += footprint(&q, 1, nullptr) - gmres_work_bytes(q.n_vertices, 1, R);
+    aim_params q = dual_params(p, rxy);
+    q.max_restart = 0;
+    b += footprint(&q, 0, nullptr);
   }
   return b;
 }
@@ -127,8 +135,13 @@ const char* aim_strerror(aim_status s) {
 }
 
 size_t aim_footprint_bytes(const aim_params* p, int32_t restart) {
-  if (!p || p->n_vertices < 1 || p->m < 1 || p->max_rhs < 1 || restart < 1) return 0;
+  if (!p || p->n_vertices < 1 || p->m < 1 || p->max_rhs < 1 || restart < 0 || p->max_restart < 0) return 0;
   return footprint(p, restart, nullptr);
+}
+
+size_t aim_workspace_bytes(int32_t n_unknowns, int32_t nrhs, int32_t restart) {
+  if (n_unknowns < 1 || nrhs < 1 || nrhs > AIM_MAX_RHS || restart < 1 || restart > 1000) return 0;
+  return gmres_work_bytes((size_t)n_unknowns, (size_t)restart, (size_t)nrhs);
 }
 
 aim_status aim_setup(const aim_params* p, aim_ctx* out) {
@@ -136,6 +149,11 @@ aim_status aim_setup(const aim_params* p, aim_ctx* out) {
   *out = nullptr;
   if (p->precision != AIM_FP64 && p->precision != AIM_MIXED) return AIM_E_ARG;
   if (p->dual != 0 && (p->dual != 1 || p->basis != AIM_PULSE || p->node_order != 0)) return AIM_E_ARG;
+  if (p->max_restart < 0 || p->max_restart > 1000) return AIM_E_ARG;
+  if (p->workspace && (p->max_restart < 1 || ((uintptr_t)p->workspace & 255) != 0 || p->n_vertices < 1 ||
+                       p->max_rhs < 1 || p->max_rhs > AIM_MAX_RHS ||
+                       p->workspace_bytes < gmres_work_bytes(p->n_vertices, p->max_restart, p->max_rhs)))
+    return AIM_E_ARG;
   aim_ctx_s* h = new (std::nothrow) aim_ctx_s();
   if (!h) return AIM_E_OOM;
   Ctx* c = &h->c;
@@ -173,6 +191,15 @@ aim_status aim_setup(const aim_params* p, aim_ctx* out) {
     c->dual->device = c->device;
     st = setup_device(c->dual);
     if (st == AIM_OK) st = setup_dual(c);
+  }
+  if (st == AIM_OK && p->max_restart > 0 && c->t.node_order == 0) {
+    // the Krylov workspace of aim_solve: the caller's, or allocated here once
+    void* ws = p->workspace;
+    const size_t need = gmres_work_bytes(c->t.N, p->max_restart, p->max_rhs);
+    if (!ws) st = dev_alloc(c, &ws, need);
+    if (st == AIM_OK) st = bind_gmres_work(c, c->gw, ws, p->workspace ? p->workspace_bytes : need, p->max_restart,
+                                           p->max_rhs);
+    if (st == AIM_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = AIM_E_HIP;
   }
   if (st != AIM_OK) {
     free_ctx(c);
@@ -217,11 +244,12 @@ aim_status aim_solve(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs,
 }
 
 aim_status aim_solver_begin(aim_ctx ctx, int32_t form, int32_t precision, int32_t nrhs, const void* b_dev,
-                            void* x_dev, double tol, int32_t maxit, int32_t restart, aim_solver* out) {
-  if (!ctx || !b_dev || !x_dev || b_dev == x_dev || !out) return AIM_E_ARG;
+                            void* x_dev, double tol, int32_t maxit, int32_t restart, void* workspace_dev,
+                            size_t workspace_bytes, aim_solver* out) {
+  if (!ctx || !b_dev || !x_dev || b_dev == x_dev || !out || !workspace_dev) return AIM_E_ARG;
   if (ctx->c.t.node_order != 0) return AIM_E_STATE;   // every system operator needs the near field
   return solver_begin(&ctx->c, form, precision, nrhs, (const double2*)b_dev, (double2*)x_dev, tol, maxit, restart,
-                      out);
+                      workspace_dev, workspace_bytes, out);
 }
 
 aim_status aim_solver_step(aim_solver* group, int32_t count) { return solver_step(group, count); }

@@ -695,6 +695,146 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 // inverse is the matching decimation in time.
 // MODE 1 (set-up): plain forward FFT of CB consecutive columns of a
 // row-major N x N array.
+// The column pass of one tile [row][CB] (nr kept rows, the rest of the
+// column is the zero padding), in place: column FFT, spectrum multiply,
+// inverse column FFT (the MODE 0 body of k_cols and of k_cols_group).
+template <typename T, int N>
+__device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict__ tile, int nr, int b,
+                                               const cplx<T>* __restrict__ Cq, const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
+  constexpr int CB = ColCfg<T, N>::CB;
+  constexpr int NT = ColCfg<T, N>::NT;
+  const int tid = threadIdx.x;
+  static_assert(N >= 32, "column pass assumes at least two forward passes");
+  constexpr int RL = last_radix<N>();
+  constexpr int S1 = N / 16;
+  constexpr int SM = N / 256;                   // middle radix-16 pass stride
+  constexpr bool MID = SM >= RL && SM >= 1;
+  static_assert(!MID || SM / 16 < RL, "at most one middle pass per direction");
+  constexpr int NB1 = S1 * CB, PER1 = (NB1 + NT - 1) / NT;
+  constexpr int NBM = (N / 16) * CB, PERM = (NBM + NT - 1) / NT;
+  constexpr int NG = N / RL, NBF = NG * CB, PERF = (NBF + NT - 1) / NT;
+  // forward pass 1 (stride N/16, radix 16) from HBM: inputs m + S1 r with
+  // r >= 8 lie in the zero half
+  V v[PER1][16];
+#pragma unroll
+  for (int q = 0; q < PER1; ++q) {
+    const int bb = tid + q * NT;
+    if ((NB1 % NT) == 0 || bb < NB1) {
+      const int c = bb % CB, m = bb / CB;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = m + r * S1;
+        v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
+      }
+    }
+  }
+  // everything else this block reads from HBM does not depend on the data:
+  // the spectrum values of the fused pass and the twiddles of the other
+  // passes are issued now and consumed passes later, so their latency
+  // overlaps the first passes instead of stalling each one (the spectrum
+  // only in FP64 up to N = 2048: elsewhere the extra registers would cost
+  // a wave per SIMD or spill).
+  // The spectrum row is folded (ky and N - ky share a slot): group g holds
+  // ky = low + W r with low the base-16 digit reversal of g; a group with
+  // low > W/2 reads its mirror group W - low and reverses r (in registers,
+  // at the multiply, so a prefetch never waits).
+  constexpr int W = N / RL, HS = (W / 2 + 1) * RL;
+  auto mirrored = [&](int g, int& lowc) {
+    int low = 0;
+#pragma unroll
+    for (int t = 1, gg = g; t < W; t *= 16, gg >>= 4) low = low * 16 + (gg & 15);
+    lowc = low > W / 2 ? W - low : low;
+    return low > W / 2;
+  };
+  auto load_spec = [&](int bb, V* cv) {
+    const int g = bb % NG, c = bb / NG;
+    int kx, kxq, lowc;
+    col_of(b, c, N, CB, kx, kxq);
+    mirrored(g, lowc);
+    const V* Cp = Cq + (size_t)kxq * HS + lowc * RL;
+#pragma unroll
+    for (int r = 0; r < RL; ++r) cv[r] = Cp[r];
+  };
+  constexpr bool PRE = sizeof(T) == 8 && N <= 2048 && PERF * RL <= 16;
+  V cv[PERF][RL];
+  if constexpr (PRE) {
+#pragma unroll
+    for (int q = 0; q < PERF; ++q) {
+      const int bb = tid + q * NT;
+      if ((NBF % NT) == 0 || bb < NBF) load_spec(bb, cv[q]);
+    }
+  }
+  V w1[PER1], wm[PERM];
+#pragma unroll
+  for (int q = 0; q < PER1; ++q) {
+    const int bb = tid + q * NT;
+    w1[q] = ((NB1 % NT) == 0 || bb < NB1) ? tw_base<T, N, S1, 16>(bb / CB, tw) : mk<T>(1, 0);
+  }
+  if constexpr (MID) {
+#pragma unroll
+    for (int q = 0; q < PERM; ++q) {
+      const int bb = tid + q * NT;
+      wm[q] = ((NBM % NT) == 0 || bb < NBM) ? tw_base<T, N, SM, 16>((bb / CB) % SM, tw) : mk<T>(1, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER1; ++q) {
+    const int bb = tid + q * NT;
+    if ((NB1 % NT) == 0 || bb < NB1) {
+      const int c = bb % CB, m = bb / CB;
+      dft16_halfin<T, false>(v[q]);
+      apply_twiddle<T, false, S1, 16>(v[q], w1[q]);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) buf[pidx((m + r * S1) * CB + c)] = v[q][r];
+    }
+  }
+  __syncthreads();
+  if constexpr (MID) ct_pass_w<T, N, CB, NT, false, SM, 16>(buf, wm);
+  // last forward pass (contiguous groups of RL), spectrum multiply in the
+  // stored frequency order, first inverse pass; lanes run along the groups
+#pragma unroll
+  for (int q = 0; q < PERF; ++q) {
+    const int bb = tid + q * NT;
+    if ((NBF % NT) == 0 || bb < NBF) {
+      const int g = bb % NG, c = bb / NG;
+      if constexpr (!PRE) load_spec(bb, cv[q]);
+      V u[RL];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) u[r] = buf[pidx((g * RL + r) * CB + c)];
+      int lowc;
+      const bool mir = mirrored(g, lowc);
+      dft_r<T, RL, false>(u);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) u[r] = cmul(u[r], mir ? cv[q][RL - 1 - r] : cv[q][r]);
+      dft_r<T, RL, true>(u);
+#pragma unroll
+      for (int r = 0; r < RL; ++r) buf[pidx((g * RL + r) * CB + c)] = u[r];
+    }
+  }
+  __syncthreads();
+  if constexpr (MID) ct_pass_w<T, N, CB, NT, true, SM, 16>(buf, wm);
+  // last inverse pass (stride N/16, radix 16) straight to HBM: outputs
+  // m + S1 r, only r < 8 can be a kept row
+#pragma unroll
+  for (int q = 0; q < PER1; ++q) {
+    const int bb = tid + q * NT;
+    if ((NB1 % NT) == 0 || bb < NB1) {
+      const int c = bb % CB, m = bb / CB;
+      V u[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = buf[pidx((m + r * S1) * CB + c)];
+      apply_twiddle<T, true, S1, 16>(u, w1[q]);
+      dft16_halfout<T, true>(u);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int i = m + r * S1;
+        if (i < nr) tile[(size_t)i * CB + c] = u[r];
+      }
+    }
+  }
+}
+
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
     cplx<T>* __restrict__ Tb, int nr, int ldt, const cplx<T>* __restrict__ Cq,
@@ -708,135 +848,7 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
   const int pair = blockIdx.y;
   const int tid = threadIdx.x;
   if constexpr (MODE == 0) {
-    static_assert(N >= 32, "column pass assumes at least two forward passes");
-    constexpr int RL = last_radix<N>();
-    constexpr int S1 = N / 16;
-    constexpr int SM = N / 256;                   // middle radix-16 pass stride
-    constexpr bool MID = SM >= RL && SM >= 1;
-    static_assert(!MID || SM / 16 < RL, "at most one middle pass per direction");
-    constexpr int NB1 = S1 * CB, PER1 = (NB1 + NT - 1) / NT;
-    constexpr int NBM = (N / 16) * CB, PERM = (NBM + NT - 1) / NT;
-    constexpr int NG = N / RL, NBF = NG * CB, PERF = (NBF + NT - 1) / NT;
-    V* tile = Tb + ((size_t)pair * NBLK + b) * ldt * CB;
-    // forward pass 1 (stride N/16, radix 16) from HBM: inputs m + S1 r with
-    // r >= 8 lie in the zero half
-    V v[PER1][16];
-#pragma unroll
-    for (int q = 0; q < PER1; ++q) {
-      const int bb = tid + q * NT;
-      if ((NB1 % NT) == 0 || bb < NB1) {
-        const int c = bb % CB, m = bb / CB;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int i = m + r * S1;
-          v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
-        }
-      }
-    }
-    // everything else this block reads from HBM does not depend on the data:
-    // the spectrum values of the fused pass and the twiddles of the other
-    // passes are issued now and consumed passes later, so their latency
-    // overlaps the first passes instead of stalling each one (the spectrum
-    // only in FP64 up to N = 2048: elsewhere the extra registers would cost
-    // a wave per SIMD or spill).
-    // The spectrum row is folded (ky and N - ky share a slot): group g holds
-    // ky = low + W r with low the base-16 digit reversal of g; a group with
-    // low > W/2 reads its mirror group W - low and reverses r (in registers,
-    // at the multiply, so a prefetch never waits).
-    constexpr int W = N / RL, HS = (W / 2 + 1) * RL;
-    auto mirrored = [&](int g, int& lowc) {
-      int low = 0;
-#pragma unroll
-      for (int t = 1, gg = g; t < W; t *= 16, gg >>= 4) low = low * 16 + (gg & 15);
-      lowc = low > W / 2 ? W - low : low;
-      return low > W / 2;
-    };
-    auto load_spec = [&](int bb, V* cv) {
-      const int g = bb % NG, c = bb / NG;
-      int kx, kxq, lowc;
-      col_of(b, c, N, CB, kx, kxq);
-      mirrored(g, lowc);
-      const V* Cp = Cq + (size_t)kxq * HS + lowc * RL;
-#pragma unroll
-      for (int r = 0; r < RL; ++r) cv[r] = Cp[r];
-    };
-    constexpr bool PRE = sizeof(T) == 8 && N <= 2048 && PERF * RL <= 16;
-    V cv[PERF][RL];
-    if constexpr (PRE) {
-#pragma unroll
-      for (int q = 0; q < PERF; ++q) {
-        const int bb = tid + q * NT;
-        if ((NBF % NT) == 0 || bb < NBF) load_spec(bb, cv[q]);
-      }
-    }
-    V w1[PER1], wm[PERM];
-#pragma unroll
-    for (int q = 0; q < PER1; ++q) {
-      const int bb = tid + q * NT;
-      w1[q] = ((NB1 % NT) == 0 || bb < NB1) ? tw_base<T, N, S1, 16>(bb / CB, tw) : mk<T>(1, 0);
-    }
-    if constexpr (MID) {
-#pragma unroll
-      for (int q = 0; q < PERM; ++q) {
-        const int bb = tid + q * NT;
-        wm[q] = ((NBM % NT) == 0 || bb < NBM) ? tw_base<T, N, SM, 16>((bb / CB) % SM, tw) : mk<T>(1, 0);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < PER1; ++q) {
-      const int bb = tid + q * NT;
-      if ((NB1 % NT) == 0 || bb < NB1) {
-        const int c = bb % CB, m = bb / CB;
-        dft16_halfin<T, false>(v[q]);
-        apply_twiddle<T, false, S1, 16>(v[q], w1[q]);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) buf[pidx((m + r * S1) * CB + c)] = v[q][r];
-      }
-    }
-    __syncthreads();
-    if constexpr (MID) ct_pass_w<T, N, CB, NT, false, SM, 16>(buf, wm);
-    // last forward pass (contiguous groups of RL), spectrum multiply in the
-    // stored frequency order, first inverse pass; lanes run along the groups
-#pragma unroll
-    for (int q = 0; q < PERF; ++q) {
-      const int bb = tid + q * NT;
-      if ((NBF % NT) == 0 || bb < NBF) {
-        const int g = bb % NG, c = bb / NG;
-        if constexpr (!PRE) load_spec(bb, cv[q]);
-        V u[RL];
-#pragma unroll
-        for (int r = 0; r < RL; ++r) u[r] = buf[pidx((g * RL + r) * CB + c)];
-        int lowc;
-        const bool mir = mirrored(g, lowc);
-        dft_r<T, RL, false>(u);
-#pragma unroll
-        for (int r = 0; r < RL; ++r) u[r] = cmul(u[r], mir ? cv[q][RL - 1 - r] : cv[q][r]);
-        dft_r<T, RL, true>(u);
-#pragma unroll
-        for (int r = 0; r < RL; ++r) buf[pidx((g * RL + r) * CB + c)] = u[r];
-      }
-    }
-    __syncthreads();
-    if constexpr (MID) ct_pass_w<T, N, CB, NT, true, SM, 16>(buf, wm);
-    // last inverse pass (stride N/16, radix 16) straight to HBM: outputs
-    // m + S1 r, only r < 8 can be a kept row
-#pragma unroll
-    for (int q = 0; q < PER1; ++q) {
-      const int bb = tid + q * NT;
-      if ((NB1 % NT) == 0 || bb < NB1) {
-        const int c = bb % CB, m = bb / CB;
-        V u[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) u[r] = buf[pidx((m + r * S1) * CB + c)];
-        apply_twiddle<T, true, S1, 16>(u, w1[q]);
-        dft16_halfout<T, true>(u);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int i = m + r * S1;
-          if (i < nr) tile[(size_t)i * CB + c] = u[r];
-        }
-      }
-    }
+    cols_conv_tile<T, N>(buf, Tb + ((size_t)pair * NBLK + b) * ldt * CB, nr, b, Cq, tw);
   } else {
     const int kx0 = b * CB;
     for (int idx = tid; idx < N * CB; idx += NT) {
@@ -850,6 +862,28 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
       Tb[(size_t)i * N + kx0 + c] = buf[pidx(idx)];
     }
   }
+}
+
+// Column passes of several contexts that share one spectrum (same n, k eps
+// and precision), one launch: entry e of the batch is a pair's tile set
+// (tile base of column block 0, kept rows, tile stride); blockIdx.y picks
+// the entry.  Each tile is computed exactly as by k_cols.
+struct ColBatch {
+  static constexpr int kMax = kColBatchMax;
+  void* tile[kMax];
+  int nr[kMax];
+  int ldt[kMax];
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols_group(ColBatch batch, const cplx<T>* __restrict__ Cq,
+                                                                 const cplx<T>* __restrict__ tw) {
+  using V = cplx<T>;
+  constexpr int CB = ColCfg<T, N>::CB;
+  __shared__ V buf[padded(N * CB)];
+  const int e = blockIdx.y, b = blockIdx.x;
+  V* tile = (V*)batch.tile[e] + (size_t)b * batch.ldt[e] * CB;
+  cols_conv_tile<T, N>(buf, tile, batch.nr[e], b, Cq, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -918,6 +952,43 @@ aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int ldt, int pairs,
   return hipGetLastError() == hipSuccess ? AIM_OK : AIM_E_HIP;
 }
 
+// columns per tile of the column pass (tile layout of the intermediate)
+int col_block(int n, bool f32) {
+  switch (n) {
+#define CASE(NN) \
+  case NN: return f32 ? ColCfg<float, NN>::CB : ColCfg<double, NN>::CB;
+    AIM_FOR_SIZES(CASE)
+#undef CASE
+  }
+  return 0;
+}
+
+// grouped column pass over `count` tile sets (count <= ColBatch::kMax)
+template <typename T>
+aim_status launch_cols_group(int n, int count, void* const* tiles, const int* nr, const int* ldt,
+                             const cplx<T>* Cq, const cplx<T>* tw, hipStream_t s) {
+  if (count < 1 || count > ColBatch::kMax) return AIM_E_ARG;
+  ColBatch bt;
+  for (int e = 0; e < ColBatch::kMax; ++e) {
+    const int q = e < count ? e : 0;
+    if (nr[q] < 1 || nr[q] > n / 2 || ldt[q] < nr[q]) return AIM_E_ARG;
+    bt.tile[e] = tiles[q];
+    bt.nr[e] = nr[q];
+    bt.ldt[e] = ldt[q];
+  }
+  switch (n) {
+#define CASE(NN)                                                                                              \
+  case NN:                                                                                                    \
+    hipLaunchKernelGGL((k_cols_group<T, NN>), dim3(NN / ColCfg<T, NN>::CB, count), dim3(ColCfg<T, NN>::NT), 0, \
+                       s, bt, Cq, tw);                                                                        \
+    break;
+    AIM_FOR_SIZES(CASE)
+#undef CASE
+    default: return AIM_E_ARG;
+  }
+  return hipGetLastError() == hipSuccess ? AIM_OK : AIM_E_HIP;
+}
+
 aim_status launch_rows_fft_inplace(int n, double2* A, const double2* tw, hipStream_t s) {
   switch (n) {
 #define CASE(NN)                                                                                   \
@@ -943,5 +1014,9 @@ template aim_status launch_cols<double>(int, int, double2*, int, int, int, const
                                         hipStream_t, hipEvent_t, hipEvent_t);
 template aim_status launch_cols<float>(int, int, float2*, int, int, int, const float2*, const float2*, hipStream_t,
                                        hipEvent_t, hipEvent_t);
+template aim_status launch_cols_group<double>(int, int, void* const*, const int*, const int*, const double2*,
+                                              const double2*, hipStream_t);
+template aim_status launch_cols_group<float>(int, int, void* const*, const int*, const int*, const float2*,
+                                             const float2*, hipStream_t);
 
 }  // namespace aim

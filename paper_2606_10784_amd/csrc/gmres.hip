@@ -571,89 +571,94 @@ __global__ void k_set_g0(int nrhs, int ldh, const double2* nrm2, const int* acti
 }
 
 // ---------------------------------------------------------------------------
-void free_gmres_work(GmresWork& w) {
-  for (void* p : {(void*)w.V, (void*)w.W, (void*)w.H, (void*)w.Hu, (void*)w.hp, (void*)w.coef, (void*)w.g, (void*)w.cs,
-                  (void*)w.sn, (void*)w.y, (void*)w.part, (void*)w.r, (void*)w.d, (void*)w.b2, (void*)w.nrm,
-                  (void*)w.resid, (void*)w.npart, (void*)w.active})
-    if (p) (void)hipFree(p);
-  if (w.host_resid) (void)hipHostFree(w.host_resid);
-  if (w.pin) (void)hipHostFree(w.pin);
-  w = GmresWork();
+// workspace: carved from one caller- or context-owned device region, so no
+// solve path allocates device memory
+// ---------------------------------------------------------------------------
+__global__ void k_zero_words(size_t n, uint64_t* __restrict__ p) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+__global__ void k_fill_int(int n, int v, int* __restrict__ p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+// up to 32 values carried in the kernel arguments (no staging memory)
+struct IntChunk {
+  int v[32];
+};
+__global__ void k_put_ints(int n, IntChunk c, int* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = c.v[i];
 }
 
-// Device bytes of the workspace alloc_work allocates (its allocation list).
-size_t gmres_work_bytes(size_t N, size_t restart, size_t nrhs) {
+static constexpr size_t kWorkAlign = 256;
+
+// Carves the buffers of a (restart, nrhs) workspace out of base (nullptr:
+// only counts); returns the bytes used.
+static size_t carve_work(GmresWork& w, char* base, size_t N, size_t restart, size_t nrhs) {
   const size_t ldh = restart + 1, nchunk = (N + RED_CHUNK - 1) / RED_CHUNK;
-  const size_t c16 = nrhs * 16;
-  return c16 * (ldh * N + N + ldh * restart + ldh * ldh + 2 * ldh + (2 * ldh + 2) + ldh + 3 * restart +
-                ldh * nchunk * 2 + 3 * N + 2) +
-         nrhs * restart * 8 + nrhs * nchunk * 8 + nrhs * 4 * 2;
+  size_t off = 0;
+  auto take = [&](auto** ptr, size_t bytes) {
+    using P = std::remove_reference_t<decltype(**ptr)>;
+    *ptr = base ? reinterpret_cast<P*>(base + off) : nullptr;
+    off += (bytes + kWorkAlign - 1) / kWorkAlign * kWorkAlign;
+  };
+  take(&w.V, nrhs * ldh * N * 16);
+  take(&w.W, nrhs * N * 16);
+  take(&w.H, nrhs * ldh * restart * 16);
+  take(&w.Hu, nrhs * ldh * ldh * 16);
+  take(&w.hp, nrhs * 2 * ldh * 16);
+  take(&w.coef, nrhs * (2 * ldh + 2) * 16);
+  take(&w.g, nrhs * ldh * 16);
+  take(&w.cs, nrhs * restart * 16);
+  take(&w.sn, nrhs * restart * 16);
+  take(&w.y, nrhs * restart * 16);
+  take(&w.part, nrhs * ldh * nchunk * 2 * 16);
+  take(&w.r, nrhs * N * 16);
+  take(&w.d, nrhs * N * 16);
+  take(&w.b2, nrhs * N * 16);
+  take(&w.nrm, nrhs * 2 * 16);
+  take(&w.resid, nrhs * restart * 8);
+  take(&w.npart, nrhs * nchunk * 8);
+  take(&w.active, nrhs * 4 * 2);
+  return off;
 }
 
-// Allocates the workspace for (restart, nrhs) into the empty w; on an error
-// the caller frees whatever was allocated.
-static aim_status alloc_work(Ctx* c, GmresWork& w, int restart, int nrhs) {
-  const int N = c->t.N;
-  const int ldh = restart + 1;
+size_t gmres_work_bytes(size_t N, size_t restart, size_t nrhs) {
+  GmresWork w;
+  return carve_work(w, nullptr, N, restart, nrhs);
+}
+
+// Binds a (restart, nrhs) workspace to `bytes` of device memory at base
+// (256-byte aligned): carves its buffers, clears them with a fill kernel,
+// sets the all-ones mask and sizes the host copies of the residual
+// estimates.  Allocates no device memory.
+aim_status bind_gmres_work(Ctx* c, GmresWork& w, void* base, size_t bytes, int restart, int nrhs) {
+  if (!base || ((uintptr_t)base % kWorkAlign) != 0 || restart < 1 || nrhs < 1) return AIM_E_ARG;
+  const size_t need = gmres_work_bytes(c->t.N, restart, nrhs);
+  if (bytes < need) return AIM_E_ARG;
+  w = GmresWork();
   w.restart = restart;
   w.nrhs = nrhs;
-  w.nchunk = (N + RED_CHUNK - 1) / RED_CHUNK;
-  size_t tot = 0;
-  auto A = [&](void** p, size_t b) -> bool {
-    tot += b;
-    if (hipMalloc(p, b) != hipSuccess) return false;
-    return hipMemset(*p, 0, b) == hipSuccess;
-  };
-  bool ok = A((void**)&w.V, (size_t)nrhs * ldh * N * 16) && A((void**)&w.W, (size_t)nrhs * N * 16) &&
-            A((void**)&w.H, (size_t)nrhs * ldh * restart * 16) && A((void**)&w.Hu, (size_t)nrhs * ldh * ldh * 16) &&
-            A((void**)&w.hp, (size_t)nrhs * 2 * ldh * 16) &&
-            A((void**)&w.coef, (size_t)nrhs * (2 * ldh + 2) * 16) && A((void**)&w.g, (size_t)nrhs * ldh * 16) &&
-            A((void**)&w.cs, (size_t)nrhs * restart * 16) && A((void**)&w.sn, (size_t)nrhs * restart * 16) &&
-            A((void**)&w.y, (size_t)nrhs * restart * 16) &&
-            A((void**)&w.part, (size_t)nrhs * ldh * w.nchunk * 2 * 16) && A((void**)&w.r, (size_t)nrhs * N * 16) &&
-            A((void**)&w.d, (size_t)nrhs * N * 16) && A((void**)&w.b2, (size_t)nrhs * N * 16) &&
-            A((void**)&w.nrm, (size_t)nrhs * 2 * 16) && A((void**)&w.resid, (size_t)nrhs * restart * 8) &&
-            A((void**)&w.npart, (size_t)nrhs * w.nchunk * 8) && A((void**)&w.active, (size_t)nrhs * 4 * 2);
-  if (!ok) return AIM_E_OOM;
-  if (hipHostMalloc((void**)&w.host_resid, (size_t)nrhs * restart * 8) != hipSuccess) return AIM_E_OOM;
-  // pinned staging for the host-to-device mask copies (one region per use,
-  // each rewritten only after the stream has been synchronised)
-  if (hipHostMalloc((void**)&w.pin, (size_t)nrhs * 4 * sizeof(int)) != hipSuccess) return AIM_E_OOM;
-  for (int r = 0; r < 4 * nrhs; ++r) w.pin[r] = 1;
+  w.nchunk = (c->t.N + RED_CHUNK - 1) / RED_CHUNK;
+  carve_work(w, (char*)base, c->t.N, restart, nrhs);
+  w.bytes = need;
+  hipLaunchKernelGGL(k_zero_words, dim3(1024), dim3(256), 0, c->stream, need / 8, (uint64_t*)base);
   // all-ones mask used by the residual checks
-  if (hipMemcpy(w.active + nrhs, w.pin, (size_t)nrhs * 4, hipMemcpyHostToDevice) != hipSuccess) return AIM_E_HIP;
-  w.bytes = tot;
-  {
-    // a check may rotate up to kCheckEvery + 1 columns (the last one of a
-    // cycle is finalised with the batch); batches that do not fit one
-    // block's LDS are split by givens_batches()
-    int lds = 0;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || lds <= 0)
-      return AIM_E_HIP;
-    w.lds_max = (size_t)lds;
-    const size_t gb = std::min(((size_t)(kCheckEvery + 1) * ldh + 2 * (size_t)restart) * 16, w.lds_max);
-    if (gb > 65536 &&
-        hipFuncSetAttribute((const void*)k_givens_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gb) !=
-            hipSuccess)
-      return AIM_E_HIP;
-  }
-  return AIM_OK;
-}
-
-// The workspace of the context, grown when a solve needs a longer restart or
-// more right-hand sides.  A failed allocation leaves it empty, so a later
-// call allocates afresh instead of using a partial workspace.
-static aim_status ensure_work(Ctx* c, int restart, int nrhs) {
-  GmresWork& w = c->gw;
-  if (w.V && w.restart >= restart && w.nrhs >= nrhs) return AIM_OK;
-  c->dev_bytes -= w.bytes;
-  free_gmres_work(w);
-  const aim_status st = alloc_work(c, w, restart, nrhs);
-  if (st != AIM_OK) {
-    free_gmres_work(w);
-    return st;
-  }
-  c->dev_bytes += w.bytes;
+  hipLaunchKernelGGL(k_fill_int, dim3((nrhs + 255) / 256), dim3(256), 0, c->stream, nrhs, 1, w.active + nrhs);
+  AIM_HIP_CHECK(hipGetLastError());
+  w.host_resid.assign((size_t)nrhs * restart, 0.0);
+  // a check may rotate up to kCheckEvery + 1 columns (the last one of a
+  // cycle is finalised with the batch); batches that do not fit one block's
+  // LDS are split by close_batch
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || lds <= 0)
+    return AIM_E_HIP;
+  w.lds_max = (size_t)lds;
+  const size_t gb = std::min(((size_t)(kCheckEvery + 1) * (restart + 1) + 2 * (size_t)restart) * 16, w.lds_max);
+  if (gb > 65536 &&
+      hipFuncSetAttribute((const void*)k_givens_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gb) !=
+          hipSuccess)
+    return AIM_E_HIP;
   return AIM_OK;
 }
 
@@ -694,40 +699,45 @@ struct GmresRun {
   int op, nrhs;
   const double2* b;
   double2* x;
-  double tol;
+  std::vector<double> tol;   // per right-hand side
   int maxit, restart;
   GmresResult& res;
   hipStream_t s;
   int N, ldh, gblk;
   int64_t ldv;
   dim3 gN;
-  int *d_all, *pin_act, *pin_upd, *pin_jm;
+  int* d_all;
   std::vector<int> act, jdone, cyc;
   std::vector<double> bn;
   int total = 0, j = 0, jfin = 0, jend = 0;
   bool batch = false;
   Phase phase = TOP;
 
-  GmresRun(Ctx* c_, GmresWork& w_, int op_, int nrhs_, const double2* b_, double2* x_, double tol_, int maxit_,
-           int restart_, GmresResult& res_)
-      : c(c_), w(w_), op(op_), nrhs(nrhs_), b(b_), x(x_), tol(tol_), maxit(maxit_), restart(restart_), res(res_) {
+  GmresRun(Ctx* c_, GmresWork& w_, int op_, int nrhs_, const double2* b_, double2* x_, std::vector<double> tol_,
+           int maxit_, int restart_, GmresResult& res_)
+      : c(c_), w(w_), op(op_), nrhs(nrhs_), b(b_), x(x_), tol(std::move(tol_)), maxit(maxit_), restart(restart_),
+        res(res_) {
     s = c->stream;
     N = c->t.N;
     ldh = restart + 1;
     ldv = (int64_t)ldh * N;
     gN = dim3((N + 255) / 256, nrhs);
     gblk = (N + GV_ROWS - 1) / GV_ROWS;
-    d_all = w.active + w.nrhs;   // all-ones mask (set at allocation)
-    pin_act = w.pin;
-    pin_upd = w.pin + nrhs;
-    pin_jm = w.pin + 2 * nrhs;
+    d_all = w.active + w.nrhs;   // all-ones mask (set when the workspace is bound)
     act.assign(nrhs, 1);
     jdone.assign(nrhs, 0);
   }
 
-  hipError_t put_mask(int* dst, int* stage, const std::vector<int>& v) {
-    std::copy(v.begin(), v.end(), stage);
-    return hipMemcpyAsync(dst, stage, nrhs * 4, hipMemcpyHostToDevice, s);
+  // host values to the device through kernel arguments, 32 per launch: no
+  // staging memory, and a captured launch keeps its values
+  hipError_t put_mask(int* dst, const std::vector<int>& v) {
+    for (int i0 = 0; i0 < nrhs; i0 += 32) {
+      IntChunk ch;
+      const int n = std::min(32, nrhs - i0);
+      for (int i = 0; i < 32; ++i) ch.v[i] = i < n ? v[i0 + i] : 0;
+      hipLaunchKernelGGL(k_put_ints, dim3(1), dim3(32), 0, s, n, ch, dst + i0);
+    }
+    return hipGetLastError();
   }
 
   // ||b||; zero right-hand sides give x = 0
@@ -745,7 +755,8 @@ struct GmresRun {
       if (bn[r] == 0.0) {
         res.conv[r] = 1;
         act[r] = 0;
-        AIM_HIP_CHECK(hipMemsetAsync(x + (size_t)r * N, 0, (size_t)N * 16, s));
+        hipLaunchKernelGGL(k_zero_words, dim3((N + 255) / 256), dim3(256), 0, s, (size_t)N * 2,
+                           (uint64_t*)(x + (size_t)r * N));
       }
     phase = TOP;
     return AIM_OK;
@@ -757,7 +768,7 @@ struct GmresRun {
     TRY(matvec(c, op, nrhs, x, N, w.W, N));
     res.matvecs++;
     hipLaunchKernelGGL(k_bminus, gN, dim3(256), 0, s, N, b, w.W);
-    AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
+    AIM_HIP_CHECK(put_mask(w.active, act));
     TRY(norms(c, w, nrhs, w.W, N, w.active, w.nrm));
     std::vector<double2> h0(nrhs);
     AIM_HIP_CHECK(hipMemcpyAsync(h0.data(), w.nrm, nrhs * 16, hipMemcpyDeviceToHost, s));
@@ -768,14 +779,14 @@ struct GmresRun {
       const double rel = std::sqrt(h0[r].x) / bn[r];
       if (!std::isfinite(rel)) return AIM_E_NUMERIC;
       res.est[r] = rel;
-      if (rel <= tol) { act[r] = 0; res.conv[r] = 1; }
+      if (rel <= tol[r]) { act[r] = 0; res.conv[r] = 1; }
       else any = true;
     }
     if (!any || total >= maxit) {
       phase = DONE;
       return AIM_OK;
     }
-    AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
+    AIM_HIP_CHECK(put_mask(w.active, act));
     hipLaunchKernelGGL(k_normalize, gN, dim3(256), 0, s, N, w.nrm, w.W, (int64_t)N, w.V, ldv, w.active);
     hipLaunchKernelGGL(k_set_g0, dim3((nrhs + 63) / 64), dim3(64), 0, s, nrhs, ldh, w.nrm, w.active, w.g);
     std::fill(jdone.begin(), jdone.end(), 0);
@@ -792,6 +803,11 @@ struct GmresRun {
   // one Arnoldi step: w = A u_j, reduction pass, update pass
   aim_status arnoldi_step() {
     TRY(matvec(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
+    return orthogonalise();
+  }
+
+  // the passes of step j after its operator application w = A u_j
+  aim_status orthogonalise() {
     res.matvecs++;
     hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0, s,
                        N, j, w.V, ldv, w.W, (int64_t)N, w.active, w.part, w.nchunk, ldh, w.Hu, w.coef, w.hp);
@@ -800,6 +816,28 @@ struct GmresRun {
     AIM_HIP_CHECK(hipGetLastError());
     total++;
     ++j;
+    return AIM_OK;
+  }
+
+  // The grouped step (solver_step): an Arnoldi step whose operator
+  // application is split at its column pass, which runs in one launch with
+  // other solvers' (same kernels, same order of this solver's work as
+  // arnoldi_step).  at_step: the next action is an Arnoldi step.
+  bool at_step() const { return phase == ARNOLDI && batch && j < jend; }
+  aim_status step_pre(ColsJob* job) { return matvec_pre(c, op, nrhs, w.V + (size_t)j * N, ldv, job); }
+  aim_status step_post() {
+    TRY(matvec_post(c, op, nrhs, w.V + (size_t)j * N, ldv, w.W, N));
+    TRY(orthogonalise());
+    return after_step();
+  }
+
+  // after a step: the check that closes a completed batch
+  aim_status after_step() {
+    if (j < jend) return AIM_OK;
+    batch = false;
+    bool over = false;
+    TRY(close_batch(over));
+    if (over) TRY(end_cycle());
     return AIM_OK;
   }
 
@@ -830,10 +868,10 @@ struct GmresRun {
       AIM_HIP_CHECK(hipGetLastError());
       a = e;
     }
-    for (int r = 0; r < nrhs; ++r)
-      if (act[r])
-        AIM_HIP_CHECK(hipMemcpyAsync(w.host_resid + (size_t)r * restart + jfin, w.resid + (size_t)r * restart + jfin,
-                                     (size_t)(c1 - jfin) * 8, hipMemcpyDeviceToHost, s));
+    // residual estimates jfin .. c1-1 of every rhs in one strided copy
+    AIM_HIP_CHECK(hipMemcpy2DAsync(w.host_resid.data() + jfin, (size_t)restart * 8, w.resid + jfin,
+                                   (size_t)restart * 8, (size_t)(c1 - jfin) * 8, (size_t)nrhs, hipMemcpyDeviceToHost,
+                                   s));
     AIM_HIP_CHECK(hipStreamSynchronize(s));
     bool left = false, changed = false;
     for (int r = 0; r < nrhs; ++r) {
@@ -844,7 +882,7 @@ struct GmresRun {
         const double rel = w.host_resid[(size_t)r * restart + jj] / bn[r];
         if (!std::isfinite(rel)) return AIM_E_NUMERIC;
         res.est[r] = rel;
-        if (rel <= tol) { act[r] = 0; changed = true; break; }
+        if (rel <= tol[r]) { act[r] = 0; changed = true; break; }
       }
       if (act[r]) left = true;
     }
@@ -853,7 +891,7 @@ struct GmresRun {
       over = true;
       return AIM_OK;
     }
-    if (changed) AIM_HIP_CHECK(put_mask(w.active, pin_act, act));
+    if (changed) AIM_HIP_CHECK(put_mask(w.active, act));
     return AIM_OK;
   }
 
@@ -862,8 +900,8 @@ struct GmresRun {
     std::vector<int> upd(nrhs, 0);
     for (int r = 0; r < nrhs; ++r) upd[r] = (cyc[r] && jdone[r] > 0) ? 1 : 0;
     int* d_jm = (int*)w.part;   // scratch: jm then mask
-    AIM_HIP_CHECK(put_mask(d_jm, pin_jm, jdone));
-    AIM_HIP_CHECK(put_mask(w.active, pin_upd, upd));
+    AIM_HIP_CHECK(put_mask(d_jm, jdone));
+    AIM_HIP_CHECK(put_mask(w.active, upd));
     hipLaunchKernelGGL(k_trisolve, dim3(nrhs), dim3(256), (size_t)ldh * 16, s, nrhs, ldh, d_jm, w.H, w.g, w.y);
     int jmax = 0;
     for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jdone[r]);
@@ -890,7 +928,7 @@ struct GmresRun {
       for (int r = 0; r < nrhs; ++r)
         if (bn[r] > 0) {
           res.est[r] = std::sqrt(h0[r].x) / bn[r];
-          res.conv[r] = res.est[r] <= tol;
+          res.conv[r] = res.est[r] <= tol[r];
         }
       phase = DONE;
     } else {
@@ -920,12 +958,8 @@ struct GmresRun {
         if (steps <= 0) return AIM_OK;
         TRY(arnoldi_step());
         --steps;
-        if (j < jend) continue;
       }
-      batch = false;
-      bool over = false;
-      TRY(close_batch(over));
-      if (over) TRY(end_cycle());
+      TRY(after_step());
     }
     return AIM_OK;
   }
@@ -1033,7 +1067,8 @@ struct SolveRun {
   aim_status begin() {
     TRY(system_rhs(c, w, form, nrhs, b, &rhs));
     if (precision == AIM_FP64) {
-      run.reset(new (std::nothrow) GmresRun(c, w, op, nrhs, rhs, x, tol, maxit, restart, gr));
+      run.reset(new (std::nothrow) GmresRun(c, w, op, nrhs, rhs, x, std::vector<double>(nrhs, tol), maxit, restart,
+                                            gr));
       if (!run) return AIM_E_OOM;
       TRY(run->start());
       phase = FP64_RUN;
@@ -1043,7 +1078,11 @@ struct SolveRun {
     return AIM_OK;
   }
 
-  // refinement: FP64 residual, FP32-grid inner GMRES on it
+  // refinement: FP64 residual, FP32-grid inner GMRES on it.  Columns are
+  // refined independently: a converged column gets a zero inner right-hand
+  // side (its correction is zero and it takes no steps), and each column's
+  // inner tolerance follows its own residual, so a column's result does not
+  // depend on the other columns of the batch.
   aim_status mix_check() {
     if (outer >= 30) {
       phase = FINAL;
@@ -1055,11 +1094,9 @@ struct SolveRun {
     TRY(true_resid(c, w, op, nrhs, rhs, x, rel));
     matvecs++;
     bool done = true;
-    double worst = 0;
     for (int r = 0; r < nrhs; ++r) {
       if (!std::isfinite(rel[r])) return AIM_E_NUMERIC;
       if (rel[r] > tol) done = false;
-      worst = std::max(worst, rel[r]);
       est[r] = rel[r];
       conv[r] = rel[r] <= tol;
     }
@@ -1069,14 +1106,22 @@ struct SolveRun {
       phase = FINAL;
       return AIM_OK;
     }
-    // r = b - A x (left in w.W by true_resid), d = 0; the inner solve works on
-    // its own copy of the residual (it reads w.r, writes w.d)
+    // r = b - A x (left in w.W by true_resid), zero for converged columns;
+    // d = 0.  The inner solve reads w.r and writes w.d.
     AIM_HIP_CHECK(hipMemcpyAsync(w.r, w.W, (size_t)N * nrhs * 16, hipMemcpyDeviceToDevice, s));
-    AIM_HIP_CHECK(hipMemsetAsync(w.d, 0, (size_t)N * nrhs * 16, s));
-    const double tin = std::max(tin_min, 0.5 * tol / worst);
+    std::vector<double> tin(nrhs, 0.5);
+    for (int r = 0; r < nrhs; ++r) {
+      if (conv[r])
+        hipLaunchKernelGGL(k_zero_words, dim3((N + 255) / 256), dim3(256), 0, s, (size_t)N * 2,
+                           (uint64_t*)(w.r + (size_t)r * N));
+      else
+        tin[r] = std::min(std::max(tin_min, 0.5 * tol / rel[r]), 0.5);
+    }
+    hipLaunchKernelGGL(k_zero_words, dim3(1024), dim3(256), 0, s, (size_t)N * nrhs * 2, (uint64_t*)w.d);
+    AIM_HIP_CHECK(hipGetLastError());
     gr = GmresResult();
-    run.reset(new (std::nothrow) GmresRun(c, w, op | AIM_OP_GRID_FP32, nrhs, w.r, w.d, std::min(tin, 0.5),
-                                          maxit - tot_it, restart, gr));
+    run.reset(new (std::nothrow) GmresRun(c, w, op | AIM_OP_GRID_FP32, nrhs, w.r, w.d, tin, maxit - tot_it, restart,
+                                          gr));
     if (!run) return AIM_E_OOM;
     TRY(run->start());
     phase = MIX_INNER;
@@ -1149,6 +1194,25 @@ struct SolveRun {
     return AIM_OK;
   }
 
+  // Grouped step (solver_step): the running GMRES is right before an
+  // Arnoldi step; step_pre runs its operator up to the column pass,
+  // step_post the rest of the step and whatever follows it up to the next
+  // step (as advance(1) does).  An error ends the solve with that status.
+  bool at_step() const { return (phase == FP64_RUN || phase == MIX_INNER) && run && run->at_step(); }
+  int step_op() const { return run->op; }
+  aim_status end_with(aim_status st) {
+    if (st != AIM_OK) {
+      status = st;
+      phase = DONE;
+    }
+    return st;
+  }
+  aim_status step_pre(ColsJob* job) { return end_with(run->step_pre(job)); }
+  aim_status step_post() {
+    TRY(end_with(run->step_post()));
+    return advance(0);
+  }
+
   void fill(aim_solve_info* info, double secs) const {
     const bool fin = phase == DONE && tr.size() == (size_t)nrhs;
     for (int r = 0; r < nrhs; ++r) {
@@ -1171,7 +1235,9 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
                  int restart, aim_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();
   TRY(check_solve(c, form, precision, nrhs, tol, maxit, restart));
-  TRY(ensure_work(c, restart, nrhs));
+  // the context's workspace, bound at set-up for max_rhs and max_restart
+  if (!c->gw.V) return AIM_E_STATE;
+  if (restart > c->gw.restart || nrhs > c->gw.nrhs) return AIM_E_ARG;
   SolveRun sr(c, c->gw, form, precision, nrhs, b, x, tol, maxit, restart);
   TRY(sr.begin());
   TRY(sr.advance(std::numeric_limits<long>::max()));
@@ -1193,31 +1259,31 @@ struct aim_solver_s {
   std::unique_ptr<aim::SolveRun> run;
   std::chrono::steady_clock::time_point t0;
   double seconds = 0;
+  hipEvent_t ev = nullptr;   // orders a grouped column pass across streams
 };
 
 namespace aim {
 
 static void solver_free(aim_solver_s* sv) {
   sv->run.reset();
-  sv->c->dev_bytes -= sv->w.bytes;
-  free_gmres_work(sv->w);
+  if (sv->ev) (void)hipEventDestroy(sv->ev);
   delete sv;
 }
 
 aim_status solver_begin(Ctx* c, int form, int precision, int nrhs, const double2* b, double2* x, double tol,
-                        int maxit, int restart, aim_solver_s** out) {
+                        int maxit, int restart, void* workspace, size_t workspace_bytes, aim_solver_s** out) {
   TRY(check_solve(c, form, precision, nrhs, tol, maxit, restart));
   aim_solver_s* sv = new (std::nothrow) aim_solver_s();
   if (!sv) return AIM_E_OOM;
   sv->c = c;
   sv->t0 = std::chrono::steady_clock::now();
-  aim_status st = alloc_work(c, sv->w, restart, nrhs);
+  // the caller's workspace (device memory it owns until aim_solver_end)
+  aim_status st = bind_gmres_work(c, sv->w, workspace, workspace_bytes, restart, nrhs);
+  if (st == AIM_OK && hipEventCreateWithFlags(&sv->ev, hipEventDisableTiming) != hipSuccess) st = AIM_E_HIP;
   if (st != AIM_OK) {
-    free_gmres_work(sv->w);
-    delete sv;
+    solver_free(sv);
     return st;
   }
-  c->dev_bytes += sv->w.bytes;
   sv->run.reset(new (std::nothrow) SolveRun(c, sv->w, form, precision, nrhs, b, x, tol, maxit, restart));
   st = sv->run ? sv->run->begin() : AIM_E_OOM;
   if (st != AIM_OK) {
@@ -1229,16 +1295,89 @@ aim_status solver_begin(Ctx* c, int form, int precision, int nrhs, const double2
   return AIM_OK;
 }
 
+// One Arnoldi step for each unfinished solver.  Solvers whose next step
+// applies an operator with a single grid product (TM, S, S^alpha, N,
+// N^alpha; FP64 or FP32 grid), on contexts that no other solver of this
+// call uses, are grouped by spectrum: their column passes run as one
+// launch over all members' tiles, which reads the shared spectrum once.
+// The launch waits for the members' forward row passes (events across
+// their streams) and their inverse row passes wait for it.  Every other
+// solver takes its step alone.  Each tile is computed as in a step alone,
+// so results do not depend on the grouping.
 aim_status solver_step(aim_solver_s** group, int count) {
   if (count < 0 || (count > 0 && !group)) return AIM_E_ARG;
   aim_status first = AIM_OK;
-  for (int i = 0; i < count; ++i) {
-    aim_solver_s* sv = group[i];
-    if (!sv || sv->run->phase == SolveRun::DONE) continue;
-    const aim_status st = sv->run->advance(1);
-    if (sv->run->phase == SolveRun::DONE)
+  auto note = [&](aim_solver_s* sv, aim_status st) {
+    if (sv->run->phase == SolveRun::DONE && sv->seconds == 0.0)
       sv->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
     if (st != AIM_OK && first == AIM_OK) first = st;
+  };
+  std::vector<aim_solver_s*> live;
+  for (int i = 0; i < count; ++i)
+    if (group[i] && group[i]->run->phase != SolveRun::DONE) live.push_back(group[i]);
+  // contexts stepped by more than one solver here share work buffers: those
+  // solvers step alone, in call order
+  std::vector<aim_solver_s*> solo, cand;
+  for (aim_solver_s* sv : live) {
+    int uses = 0;
+    for (aim_solver_s* o : live) uses += o->c == sv->c;
+    (uses > 1 ? solo : cand).push_back(sv);
+  }
+  for (aim_solver_s* sv : solo) note(sv, sv->run->advance(1));
+  // position the others right before their next Arnoldi step
+  std::vector<aim_solver_s*> split;
+  for (aim_solver_s* sv : cand) {
+    aim_status st = sv->run->advance(0);
+    if (st != AIM_OK || sv->run->phase == SolveRun::DONE) {
+      note(sv, st);
+      continue;
+    }
+    if (sv->run->at_step() && matvec_splits(sv->c, sv->run->step_op())) split.push_back(sv);
+    else note(sv, sv->run->advance(1));
+  }
+  // forward halves of the split steps
+  std::vector<ColsJob> jobs(split.size());
+  std::vector<aim_solver_s*> ok;
+  std::vector<ColsJob> okjobs;
+  for (size_t i = 0; i < split.size(); ++i) {
+    aim_status st = split[i]->run->step_pre(&jobs[i]);
+    if (st != AIM_OK) note(split[i], st);
+    else {
+      ok.push_back(split[i]);
+      okjobs.push_back(jobs[i]);
+    }
+  }
+  // column passes, one launch per spectrum
+  std::vector<char> taken(ok.size(), 0);
+  for (size_t i = 0; i < ok.size(); ++i) {
+    if (taken[i]) continue;
+    std::vector<size_t> mem;
+    for (size_t k = i; k < ok.size(); ++k)
+      if (!taken[k] && okjobs[k].Cq == okjobs[i].Cq && okjobs[k].n == okjobs[i].n && okjobs[k].f32 == okjobs[i].f32) {
+        mem.push_back(k);
+        taken[k] = 1;
+      }
+    hipStream_t lead = ok[mem[0]]->c->stream;
+    aim_status st = AIM_OK;
+    for (size_t q = 1; q < mem.size() && st == AIM_OK; ++q) {
+      aim_solver_s* sv = ok[mem[q]];
+      if (sv->c->stream == lead) continue;
+      if (hipEventRecord(sv->ev, sv->c->stream) != hipSuccess || hipStreamWaitEvent(lead, sv->ev, 0) != hipSuccess)
+        st = AIM_E_HIP;
+    }
+    std::vector<ColsJob> gj;
+    for (size_t k : mem) gj.push_back(okjobs[k]);
+    if (st == AIM_OK) st = launch_cols_jobs(gj.data(), (int)gj.size(), lead);
+    aim_solver_s* l = ok[mem[0]];
+    if (st == AIM_OK && mem.size() > 1 && hipEventRecord(l->ev, lead) != hipSuccess) st = AIM_E_HIP;
+    for (size_t q = 1; q < mem.size() && st == AIM_OK; ++q) {
+      aim_solver_s* sv = ok[mem[q]];
+      if (sv->c->stream != lead && hipStreamWaitEvent(sv->c->stream, l->ev, 0) != hipSuccess) st = AIM_E_HIP;
+    }
+    for (size_t k : mem) {
+      aim_solver_s* sv = ok[k];
+      note(sv, st != AIM_OK ? sv->run->end_with(st) : sv->run->step_post());
+    }
   }
   return first;
 }

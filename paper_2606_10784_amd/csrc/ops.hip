@@ -31,6 +31,10 @@ aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int ldt, int pairs,
                        const cplx<T>* tw, hipStream_t s, hipEvent_t ev_start = nullptr,
                        hipEvent_t ev_stop = nullptr);
 aim_status launch_rows_fft_inplace(int n, double2* A, const double2* tw, hipStream_t s);
+template <typename T>
+aim_status launch_cols_group(int n, int count, void* const* tiles, const int* nr, const int* ldt,
+                             const cplx<T>* Cq, const cplx<T>* tw, hipStream_t s);
+int col_block(int n, bool f32);
 
 static constexpr double kPi = 3.14159265358979323846264338327950288;
 static constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
@@ -1173,6 +1177,8 @@ aim_status setup_device(Ctx* c) {
   TRY(dev_alloc(c, (void**)&c->d_tmp1, (size_t)N * c->max_rhs * 16));
   TRY(dev_alloc(c, (void**)&c->d_tmp2, (size_t)N * c->max_rhs * 16));
   TRY(dev_alloc(c, (void**)&c->d_rhs, (size_t)N * c->max_rhs * 16));
+  TRY(dev_alloc(c, (void**)&c->d_phi, (size_t)AIM_MAX_RHS * 8));
+  TRY(dev_alloc(c, (void**)&c->d_dot, (size_t)c->max_rhs * 24));   // sums, then the values
   TRY(dev_alloc(c, (void**)&c->d_red, (size_t)std::max(5 * N, 64) * std::max(c->max_rhs, 1) * 8));
   AIM_HIP_CHECK(hipStreamSynchronize(s));
   return AIM_OK;
@@ -1247,15 +1253,27 @@ aim_status apply_filter_analytic(Ctx* c, double alpha) {
   return AIM_OK;
 }
 
-// grid part: V = [F^-1 (Chat . F(Lambda x))]_restr for nch channels
+// grid part: V = [F^-1 (Chat . F(Lambda x))]_restr for nch channels, in
+// three steps: anterpolation and forward row FFTs (grid_pre), the column
+// pass (launch_cols, or one grouped launch for several contexts), inverse
+// row FFTs (grid_post)
 template <typename T>
-static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int nrhs, const double2* x,
-                             int64_t ldx) {
+static const cplx<T>* grid_spectrum(Ctx* c, bool filt) {
+  const bool f32 = sizeof(T) == 4;
+  return f32 ? (const cplx<T>*)(filt ? (void*)c->d_Caf : (void*)c->d_Cf)
+             : (const cplx<T>*)(filt ? (void*)c->d_Ca : (void*)c->d_C);
+}
+template <typename T>
+static const cplx<T>* grid_twiddles(Ctx* c) {
+  return sizeof(T) == 4 ? (const cplx<T>*)c->d_twf : (const cplx<T>*)c->d_tw;
+}
+
+template <typename T>
+static aim_status grid_pre(Ctx* c, const int* chans, int nch, int nrhs, const double2* x, int64_t ldx) {
   HostTables& t = c->t;
   hipStream_t s = c->stream;
   const int pairs = nch * nrhs;
   cplx<T>* U = (cplx<T>*)c->d_U;
-  cplx<T>* V = (cplx<T>*)c->d_V;
   cplx<T>* Tb = (cplx<T>*)c->d_T;
   const bool f32 = sizeof(T) == 4;
   dim3 ga((unsigned)(((size_t)t.n_act * 16 + 255) / 256), pairs);
@@ -1272,24 +1290,32 @@ static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int n
   }
   }
   AIM_HIP_CHECK(hipGetLastError());
-  const cplx<T>* tw = f32 ? (const cplx<T>*)c->d_twf : (const cplx<T>*)c->d_tw;
-  const cplx<T>* Cq = f32 ? (const cplx<T>*)(filt ? (void*)c->d_Caf : (void*)c->d_Cf)
-                          : (const cplx<T>*)(filt ? (void*)c->d_Ca : (void*)c->d_C);
-  {
-    ProfScope ps(c, AIM_K_ROWS_FWD);
-    TRY(launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, tile_rows(t.nr), pairs, Tb, tw, s));
-  }
+  ProfScope ps(c, AIM_K_ROWS_FWD);
+  return launch_rows_fwd<T>(t.n, U, t.n_act, c->d_row_ptr, c->d_act_ix, t.nr, tile_rows(t.nr), pairs, Tb,
+                            grid_twiddles<T>(c), s);
+}
+
+template <typename T>
+static aim_status grid_post(Ctx* c, int nch, int nrhs) {
+  HostTables& t = c->t;
+  ProfScope ps(c, AIM_K_ROWS_INV);
+  return launch_rows_inv<T>(t.n, (cplx<T>*)c->d_T, t.nr, tile_rows(t.nr), c->d_row_ptr, c->d_act_ix, nch * nrhs,
+                            (cplx<T>*)c->d_V, t.n_act, grid_twiddles<T>(c), c->stream);
+}
+
+template <typename T>
+static aim_status grid_apply(Ctx* c, const int* chans, int nch, bool filt, int nrhs, const double2* x,
+                             int64_t ldx) {
+  HostTables& t = c->t;
+  TRY(grid_pre<T>(c, chans, nch, nrhs, x, ldx));
   {
     // the dominant kernel's sampled launches carry their events in the
     // dispatch itself, so the interval is the kernel's own execution
     ProfScope ps(c, AIM_K_COLS, true);
-    TRY(launch_cols<T>(t.n, 0, Tb, t.nr, tile_rows(t.nr), pairs, Cq, tw, s, ps.start(), ps.stop()));
+    TRY(launch_cols<T>(t.n, 0, (cplx<T>*)c->d_T, t.nr, tile_rows(t.nr), nch * nrhs, grid_spectrum<T>(c, filt),
+                       grid_twiddles<T>(c), c->stream, ps.start(), ps.stop()));
   }
-  {
-    ProfScope ps(c, AIM_K_ROWS_INV);
-    TRY(launch_rows_inv<T>(t.n, Tb, t.nr, tile_rows(t.nr), c->d_row_ptr, c->d_act_ix, pairs, V, t.n_act, tw, s));
-  }
-  return AIM_OK;
+  return grid_post<T>(c, nch, nrhs);
 }
 
 template <typename T, int LANES>
@@ -1542,20 +1568,122 @@ aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, doubl
   return AIM_E_ARG;
 }
 
+// ---------------------------------------------------------------------------
+// matvec split at its column pass (the grouped solver step): operators with
+// one grid product run as matvec_pre -> column pass -> matvec_post, and the
+// column passes of several contexts that share a spectrum go into one
+// launch (launch_cols_jobs).  Each tile is computed as by matvec.
+// ---------------------------------------------------------------------------
+static bool split_parts(Ctx* c, int op, const int** chans, int* nch, bool* filt, bool* near, double* sg,
+                        double2* scale) {
+  static const int chS[1] = {0};
+  static const int chN[3] = {1, 2, 3};
+  const int base = op & 0xff;
+  const bool hat = c->t.basis == AIM_HAT;
+  *scale = make_double2(1.0, 0.0);
+  switch (base) {
+    case AIM_OP_S: case AIM_OP_S_ALPHA: case AIM_OP_TM:
+      if (base == AIM_OP_TM && hat) return false;
+      *chans = chS; *nch = 1; *sg = 0.0;
+      *filt = base == AIM_OP_S_ALPHA;
+      *near = !*filt;
+      if (base == AIM_OP_TM) *scale = make_double2(0.0, c->t.k * c->t.eta);
+      break;
+    case AIM_OP_N: case AIM_OP_N_ALPHA:
+      if (!hat) return false;
+      *chans = chN; *nch = 3; *sg = -c->t.k * c->t.k;
+      *filt = base == AIM_OP_N_ALPHA;
+      *near = !*filt;
+      break;
+    default:
+      return false;
+  }
+  if (c->t.node_order != 0 && *near) return false;
+  if ((op & AIM_OP_GRID_FP32) && c->precision != AIM_MIXED) return false;
+  return true;
+}
+
+bool matvec_splits(Ctx* c, int op) {
+  const int* ch; int nch; bool filt, near; double sg; double2 sc;
+  return split_parts(c, op, &ch, &nch, &filt, &near, &sg, &sc);
+}
+
+aim_status matvec_pre(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, ColsJob* job) {
+  const int* ch; int nch; bool filt, near; double sg; double2 sc;
+  if (nrhs < 1 || nrhs > c->max_rhs || !split_parts(c, op, &ch, &nch, &filt, &near, &sg, &sc)) return AIM_E_ARG;
+  const bool f32 = (op & AIM_OP_GRID_FP32) != 0;
+  job->n = c->t.n;
+  job->nr = c->t.nr;
+  job->ldt = tile_rows(c->t.nr);
+  job->pairs = nch * nrhs;
+  job->f32 = f32;
+  job->tiles = c->d_T;
+  if (f32) {
+    job->Cq = grid_spectrum<float>(c, filt);
+    job->tw = grid_twiddles<float>(c);
+    return grid_pre<float>(c, ch, nch, nrhs, x, ldx);
+  }
+  job->Cq = grid_spectrum<double>(c, filt);
+  job->tw = grid_twiddles<double>(c);
+  return grid_pre<double>(c, ch, nch, nrhs, x, ldx);
+}
+
+aim_status matvec_post(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy) {
+  const int* ch; int nch; bool filt, near; double sg; double2 sc;
+  if (!split_parts(c, op, &ch, &nch, &filt, &near, &sg, &sc)) return AIM_E_ARG;
+  const double2* Cn = near ? (nch == 1 ? c->d_CS : c->d_CN) : nullptr;
+  if (op & AIM_OP_GRID_FP32) {
+    TRY(grid_post<float>(c, nch, nrhs));
+    return interp<float>(c, ch, nch, sg, near, Cn, nrhs, x, ldx, y, ldy, sc);
+  }
+  TRY(grid_post<double>(c, nch, nrhs));
+  return interp<double>(c, ch, nch, sg, near, Cn, nrhs, x, ldx, y, ldy, sc);
+}
+
+// One column pass over the tile sets of `count` jobs with the same spectrum,
+// twiddles, n and precision, in launches of up to ColBatch::kMax pairs.
+aim_status launch_cols_jobs(const ColsJob* jobs, int count, hipStream_t s) {
+  if (count < 1) return AIM_OK;
+  const int n = jobs[0].n;
+  const bool f32 = jobs[0].f32;
+  const int cb = col_block(n, f32);
+  if (cb <= 0) return AIM_E_ARG;
+  std::vector<void*> tiles;
+  std::vector<int> nr, ldt;
+  for (int i = 0; i < count; ++i) {
+    const ColsJob& j = jobs[i];
+    if (j.n != n || j.f32 != f32 || j.Cq != jobs[0].Cq) return AIM_E_ARG;
+    const size_t pair_bytes = (size_t)(n / cb) * j.ldt * cb * (f32 ? 8 : 16);
+    for (int p = 0; p < j.pairs; ++p) {
+      tiles.push_back((char*)j.tiles + p * pair_bytes);
+      nr.push_back(j.nr);
+      ldt.push_back(j.ldt);
+    }
+  }
+  const int total = (int)tiles.size();
+  for (int e0 = 0; e0 < total; e0 += kColBatchMax) {
+    const int cnt = std::min(kColBatchMax, total - e0);
+    if (f32)
+      TRY(launch_cols_group<float>(n, cnt, tiles.data() + e0, nr.data() + e0, ldt.data() + e0,
+                                   (const float2*)jobs[0].Cq, (const float2*)jobs[0].tw, s));
+    else
+      TRY(launch_cols_group<double>(n, cnt, tiles.data() + e0, nr.data() + e0, ldt.data() + e0,
+                                    (const double2*)jobs[0].Cq, (const double2*)jobs[0].tw, s));
+  }
+  return AIM_OK;
+}
+
+// The angles go to the context's buffer; the call waits for the copy, so
+// the caller's host array is free on return.
 aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b) {
   HostTables& t = c->t;
   if (nrhs < 1 || nrhs > AIM_MAX_RHS) return AIM_E_ARG;
-  double* d_phi = nullptr;
-  AIM_HIP_CHECK(hipMalloc(&d_phi, (size_t)nrhs * 8));
-  hipError_t e = hipMemcpyAsync(d_phi, phi_host, (size_t)nrhs * 8, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_rhs, dim3((t.N + 127) / 128, nrhs), dim3(128), 0, c->stream, t.N, nrhs, t.basis, t.p,
-                       c->d_glx, c->d_glw, c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, d_phi, t.k, t.eta, amp, b);
-    e = hipGetLastError();
-  }
-  const hipError_t es = hipStreamSynchronize(c->stream);
-  (void)hipFree(d_phi);
-  return e == hipSuccess && es == hipSuccess ? AIM_OK : AIM_E_HIP;
+  AIM_HIP_CHECK(hipMemcpyAsync(c->d_phi, phi_host, (size_t)nrhs * 8, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_rhs, dim3((t.N + 127) / 128, nrhs), dim3(128), 0, c->stream, t.N, nrhs, t.basis, t.p,
+                     c->d_glx, c->d_glw, c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, c->d_phi, t.k, t.eta, amp, b);
+  AIM_HIP_CHECK(hipGetLastError());
+  AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
+  return AIM_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1633,21 +1761,34 @@ aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host,
   return AIM_OK;
 }
 
-aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma) {
+// sigma_r = scale |dot_r|^2
+__global__ void k_sigma(int nrhs, double scale, const double2* __restrict__ dot, double* __restrict__ sigma) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) sigma[r] = scale * (dot[r].x * dot[r].x + dot[r].y * dot[r].y);
+}
+
+// sigma_r = (k eta^2 / 4) |sum_j b_j(phi_r) J_jr|^2 with b the plane-wave
+// right-hand side of unit amplitude, on device buffers phi_dev (nrhs
+// angles), b_dev (N x nrhs), dot_dev (nrhs sums) and sig_dev (nrhs values);
+// the values go to sigma_host, nothing else touches host memory
+aim_status rcs_into(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma_host, double* phi_dev,
+                    double2* b_dev, double2* dot_dev, double* sig_dev) {
   HostTables& t = c->t;
-  if (t.basis != AIM_PULSE || nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
-  TRY(rhs_planewave(c, nrhs, phi_host, 1.0, c->d_rhs));
-  double* d_out = nullptr;
-  AIM_HIP_CHECK(hipMalloc(&d_out, nrhs * 16));
-  hipLaunchKernelGGL(k_dotu_cols, dim3(nrhs), dim3(256), 0, c->stream, t.N, c->d_rhs, J, d_out);
-  std::vector<double> h(2 * nrhs);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_out, nrhs * 16, hipMemcpyDeviceToHost, c->stream);
-  const hipError_t es = hipStreamSynchronize(c->stream);
-  (void)hipFree(d_out);
-  if (e != hipSuccess || es != hipSuccess) return AIM_E_HIP;
-  for (int r = 0; r < nrhs; ++r) sigma[r] = t.k * t.eta * t.eta / 4.0 * (h[2 * r] * h[2 * r] + h[2 * r + 1] * h[2 * r + 1]);
+  AIM_HIP_CHECK(hipMemcpyAsync(phi_dev, phi_host, (size_t)nrhs * 8, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_rhs, dim3((t.N + 127) / 128, nrhs), dim3(128), 0, c->stream, t.N, nrhs, t.basis, t.p,
+                     c->d_glx, c->d_glw, c->d_vx, c->d_vy, c->d_h, c->d_tx, c->d_ty, phi_dev, t.k, t.eta, 1.0, b_dev);
+  hipLaunchKernelGGL(k_dotu_cols, dim3(nrhs), dim3(256), 0, c->stream, t.N, b_dev, J, (double*)dot_dev);
+  hipLaunchKernelGGL(k_sigma, dim3((nrhs + 255) / 256), dim3(256), 0, c->stream, nrhs, t.k * t.eta * t.eta / 4.0,
+                     dot_dev, sig_dev);
+  AIM_HIP_CHECK(hipGetLastError());
+  AIM_HIP_CHECK(hipMemcpyAsync(sigma_host, sig_dev, (size_t)nrhs * 8, hipMemcpyDeviceToHost, c->stream));
+  AIM_HIP_CHECK(hipStreamSynchronize(c->stream));
   return AIM_OK;
+}
+
+aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma) {
+  if (c->t.basis != AIM_PULSE || nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
+  return rcs_into(c, nrhs, J, phi_host, sigma, c->d_phi, c->d_rhs, c->d_dot, (double*)(c->d_dot + c->max_rhs));
 }
 
 aim_status eval_green(Ctx* c, int n, const double* R, double2* out) {

@@ -49,6 +49,40 @@ class ServeResult:
         return self.finish - self.arrival
 
 
+def describe(res: ServeResult, req):
+    """Sizes of the request, recorded at arrival."""
+    res.n, res.m, res.nrhs, res.precision = len(req.xy), req.m, len(req.phis), req.precision
+
+
+def log_line(res: ServeResult):
+    """One JSON line per finished request: times in seconds from the start
+    of the run, sizes, precision and solver counts."""
+    import json
+    f = lambda v: None if (isinstance(v, float) and math.isnan(v)) else v
+    return json.dumps({"rid": res.rid, "arrival": f(res.arrival), "admit": f(res.admit), "finish": f(res.finish),
+                       "latency": f(res.latency), "status": res.status, "N": res.n, "m": res.m, "R": res.nrhs,
+                       "precision": "mixed" if res.precision else "fp64", "iterations": res.iterations,
+                       "matvecs": res.matvecs, "resid": f(res.resid)})
+
+
+class RequestLog:
+    """Appends log_line of each finished request to a JSONL file (thread-safe)."""
+
+    def __init__(self, path):
+        self.path = path
+        self.lock = threading.Lock()
+        self.n = 0
+        if path:
+            open(path, "w").close()
+
+    def write(self, res: ServeResult):
+        if not self.path:
+            return
+        with self.lock, open(self.path, "a") as fh:
+            fh.write(log_line(res) + "\n")
+            self.n += 1
+
+
 def gpu_footprint(req, restart):
     from . import aim
     return aim.aim_footprint_bytes(req.xy, req.k, req.eta, req.basis, req.m, req.eps,
@@ -83,7 +117,7 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             prec = aim.AIM_MIXED if req.precision else aim.AIM_FP64
             ctx = aim.Context(req.xy, req.k, req.eta, req.basis, req.m, req.eps, precision=prec,
-                              max_rhs=len(req.phis), stream=stream)
+                              max_rhs=len(req.phis), stream=stream, max_restart=self.restart)
             try:
                 b = ctx.rhs_planewave(np.asarray(req.phis, dtype=float))
                 x, info = ctx.solve("TM", b, tol=req.tol, maxit=self.maxit, restart=self.restart,
@@ -102,12 +136,13 @@ class GpuExecutor:
 
 
 class Server:
-    def __init__(self, executor, hbm_budget: int, slots: int = 4):
+    def __init__(self, executor, hbm_budget: int, slots: int = 4, log_path=None):
         self.exe = executor
         self.budget = int(hbm_budget)
         self.slots = int(slots)
         self.max_reserved = 0
         self.max_active = 0
+        self.log = RequestLog(log_path)
 
     def run(self, requests, realtime: bool = True):
         reqs = sorted(requests, key=lambda r: r.arrival)
@@ -126,6 +161,7 @@ class Server:
                 except Exception as e:               # failure is recorded, the loop goes on
                     res.status = f"error: {e}"
                 res.finish = time.perf_counter() - t0
+                self.log.write(res)
                 done.put(req.rid)
 
         threads = [threading.Thread(target=worker, daemon=True) for _ in range(self.slots)]
@@ -148,9 +184,11 @@ class Server:
                 r = reqs[nxt]
                 fp[r.rid] = self.exe.footprint(r)
                 results[r.rid].footprint = fp[r.rid]
+                describe(results[r.rid], r)
                 if fp[r.rid] > self.budget:
                     results[r.rid].status = "rejected"
                     results[r.rid].finish = now
+                    self.log.write(results[r.rid])
                     finished += 1
                 else:
                     pending.append(r)
@@ -188,14 +226,18 @@ class Server:
 
 class GpuStepEngine:
     """Step-wise requests for StepServer: set-up (context, right-hand sides,
-    aim solver) on the request's own stream, one Arnoldi step per round for
-    every running solver in one aim_solver_step call, retirement (monostatic
-    RCS, release)."""
+    aim solver with its caller-owned Krylov workspace) on the request's own
+    stream, one Arnoldi step per round for every running solver, retirement
+    (monostatic RCS, release).  group=True steps all running solvers in one
+    aim_solver_step call, which runs the column passes of requests that share
+    a grid-kernel spectrum (same grid, k eps and precision) as one launch;
+    group=False steps them one call each (no shared launches)."""
 
-    def __init__(self, restart=1000, maxit=4000, keep_solution=False):
+    def __init__(self, restart=1000, maxit=4000, keep_solution=False, group=True):
         self.restart = restart
         self.maxit = maxit
         self.keep = keep_solution
+        self.group = group
 
     def footprint(self, req):
         return gpu_footprint(req, self.restart)
@@ -206,11 +248,14 @@ class GpuStepEngine:
         stream = torch.cuda.Stream()            # default priority
         prec = aim.AIM_MIXED if req.precision else aim.AIM_FP64
         ctx = aim.Context(req.xy, req.k, req.eta, req.basis, req.m, req.eps, precision=prec,
-                          max_rhs=len(req.phis), stream=stream)
+                          max_rhs=len(req.phis), stream=stream, max_restart=0)
         try:
+            # b and the initial guess are queued on the request's stream, the
+            # one the library's work runs on
             with torch.cuda.stream(stream):
                 b = ctx.rhs_planewave(np.asarray(req.phis, dtype=float))
-            solver = aim.Solver(ctx, "TM", b, tol=req.tol, maxit=self.maxit, restart=self.restart, precision=prec)
+                solver = aim.Solver(ctx, "TM", b, tol=req.tol, maxit=self.maxit, restart=self.restart,
+                                    precision=prec)
         except Exception:
             stream.synchronize()
             ctx.close()
@@ -219,7 +264,11 @@ class GpuStepEngine:
 
     def step(self, jobs):
         from . import aim
-        aim.aim_solver_step([j["solver"] for j in jobs])
+        if self.group:
+            aim.aim_solver_step([j["solver"] for j in jobs])
+        else:
+            for j in jobs:
+                aim.aim_solver_step([j["solver"]])
 
     def done(self, job):
         from . import aim
@@ -261,7 +310,7 @@ class StepServer:
     step, then retires the finished ones, so a request that arrives while
     others run starts stepping with them at the next round."""
 
-    def __init__(self, engine, hbm_budget: int, slots: int = 8, setup_workers: int = 2):
+    def __init__(self, engine, hbm_budget: int, slots: int = 8, setup_workers: int = 2, log_path=None):
         self.eng = engine
         self.budget = int(hbm_budget)
         self.slots = int(slots)
@@ -269,6 +318,7 @@ class StepServer:
         self.max_reserved = 0
         self.max_active = 0
         self.rounds = 0
+        self.log = RequestLog(log_path)
 
     def run(self, requests, realtime: bool = True):
         from concurrent.futures import ThreadPoolExecutor
@@ -293,6 +343,7 @@ class StepServer:
             if status is not None:
                 results[rid].status = status
             results[rid].finish = time.perf_counter() - t0
+            self.log.write(results[rid])
 
         try:
             while finished < len(reqs):
@@ -305,9 +356,11 @@ class StepServer:
                     r = reqs[nxt]
                     fp[r.rid] = self.eng.footprint(r)
                     results[r.rid].footprint = fp[r.rid]
+                    describe(results[r.rid], r)
                     if fp[r.rid] > self.budget:
                         results[r.rid].status = "rejected"
                         results[r.rid].finish = now
+                        self.log.write(results[r.rid])
                         finished += 1
                     else:
                         pending.append(r)

@@ -29,7 +29,8 @@ def test_strerror_and_footprint_are_host_only():
     # on top of the per-context tables
     fp2 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=2)
     fp8 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, max_rhs=8)
-    assert fp2 > fp and fp8 - fp == 7 * (fp2 - fp)
+    # (up to the 256-byte alignment of the 18 workspace buffers)
+    assert fp2 > fp and abs((fp8 - fp) - 7 * (fp2 - fp)) <= 7 * 18 * 256
     # the Krylov space grows with the restart length, its Hessenberg part
     # quadratically
     f100 = aim.aim_footprint_bytes(w.xy, w.k, w.eta, 0, w.m, w.eps, restart=100)
@@ -109,4 +110,32 @@ def test_solver_calls_checked_on_the_host():
     assert lib.aim_solver_poll(None, None) == aim.AIM_E_ARG
     assert lib.aim_solver_end(None) == aim.AIM_E_ARG
     h = ctypes.c_void_p()
-    assert lib.aim_solver_begin(None, 0, 0, 1, None, None, 1e-6, 10, 10, ctypes.byref(h)) == aim.AIM_E_ARG
+    assert lib.aim_solver_begin(None, 0, 0, 1, None, None, 1e-6, 10, 10, None, 0, ctypes.byref(h)) == aim.AIM_E_ARG
+
+
+def test_workspace_size_and_checks_on_the_host():
+    """aim_workspace_bytes is host-only and holds the Krylov space (restart + 1
+    vectors per rhs) plus the quadratic Hessenberg part; aim_setup rejects a
+    misaligned or short caller workspace and max_restart outside 0..1000
+    before any device call."""
+    N = 16384
+    w100, w400 = aim.aim_workspace_bytes(N, 1, 100), aim.aim_workspace_bytes(N, 1, 400)
+    assert w100 >= 101 * N * 16 and w400 - w100 >= 300 * N * 16 + (401 ** 2 - 101 ** 2) * 16
+    assert aim.aim_workspace_bytes(N, 3, 100) > 3 * w100 - 3 * 4096
+    for bad in ((0, 1, 10), (N, 0, 10), (N, 1, 0), (N, 1, 1001), (N, aim.AIM_MAX_RHS + 1, 10)):
+        assert aim.aim_workspace_bytes(*bad) == 0
+    lib = aim._lib()
+    h = ctypes.c_void_p()
+    xy = wl.circle(0.5, 40)
+    need = aim.aim_workspace_bytes(40, 1, 20)
+    for kw in (dict(max_restart=-1), dict(max_restart=1001),
+               dict(max_restart=20, workspace=256 * 1024 + 8, workspace_bytes=need),      # misaligned
+               dict(max_restart=20, workspace=256 * 1024, workspace_bytes=need - 1),      # short
+               dict(max_restart=0, workspace=256 * 1024, workspace_bytes=need)):          # no restart
+        p, _keep = aim.make_params(xy, wl.K0, wl.ETA0, 0, 64, 0.05, **kw)
+        assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG, kw
+    # the admission estimate counts the longer of the two workspaces
+    f0 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, restart=0, max_restart=0)
+    f20 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, restart=0, max_restart=20)
+    assert f20 - f0 == need
+    assert aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, restart=20, max_restart=20) == f20

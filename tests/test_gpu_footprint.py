@@ -1,8 +1,8 @@
 """aim_footprint_bytes, the host-only estimate the serving loop admits
 requests by, bounds what a context then holds on the device: its tables,
-buffers and Krylov workspace (aim_get_info's device_bytes after a solve
-with the same restart length) plus its grid-kernel spectrum in the shared
-cache.  It is also not wastefully loose (at most 2.5x)."""
+buffers (aim_get_info's device_bytes after a solve), the caller-owned
+Krylov workspace of that restart length and its grid-kernel spectrum in the
+shared cache.  It is also not wastefully loose (at most 2.5x)."""
 import math
 
 import numpy as np
@@ -48,11 +48,11 @@ def test_footprint_bounds_device_bytes(case):
     restart = 120
     p = aim.AIM_MIXED if prec else aim.AIM_FP64
     est = aim.aim_footprint_bytes(xy, k, eta, basis, m, eps, precision=p, max_rhs=R, restart=restart, dual=dual)
-    ctx = aim.Context(xy, k, eta, basis, m, eps, precision=p, max_rhs=R, dual=dual)
+    ctx = aim.Context(xy, k, eta, basis, m, eps, precision=p, max_rhs=R, dual=dual, max_restart=restart)
     try:
         b = ctx.rhs_planewave(np.linspace(0.0, 1.0, R))
         ctx.solve("TM" if basis == 0 else "TE_CP_UNF", b, tol=1e-3, restart=restart, maxit=2)
-        held = ctx.info()["device_bytes"] + _spectrum_bytes(m, prec)
+        held = ctx.info()["device_bytes"] + _spectrum_bytes(m, prec) + aim.aim_workspace_bytes(len(xy), R, restart)
         print(f"case {case}: N={len(xy)} m={m} rhs={R} dual={dual} estimate {est / 1e6:.1f} MB, "
               f"held {held / 1e6:.1f} MB, ratio {est / held:.2f}")
         assert held <= est <= 2.5 * held

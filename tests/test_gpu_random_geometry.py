@@ -109,7 +109,8 @@ def test_irregular_polygon_solves(case):
     i, m, basis, xy, k, quad, radius, _ = case
     n = xy.shape[0]
     print(f"irregular polygon solve {i}: m={m} basis={basis} N={n}", flush=True)
-    ctx = aim.Context(xy, k, wl.ETA0, basis, m, EPS, quad=quad, near_radius=radius, precision=aim.AIM_MIXED)
+    ctx = aim.Context(xy, k, wl.ETA0, basis, m, EPS, quad=quad, near_radius=radius, precision=aim.AIM_MIXED,
+                      max_restart=200)
     orc = oaim.AimOracle(xy, k, wl.ETA0, basis, m, EPS, p=quad, near_radius=radius)
     if basis == 0:
         form, b = "TM", excitation.rhs_tm(xy, 0, k, 0.7, p=quad)

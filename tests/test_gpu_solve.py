@@ -41,7 +41,7 @@ def tm():
     """Circle a = 1 (ka = 2 pi), N = 512 pulses, grid 64 at lambda/10."""
     w = wl.cylinder_small()
     orc = oaim.AimOracle(w.xy, K, ETA, 0, w.m, w.eps, alpha=w.alpha)
-    ctx = aim.Context(w.xy, K, ETA, 0, w.m, w.eps, max_rhs=4, precision=aim.AIM_MIXED)
+    ctx = aim.Context(w.xy, K, ETA, 0, w.m, w.eps, max_rhs=4, precision=aim.AIM_MIXED, max_restart=200)
     ctx.filter(w.alpha)
     b = excitation.rhs_tm(w.xy, 0, K, 0.0)
     x_or, inf = ogmres(lambda v: orc.apply('TM', v), b, tol=1e-11, restart=200)
@@ -170,7 +170,7 @@ def test_longest_restart_on_a_large_star():
     same current as a short-restart solve, in fewer steps."""
     rq = wl.serving_stream(24, 0.0)[9]          # star, ka ~ 320, N = 6400, m = 1024
     print(f"long restart N={len(rq.xy)} m={rq.m}", flush=True)
-    ctx = aim.Context(rq.xy, rq.k, rq.eta, 0, rq.m, rq.eps, max_rhs=1)
+    ctx = aim.Context(rq.xy, rq.k, rq.eta, 0, rq.m, rq.eps, max_rhs=1, max_restart=1000)
     b = ctx.rhs_planewave(float(rq.phis[0]))
     x1, i1 = ctx.solve("TM", b, tol=1e-6, restart=1000, maxit=4000)
     x3, i3 = ctx.solve("TM", b, tol=1e-6, restart=300, maxit=6000)

@@ -24,7 +24,7 @@ K = 2 * math.pi
 
 def _setup(xy, eps, alpha, precision=aim.AIM_FP64, max_rhs=2, oracle=True):
     m = wl.grid_side_for(odual.refined_polygon(xy), eps)
-    ctx = aim.Context(xy, K, wl.ETA0, 0, m, eps, precision=precision, max_rhs=max_rhs, dual=1)
+    ctx = aim.Context(xy, K, wl.ETA0, 0, m, eps, precision=precision, max_rhs=max_rhs, dual=1, max_restart=200)
     ctx.filter(alpha)
     orc = odual.TMCalderonOracle(xy, K, wl.ETA0, m, eps, alpha=alpha) if oracle else None
     return ctx, orc

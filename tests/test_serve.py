@@ -212,3 +212,24 @@ def test_step_server_results_identical_alone_in_mix_and_threaded():
         assert np.array_equal(out.sigma, a.sigma)
         assert np.array_equal(th[out.rid].x, a.x) and np.array_equal(th[out.rid].sigma, a.sigma)
         assert out.resid <= 1.0000001 * reqs[out.rid].tol
+
+
+def test_request_log_has_one_line_per_request(tmp_path):
+    """The JSONL request log: one line per request (completed, rejected or
+    failed) with its times and sizes."""
+    import json
+    reqs = _reqs([0.0, 0.001, 0.002, 0.003])
+    fps = {0: 10, 1: 10, 2: 500, 3: 10}
+    exe = FakeExecutor(fps, {i: 0.01 for i in fps})
+    path = tmp_path / "req.jsonl"
+    res = serve.Server(exe, hbm_budget=100, slots=2, log_path=str(path)).run(reqs)
+    lines = [json.loads(l) for l in open(path)]
+    assert sorted(d["rid"] for d in lines) == [0, 1, 2, 3]
+    by = {d["rid"]: d for d in lines}
+    assert by[2]["status"] == "rejected"
+    for r in res:
+        d = by[r.rid]
+        assert d["N"] == 8 and d["m"] == 16 and d["R"] == 2 and d["precision"] == "fp64"
+        assert d["arrival"] == r.arrival and d["finish"] == r.finish
+        if r.status == "ok":
+            assert d["admit"] <= d["finish"] and d["matvecs"] == 10
