@@ -294,6 +294,23 @@ aim_status aim_solver_end(aim_solver solver);
 aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev,
                               const double* phi_host, double* sigma_host);
 
+/* aim_rcs_monostatic for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the same values, bit for bit, with the angles, plane-wave
+   vectors, column sums and values of the call held in one fixed device array
+   of AIM_NOALLOC_SCRATCH complex values per GPU (8 MiB, kept until the
+   process ends) instead of the context's buffers, so nrhs is not bounded by
+   max_rhs.  Calls no allocating routine.  Limit: 2 ceil16(ceil(nrhs / 2)) +
+   ceil16(nrhs) + ceil16(N nrhs) <= AIM_NOALLOC_SCRATCH (ceil16: rounded up to
+   a multiple of 16), e.g. nrhs <= 31 at N = 16384; larger calls return
+   AIM_E_ARG.  Every call on one GPU shares its array: calls that overlap on
+   one GPU (from several threads or contexts) race and must be serialised by
+   the caller.  Synchronous.  Errors: AIM_E_ARG (size, basis, null pointer),
+   AIM_E_STATE, AIM_E_HIP.                                                    */
+#define AIM_NOALLOC_SCRATCH 524288
+aim_status aim_rcs_monostatic_noalloc(aim_ctx ctx, int32_t nrhs, const void* j_dev, const double* phi_host,
+                                      double* sigma_host);
+
 /* Spectrum of an operator in the Fourier (Laplace-Beltrami) basis of a closed
    contour whose N bases are numbered along it, as in the paper's Sec. IV
    experiments (Figs. 2 and 3, the singular values of S, S^alpha and the

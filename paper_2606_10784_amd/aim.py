@@ -87,6 +87,8 @@ EXPORTS = {
                                  ctypes.POINTER(AimSolveInfo)]),
     "aim_rcs_monostatic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "aim_rcs_monostatic_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "aim_fourier_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "aim_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimCtxInfo)]),
@@ -429,6 +431,22 @@ def aim_rcs_monostatic(ctx, J, phis):
     _check(_lib().aim_rcs_monostatic(ctx.handle, nrhs, ctypes.c_void_p(J.data_ptr()),
                                      ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "aim_rcs_monostatic")
+    return sig
+
+
+def aim_rcs_monostatic_noalloc(ctx, J, phis):
+    """aim_rcs_monostatic with every buffer of the call in the library's
+    fixed per-device array (no device allocation; see include/aim.h)."""
+    J, nrhs = _as_cols(J, ctx.N)
+    ph = np.ascontiguousarray(np.atleast_1d(np.asarray(phis, dtype=np.float64)))
+    if ph.size != nrhs:
+        raise ValueError("one angle per current column")
+    sig = np.zeros(nrhs)
+    _join_in(ctx)
+    _check(_lib().aim_rcs_monostatic_noalloc(ctx.handle, nrhs, ctypes.c_void_p(J.data_ptr()),
+                                             ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "aim_rcs_monostatic_noalloc")
     return sig
 
 

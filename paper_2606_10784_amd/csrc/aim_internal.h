@@ -261,6 +261,10 @@ aim_status launch_cols_jobs(const ColsJob* jobs, int count, hipStream_t s);
 aim_status rhs_planewave(Ctx* c, int nrhs, const double* phi_host, double amp, double2* b);
 aim_status eval_green(Ctx* c, int n, const double* R, double2* out);
 aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma);
+// aim_rcs_monostatic_noalloc: the same values with every buffer of the call
+// in a fixed per-device array of kNoAllocScratch complex values
+static constexpr size_t kNoAllocScratch = AIM_NOALLOC_SCRATCH;
+aim_status rcs_noalloc(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma);
 aim_status rcs_into(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma_host, double* phi_dev,
                     double2* b_dev, double2* dot_dev, double* sig_dev);
 aim_status fourier_spectrum(Ctx* c, int op, int n_modes, const int32_t* nu_host, double2* lambda_host);

@@ -264,6 +264,12 @@ aim_status aim_rcs_monostatic(aim_ctx ctx, int32_t nrhs, const void* j_dev, cons
   return rcs(&ctx->c, nrhs, (const double2*)j_dev, phi_host, sigma_host);
 }
 
+aim_status aim_rcs_monostatic_noalloc(aim_ctx ctx, int32_t nrhs, const void* j_dev, const double* phi_host,
+                                      double* sigma_host) {
+  if (!ctx || !j_dev || !phi_host || !sigma_host) return AIM_E_ARG;
+  return rcs_noalloc(&ctx->c, nrhs, (const double2*)j_dev, phi_host, sigma_host);
+}
+
 aim_status aim_fourier_spectrum(aim_ctx ctx, int32_t op, int32_t n_modes, const int32_t* nu_host,
                                 double* lambda_host) {
   if (!ctx) return AIM_E_ARG;

@@ -1048,10 +1048,34 @@ size_t cache_clear() {
   return freed;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free RCS: the angles, plane-wave vectors, column sums and values
+// of one call live in a fixed device array, one per GPU for the life of the
+// process.  Host code never passes `scratch` itself to a kernel (it is only a
+// host-side stand-in there): its device address is resolved once per device
+// at set-up with that device current and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double2 scratch[kNoAllocScratch];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double2* g_scratch_dev[kMaxDevices] = {};
+
+// Called by setup_device with c->device current.
+static aim_status resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return AIM_E_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return AIM_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return AIM_E_HIP;
+  g_scratch_dev[device] = (double2*)p;
+  return AIM_OK;
+}
+
 aim_status setup_device(Ctx* c) {
   HostTables& t = c->t;
   const int N = t.N, n = t.n;
   hipStream_t s = c->stream;
+  TRY(resolve_scratch(c->device));
   TRY(upload(c, &c->d_vx, t.vx.data(), N * 8));
   TRY(upload(c, &c->d_vy, t.vy.data(), N * 8));
   TRY(upload(c, &c->d_h, t.h.data(), N * 8));
@@ -1789,6 +1813,33 @@ aim_status rcs_into(Ctx* c, int nrhs, const double2* J, const double* phi_host, 
 aim_status rcs(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma) {
   if (c->t.basis != AIM_PULSE || nrhs < 1 || nrhs > c->max_rhs) return AIM_E_ARG;
   return rcs_into(c, nrhs, J, phi_host, sigma, c->d_phi, c->d_rhs, c->d_dot, (double*)(c->d_dot + c->max_rhs));
+}
+
+// Complex slots of scratch one call needs: angles and values (nrhs doubles
+// each), sums (nrhs) and the plane-wave vectors (N x nrhs), each region
+// rounded to 16 slots (256 bytes).
+static size_t noalloc_slots(size_t N, size_t nrhs) {
+  auto r16 = [](size_t v) { return (v + 15) / 16 * 16; };
+  return 2 * r16((nrhs + 1) / 2) + r16(nrhs) + r16(N * nrhs);
+}
+
+aim_status rcs_noalloc(Ctx* c, int nrhs, const double2* J, const double* phi_host, double* sigma) {
+  if (c->t.basis != AIM_PULSE || nrhs < 1 || nrhs > AIM_MAX_RHS) return AIM_E_ARG;
+  if (noalloc_slots((size_t)c->t.N, (size_t)nrhs) > kNoAllocScratch) return AIM_E_ARG;
+  if (c->device < 0 || c->device >= kMaxDevices) return AIM_E_HIP;
+  double2* base;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch_dev[c->device];
+  }
+  if (!base) return AIM_E_STATE;
+  auto r16 = [](size_t v) { return (v + 15) / 16 * 16; };
+  const size_t nh = r16(((size_t)nrhs + 1) / 2);
+  double* phi_dev = (double*)base;
+  double* sig_dev = (double*)(base + nh);
+  double2* dot_dev = base + 2 * nh;
+  double2* b_dev = dot_dev + r16((size_t)nrhs);
+  return rcs_into(c, nrhs, J, phi_host, sigma, phi_dev, b_dev, dot_dev, sig_dev);
 }
 
 aim_status eval_green(Ctx* c, int n, const double* R, double2* out) {
