@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serve-log-dir", default=None, help="directory of the per-request JSONL logs")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the star TE Calderon and 360-incidence measurements of the default line")
     return ap.parse_args()
 
 
@@ -185,20 +187,63 @@ def cpu_baseline(w, sample_every=64, reps=2):
                        f"{rows.size} of {w.n_unknowns} rows scaled to all rows; {per:.2f} s per matvec")}
 
 
-def star_te(args):
-    """Star N = 65536 hats, grid 2048 -> 4096: Calderon-preconditioned TE
-    solves with the filtered S^alpha and with the accurate S, FP64 and mixed."""
+def alpha_sweep(ctx, b, alphas, tol, maxit=3000, restart=300):
+    """Filtered TE Calderon solves (G^-1 S^alpha G^-1 N, FP64) over cutoffs:
+    iterations to tol (or maxit), the unpreconditioned residual
+    ||N j - b|| / ||b|| and the current's distance from the unfiltered
+    solution (G^-1 S G^-1 N, near field included)."""
+    import torch
+    from paper_2606_10784_amd import aim
+    t0 = time.perf_counter()
+    xu, iu = ctx.solve("TE_CP_UNF", b, tol=tol, restart=restart, maxit=maxit)
+    t_unf = time.perf_counter() - t0
+    nb = float(torch.linalg.norm(b))
+    ru = float(torch.linalg.norm(ctx.matvec("N", xu) - b)) / nb
+    out = {"unfiltered": {"iterations": iu[0]["iterations"], "converged": iu[0]["converged"], "seconds": t_unf,
+                          "resid_unpreconditioned": ru}, "filtered": []}
+    for a in alphas:
+        ctx.filter(a)
+        t0 = time.perf_counter()
+        x, info = ctx.solve("TE_CP", b, tol=tol, restart=restart, maxit=maxit)
+        dt = time.perf_counter() - t0
+        rn = float(torch.linalg.norm(ctx.matvec("N", x) - b)) / nb
+        dx = float(torch.linalg.norm(x - xu) / torch.linalg.norm(xu))
+        out["filtered"].append({"alpha": a, "alpha_eps_over_pi": a * ctx_eps(ctx) / math.pi,
+                                "iterations": info[0]["iterations"], "converged": info[0]["converged"],
+                                "resid_preconditioned": info[0]["resid_true"], "resid_unpreconditioned": rn,
+                                "rel_diff_vs_unfiltered": dx, "seconds": dt})
+        print(f"[bench] TE_CP alpha={a:.1f} its={info[0]['iterations']} conv={info[0]['converged']} "
+              f"unprec={rn:.2e} diff={dx:.2e} {dt:.2f}s", file=sys.stderr, flush=True)
+    return out
+
+
+def ctx_eps(ctx):
+    return ctx.info()["eps"]
+
+
+def star_alphas(eps):
+    """Cutoffs from the 50 %-bin one (the configurations' filter) to the
+    largest grid frequency sqrt(2) pi / eps (every bin kept)."""
+    a50 = math.sqrt(2.0 * math.pi) / eps
+    return [a50, 0.9 * math.pi / eps, math.pi / eps, 1.2 * math.pi / eps, math.sqrt(2.0) * math.pi / eps]
+
+
+def c2_star(args, sweep=True):
+    """Star N = 65536 hats, grid 2048 -> 4096 at lambda/30: Calderon-
+    preconditioned TE solves, unfiltered (FP64 and mixed) and filtered over
+    the cutoff sweep; operator timings."""
     import torch
     from paper_2606_10784_amd import aim
     from paper_2606_10784_amd import workloads as wl
     w = wl.star_large()
+    t0 = time.perf_counter()
     ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=1, max_restart=300)
     ctx.filter(w.alpha)
+    torch.cuda.synchronize()
     inf = ctx.info()
-    b = ctx.rhs_planewave(0.0)
     out = {"workload": w.name, "N": inf["n_unknowns"], "grid": f"{w.m}x{w.m} pad {inf['n_pad']}",
-           "near_nnz": inf["near_nnz_s"], "alpha": w.alpha, "solves": {}}
-    x = torch.zeros_like(b)
+           "near_nnz": inf["near_nnz_s"], "alpha_50pct": w.alpha, "setup_s": time.perf_counter() - t0, "solves": {}}
+    b = ctx.rhs_planewave(0.0)
     for lab, op in (("N", "N"), ("S_ALPHA", "S_ALPHA"), ("TE_CP", "TE_CP"), ("TE_CP_UNF", "TE_CP_UNF")):
         for prec in (0, aim.AIM_OP_GRID_FP32):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -209,17 +254,22 @@ def star_te(args):
             e1.record()
             torch.cuda.synchronize()
             out.setdefault("matvec_ms", {})[lab + ("_fp32grid" if prec else "")] = e0.elapsed_time(e1) / 10
-    for form in ("TE_CP", "TE_CP_UNF"):
-        for prec in (aim.AIM_FP64, aim.AIM_MIXED):
-            t0 = time.perf_counter()
-            x, info = ctx.solve(form, b, tol=args.tol, restart=300, maxit=3000, precision=prec)
-            dt = time.perf_counter() - t0
-            out["solves"][f"{form}_{'fp64' if prec == 0 else 'mixed'}"] = {
-                "seconds": dt, "iterations": info[0]["iterations"], "outer": info[0]["outer"],
-                "converged": info[0]["converged"], "resid_true": info[0]["resid_true"]}
-            print(f"[bench] {form} prec={prec} its={info[0]['iterations']} {dt:.2f}s", file=sys.stderr, flush=True)
-    print(json.dumps(out), flush=True)
+    for prec in (aim.AIM_FP64, aim.AIM_MIXED):
+        t0 = time.perf_counter()
+        x, info = ctx.solve("TE_CP_UNF", b, tol=args.tol, restart=300, maxit=3000, precision=prec)
+        dt = time.perf_counter() - t0
+        out["solves"][f"TE_CP_UNF_{'fp64' if prec == 0 else 'mixed'}"] = {
+            "seconds": dt, "iterations": info[0]["iterations"], "outer": info[0]["outer"],
+            "converged": info[0]["converged"], "resid_true": info[0]["resid_true"]}
+        print(f"[bench] TE_CP_UNF prec={prec} its={info[0]['iterations']} {dt:.2f}s", file=sys.stderr, flush=True)
+    if sweep:
+        out["alpha_sweep"] = alpha_sweep(ctx, b, star_alphas(w.eps), args.tol)
     ctx.close()
+    return out
+
+
+def star_te(args):
+    print(json.dumps(c2_star(args)), flush=True)
 
 
 def tm_calderon(args):
@@ -271,9 +321,23 @@ def tm_calderon(args):
     ctx.close()
 
 
-def batched_360(args):
+def mie_backscatter_tm(k, a):
+    """Monostatic scattering width of a PEC circular cylinder, TM (the Mie
+    series): sigma = (4 / k) |sum_n (-1)^n J_n(ka) / H_n^(2)(ka)|^2."""
+    from scipy import special
+    x = k * a
+    nmax = int(x + 10 * x ** (1.0 / 3.0) + 20)
+    s = 0.0 + 0.0j
+    for n in range(-nmax, nmax + 1):
+        m = abs(n)
+        s += (-1) ** n * special.jv(m, x) / (special.jv(m, x) - 1j * special.yv(m, x))
+    return 4.0 / k * abs(s) ** 2
+
+
+def c3_batched(args):
     """Cylinder ka = 200 with 360 plane waves (1 degree steps) in one batched
-    solve: FP64 and FP32-grid + FP64 refinement, monostatic RCS."""
+    solve: FP32-grid GMRES inside FP64 refinement and plain FP64, monostatic
+    RCS against the Mie series."""
     import numpy as np
     import torch
     from paper_2606_10784_amd import aim
@@ -284,7 +348,7 @@ def batched_360(args):
     ctx = aim.Context(w.xy, w.k, w.eta, w.basis, w.m, w.eps, precision=aim.AIM_MIXED, max_rhs=R,
                       max_restart=args.restart)
     B = ctx.rhs_planewave(phis)
-    out = {"workload": w.name + "_360rhs", "nrhs": R, "solves": {}}
+    out = {"workload": w.name + "_360rhs", "nrhs": R, "restart": args.restart, "solves": {}}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for prec, lab in ((0, "fp64"), (aim.AIM_OP_GRID_FP32, "fp32grid")):
         Y = ctx.matvec(aim.AIM_OP_TM | prec, B)
@@ -294,7 +358,9 @@ def batched_360(args):
         e1.record()
         torch.cuda.synchronize()
         out[f"batched_matvec_ms_{lab}"] = e0.elapsed_time(e1) / 3
-    for prec, lab in ((aim.AIM_FP64, "fp64"), (aim.AIM_MIXED, "mixed")):
+    sig_mie = mie_backscatter_tm(w.k, 200.0 / w.k)
+    for prec, lab in ((aim.AIM_MIXED, "mixed"), (aim.AIM_FP64, "fp64")):
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         X, infos = ctx.solve("TM", B, tol=args.tol, restart=args.restart, precision=prec)
         dt = time.perf_counter() - t0
@@ -303,10 +369,16 @@ def batched_360(args):
                               "iterations_max": max(d["iterations"] for d in infos),
                               "converged": sum(d["converged"] for d in infos),
                               "resid_true_max": max(d["resid_true"] for d in infos),
-                              "rcs_min": float(sig.min()), "rcs_max": float(sig.max())}
+                              "rcs_min": float(sig.min()), "rcs_max": float(sig.max()),
+                              "rcs_max_rel_dev_vs_mie": float(np.max(np.abs(sig - sig_mie)) / sig_mie)}
         print(f"[bench] 360 rhs {lab}: {dt:.2f}s", file=sys.stderr, flush=True)
-    print(json.dumps(out), flush=True)
+    out["mixed_speedup_vs_fp64"] = out["solves"]["fp64"]["seconds"] / out["solves"]["mixed"]["seconds"]
     ctx.close()
+    return out
+
+
+def batched_360(args):
+    print(json.dumps(c3_batched(args)), flush=True)
 
 
 def spectrum(args):
@@ -571,6 +643,11 @@ def main():
     if args.serve_requests > 0:
         print("[bench] serving stream ...", file=sys.stderr, flush=True)
         out["serving"] = serving(args.serve_requests, log_dir=args.serve_log_dir)
+    if not args.no_configs:
+        print("[bench] star N=65536 TE Calderon (filtered vs unfiltered) ...", file=sys.stderr, flush=True)
+        out["c2_star_te"] = c2_star(args)
+        print("[bench] cylinder ka=200, 360 incidences ...", file=sys.stderr, flush=True)
+        out["c3_360_incidences"] = c3_batched(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

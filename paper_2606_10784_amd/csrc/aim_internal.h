@@ -132,6 +132,9 @@ struct DevBuf {
 };
 
 struct Ctx;
+// residual estimates one check reads back per rhs (a batch of Arnoldi steps
+// plus the column that closes a cycle), rounded up
+static constexpr int kResidPitch = 16;
 struct GmresWork {
   int restart = 0, nrhs = 0;
   // V: restart + 1 basis slots per rhs; H: Hessenberg (rotated in place by the
@@ -143,7 +146,6 @@ struct GmresWork {
           *sn = nullptr, *y = nullptr, *part = nullptr, *r = nullptr, *d = nullptr, *b2 = nullptr, *nrm = nullptr;
   double *resid = nullptr, *npart = nullptr;
   int* active = nullptr;
-  std::vector<double> host_resid; // host copy of the residual estimates (restart per rhs)
   int nchunk = 0;
   size_t lds_max = 65536;         // LDS bytes one block may use on this device
   size_t bytes = 0;
@@ -200,6 +202,7 @@ struct Ctx {
   double2* d_rhs = nullptr;
   double* d_phi = nullptr;     // AIM_MAX_RHS incidence angles (aim_rhs_planewave)
   double2* d_dot = nullptr;    // max_rhs column sums, then max_rhs values (aim_rcs_monostatic)
+  double* h_resid = nullptr;   // pinned host copy of GMRES residual estimates, kResidPitch per rhs
   double2* d_spec = nullptr;   // Fourier-spectrum work (modes, products, quotients), on first use
   double* d_red = nullptr;
   size_t dev_bytes = 0;

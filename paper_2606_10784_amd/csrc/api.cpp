@@ -25,6 +25,8 @@ void free_ctx(Ctx* c) {
   release_spectrum(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  if (c->h_resid) (void)hipHostFree(c->h_resid);
+  c->h_resid = nullptr;
   c->gw = GmresWork();
 }
 

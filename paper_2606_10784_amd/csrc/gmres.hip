@@ -40,6 +40,7 @@ namespace aim {
 static constexpr int RED_CHUNK = 2048;
 // Arnoldi steps enqueued between two host reads of the residual estimates
 static constexpr int kCheckEvery = 8;
+static_assert(kCheckEvery + 1 <= kResidPitch, "one check reads back at most kCheckEvery + 1 estimates per rhs");
 
 // sum over a 256-thread block, same value in every thread, fixed order
 // (butterfly within each wave, then the four waves in order).  red: 4*K doubles.
@@ -646,7 +647,7 @@ aim_status bind_gmres_work(Ctx* c, GmresWork& w, void* base, size_t bytes, int r
   // all-ones mask used by the residual checks
   hipLaunchKernelGGL(k_fill_int, dim3((nrhs + 255) / 256), dim3(256), 0, c->stream, nrhs, 1, w.active + nrhs);
   AIM_HIP_CHECK(hipGetLastError());
-  w.host_resid.assign((size_t)nrhs * restart, 0.0);
+  if (!c->h_resid || nrhs > c->max_rhs) return AIM_E_STATE;
   // a check may rotate up to kCheckEvery + 1 columns (the last one of a
   // cycle is finalised with the batch); batches that do not fit one block's
   // LDS are split by close_batch
@@ -868,10 +869,11 @@ struct GmresRun {
       AIM_HIP_CHECK(hipGetLastError());
       a = e;
     }
-    // residual estimates jfin .. c1-1 of every rhs in one strided copy
-    AIM_HIP_CHECK(hipMemcpy2DAsync(w.host_resid.data() + jfin, (size_t)restart * 8, w.resid + jfin,
-                                   (size_t)restart * 8, (size_t)(c1 - jfin) * 8, (size_t)nrhs, hipMemcpyDeviceToHost,
-                                   s));
+    // residual estimates jfin .. c1-1 of every rhs in one strided copy into
+    // the context's pinned buffer (kResidPitch per rhs; read right after
+    // the synchronisation, so solvers sharing the context take turns)
+    AIM_HIP_CHECK(hipMemcpy2DAsync(c->h_resid, (size_t)kResidPitch * 8, w.resid + jfin, (size_t)restart * 8,
+                                   (size_t)(c1 - jfin) * 8, (size_t)nrhs, hipMemcpyDeviceToHost, s));
     AIM_HIP_CHECK(hipStreamSynchronize(s));
     bool left = false, changed = false;
     for (int r = 0; r < nrhs; ++r) {
@@ -879,7 +881,7 @@ struct GmresRun {
       for (int jj = jfin; jj < c1; ++jj) {
         res.iters[r]++;
         jdone[r] = jj + 1;
-        const double rel = w.host_resid[(size_t)r * restart + jj] / bn[r];
+        const double rel = c->h_resid[(size_t)r * kResidPitch + (jj - jfin)] / bn[r];
         if (!std::isfinite(rel)) return AIM_E_NUMERIC;
         res.est[r] = rel;
         if (rel <= tol[r]) { act[r] = 0; changed = true; break; }

@@ -697,7 +697,15 @@ __global__ __launch_bounds__(256) void k_interp_band(
     const double2* __restrict__ Cd, const double2* __restrict__ x, int64_t ldx, double2* __restrict__ y,
     int64_t ldy, double2 scale) {
   constexpr int L = 16;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-aware block order: blocks are dealt round-robin over the 8 XCDs, so
+  // logical block (bid mod 8) * per + bid / 8 gives each XCD a contiguous
+  // range of rows.  Row i reads the band at columns i (upper half) and
+  // i - d (lower half, d <= w): the lower reads then hit in the XCD's L2
+  // the values its neighbouring blocks just fetched as upper reads, instead
+  // of fetching each band value a second time.
+  const int per = (int)((gridDim.x + 7) / 8);
+  const int lblk = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  const int gid = lblk * blockDim.x + threadIdx.x;
   const int row = gid / L, l = gid % L;
   if (row >= N) return;          // whole lane groups exit together
   const size_t o = (size_t)row * 16 + l;
@@ -1203,6 +1211,10 @@ aim_status setup_device(Ctx* c) {
   TRY(dev_alloc(c, (void**)&c->d_rhs, (size_t)N * c->max_rhs * 16));
   TRY(dev_alloc(c, (void**)&c->d_phi, (size_t)AIM_MAX_RHS * 8));
   TRY(dev_alloc(c, (void**)&c->d_dot, (size_t)c->max_rhs * 24));   // sums, then the values
+  if (hipHostMalloc((void**)&c->h_resid, (size_t)c->max_rhs * kResidPitch * 8) != hipSuccess) {
+    c->h_resid = nullptr;
+    return AIM_E_OOM;
+  }
   TRY(dev_alloc(c, (void**)&c->d_red, (size_t)std::max(5 * N, 64) * std::max(c->max_rhs, 1) * 8));
   AIM_HIP_CHECK(hipStreamSynchronize(s));
   return AIM_OK;
@@ -1369,7 +1381,8 @@ static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near
   if (t.band_w >= 0) {
     // banded symmetric near field (or none)
     const double2* Cd = !near ? nullptr : (Cn == c->d_CS ? c->d_CSd : c->d_CNd);
-    dim3 g((unsigned)(((size_t)t.N * 16 + 255) / 256));
+    // a multiple of 8 blocks (the kernel's XCD-aware order); the extra ones exit
+    dim3 g((unsigned)(8 * (((size_t)t.N * 16 + 255) / 256 + 7) / 8));
     if (sizeof(T) == 4)
       hipLaunchKernelGGL((k_interp_band<T, float>), g, dim3(256), 0, c->stream, t.N, nrhs, nch,
                          c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
