@@ -1382,7 +1382,8 @@ static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near
     // banded symmetric near field (or none)
     const double2* Cd = !near ? nullptr : (Cn == c->d_CS ? c->d_CSd : c->d_CNd);
     // a multiple of 8 blocks (the kernel's XCD-aware order); the extra ones exit
-    dim3 g((unsigned)(8 * (((size_t)t.N * 16 + 255) / 256 + 7) / 8));
+    const size_t nb = ((size_t)t.N * 16 + 255) / 256;
+    dim3 g((unsigned)(8 * ((nb + 7) / 8)));
     if (sizeof(T) == 4)
       hipLaunchKernelGGL((k_interp_band<T, float>), g, dim3(256), 0, c->stream, t.N, nrhs, nch,
                          c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
