@@ -202,7 +202,9 @@ struct Ctx {
   double2* d_rhs = nullptr;
   double* d_phi = nullptr;     // AIM_MAX_RHS incidence angles (aim_rhs_planewave)
   double2* d_dot = nullptr;    // max_rhs column sums, then max_rhs values (aim_rcs_monostatic)
-  double* h_resid = nullptr;   // pinned host copy of GMRES residual estimates, kResidPitch per rhs
+  double* h_resid = nullptr;   // pinned (coherent) GMRES residual estimates, kResidPitch per rhs
+  double* d_resid_map = nullptr;   // the device's address of h_resid
+  hipEvent_t ev_resid = nullptr;   // recorded after the kernels that write h_resid
   double2* d_spec = nullptr;   // Fourier-spectrum work (modes, products, quotients), on first use
   double* d_red = nullptr;
   size_t dev_bytes = 0;

@@ -27,6 +27,9 @@ void free_ctx(Ctx* c) {
   c->allocs.clear();
   if (c->h_resid) (void)hipHostFree(c->h_resid);
   c->h_resid = nullptr;
+  c->d_resid_map = nullptr;
+  if (c->ev_resid) (void)hipEventDestroy(c->ev_resid);
+  c->ev_resid = nullptr;
   c->gw = GmresWork();
 }
 

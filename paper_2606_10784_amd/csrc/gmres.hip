@@ -432,7 +432,8 @@ __device__ __forceinline__ void rot_apply(double ci, double2 si, double2& a, dou
 // per rhs; dynamic LDS: (j1 - j0) * ldh + 2 * j1 double2.
 __global__ __launch_bounds__(256) void k_givens_batch(int ldh, int j0, int j1, const int* __restrict__ active,
                                                       double2* H, double2* cs, double2* sn, double2* g,
-                                                      double* resid_hist) {
+                                                      double* resid_hist, double* est_out, int est_j0,
+                                                      int est_pitch) {
   extern __shared__ double2 sh[];
   const int r = blockIdx.x;
   if (!active[r]) return;
@@ -521,7 +522,10 @@ __global__ __launch_bounds__(256) void k_givens_batch(int ldh, int j0, int j1, c
       gg[jj + 1] = make_double2(-(si.x * gj.x + si.y * gj.y), -(si.x * gj.y - si.y * gj.x));
       gg[jj] = make_double2(ci * gj.x, ci * gj.y);
       resid_hist[(size_t)r * R + jj] = hypot(gg[jj + 1].x, gg[jj + 1].y);
+      // the estimate also goes straight to the host's pinned buffer
+      est_out[(size_t)r * est_pitch + (jj - est_j0)] = resid_hist[(size_t)r * R + jj];
     }
+    __threadfence_system();
   }
   __syncthreads();
   double2* dst = Hr + (size_t)j0 * ldh;
@@ -647,10 +651,10 @@ aim_status bind_gmres_work(Ctx* c, GmresWork& w, void* base, size_t bytes, int r
   // all-ones mask used by the residual checks
   hipLaunchKernelGGL(k_fill_int, dim3((nrhs + 255) / 256), dim3(256), 0, c->stream, nrhs, 1, w.active + nrhs);
   AIM_HIP_CHECK(hipGetLastError());
-  if (!c->h_resid || nrhs > c->max_rhs) return AIM_E_STATE;
+  if (!c->h_resid || !c->d_resid_map || !c->ev_resid || nrhs > c->max_rhs) return AIM_E_STATE;
   // a check may rotate up to kCheckEvery + 1 columns (the last one of a
   // cycle is finalised with the batch); batches that do not fit one block's
-  // LDS are split by close_batch
+  // LDS are split by close_issue
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess || lds <= 0)
     return AIM_E_HIP;
@@ -691,8 +695,10 @@ struct GmresResult {
 // true residual of x (top), takes steps in batches of up to kCheckEvery,
 // closes each batch with its rotations and residual estimates (the one host
 // synchronisation), and ends with x += V y.  SolveRun drives it: to the end
-// for aim_solve, a step at a time for the step-wise solver; both issue the
-// same kernels in the same order.
+// for aim_solve, a step at a time for the step-wise solver.  Both compute the
+// same values in the same order; aim_solve may in addition enqueue one batch
+// of steps ahead of the host's check (look), whose work is dropped when the
+// check ends the cycle.
 struct GmresRun {
   enum Phase { TOP, ARNOLDI, DONE };
   Ctx* c;
@@ -713,6 +719,15 @@ struct GmresRun {
   int total = 0, j = 0, jfin = 0, jend = 0;
   bool batch = false;
   Phase phase = TOP;
+  // Look-ahead (aim_solve only): the steps of the next batch are enqueued
+  // before the host waits for the estimates of the batch just closed, so
+  // the GPU does not idle through the round trip.  Steps enqueued after
+  // every column has converged are discarded (their results are never
+  // read) and not counted.
+  bool look = false;
+  int pend_c1 = 0, nspec = 0;
+  bool pend_last = false;
+  std::vector<double> est_prev;
 
   GmresRun(Ctx* c_, GmresWork& w_, int op_, int nrhs_, const double2* b_, double2* x_, std::vector<double> tol_,
            int maxit_, int restart_, GmresResult& res_)
@@ -727,6 +742,7 @@ struct GmresRun {
     d_all = w.active + w.nrhs;   // all-ones mask (set when the workspace is bound)
     act.assign(nrhs, 1);
     jdone.assign(nrhs, 0);
+    est_prev.assign(nrhs, 0.0);
   }
 
   // host values to the device through kernel arguments, 32 per launch: no
@@ -837,19 +853,48 @@ struct GmresRun {
     if (j < jend) return AIM_OK;
     batch = false;
     bool over = false;
-    TRY(close_batch(over));
+    TRY(close_issue());
+    if (look && !pend_last && worth_speculating()) {
+      jend = std::min(std::min(restart, j + kCheckEvery), j + (maxit - total));
+      batch = true;
+      while (j < jend) {
+        TRY(arnoldi_step());
+        ++nspec;
+      }
+    }
+    TRY(close_resolve(over));
+    if (over) {
+      // the look-ahead steps did not happen as far as the solve is concerned
+      total -= nspec;
+      res.matvecs -= nspec;
+      j -= nspec;
+      batch = false;
+    }
+    nspec = 0;
     if (over) TRY(end_cycle());
     return AIM_OK;
   }
 
-  // end of a batch: rotations of the newly final columns and their residual
-  // estimates; over = true when no column is left in this cycle
-  aim_status close_batch(bool& over) {
-    over = false;
+  // A look-ahead batch is wasted only if every column converges in the
+  // batch being closed: skip it when each active column's estimate, reduced
+  // by the factor its previous batch achieved, would reach its tolerance.
+  bool worth_speculating() const {
+    for (int r = 0; r < nrhs; ++r) {
+      if (!act[r]) continue;
+      const double e = res.est[r], ep = est_prev[r];
+      const double pred = (ep > 0.0 && e > 0.0 && e < ep) ? e * (e / ep) : e;
+      if (!(pred <= tol[r])) return true;
+    }
+    return false;
+  }
+
+  // end of a batch, GPU side: rotations of the newly final columns and the
+  // copy of their residual estimates to the host buffer
+  aim_status close_issue() {
     // at the end of a cycle the last column is finalised by a reduction of
     // u_j alone (no operator application)
-    const bool last = j >= restart || total >= maxit;
-    if (last) {
+    pend_last = j >= restart || total >= maxit;
+    if (pend_last) {
       hipLaunchKernelGGL(k_arnoldi_dots, dim3(w.nchunk, dot_groups(j) + hs_blocks(j, w.nchunk), nrhs), dim3(256), 0,
                          s, N, j, w.V, ldv, (const double2*)nullptr, (int64_t)0, w.active, w.part, w.nchunk, ldh,
                          w.Hu, w.coef, w.hp);
@@ -858,26 +903,38 @@ struct GmresRun {
                          1);
       AIM_HIP_CHECK(hipGetLastError());
     }
-    const int c1 = last ? j : j - 1;
-    if (c1 <= jfin) return AIM_OK;
+    pend_c1 = pend_last ? j : j - 1;
+    if (pend_c1 <= jfin) return AIM_OK;
     // in column groups whose LDS footprint fits one block (long restarts)
-    for (int a = jfin; a < c1;) {
-      int e = c1;
+    for (int a = jfin; a < pend_c1;) {
+      int e = pend_c1;
       while (e > a + 1 && ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16 > w.lds_max) --e;
+      // the residual estimates jfin .. c1-1 of every active rhs go to the
+      // context's pinned buffer (kResidPitch per rhs), written by the kernel
+      // itself: no copy sits in the stream between this batch and the next.
+      // close_resolve reads them before the next batch is closed, so
+      // solvers sharing the context take turns.
       hipLaunchKernelGGL(k_givens_batch, dim3(nrhs), dim3(256), ((size_t)(e - a) * ldh + 2 * (size_t)e) * 16, s,
-                         ldh, a, e, w.active, w.H, w.cs, w.sn, w.g, w.resid);
+                         ldh, a, e, w.active, w.H, w.cs, w.sn, w.g, w.resid, c->d_resid_map, jfin, kResidPitch);
       AIM_HIP_CHECK(hipGetLastError());
       a = e;
     }
-    // residual estimates jfin .. c1-1 of every rhs in one strided copy into
-    // the context's pinned buffer (kResidPitch per rhs; read right after
-    // the synchronisation, so solvers sharing the context take turns)
-    AIM_HIP_CHECK(hipMemcpy2DAsync(c->h_resid, (size_t)kResidPitch * 8, w.resid + jfin, (size_t)restart * 8,
-                                   (size_t)(c1 - jfin) * 8, (size_t)nrhs, hipMemcpyDeviceToHost, s));
-    AIM_HIP_CHECK(hipStreamSynchronize(s));
+    AIM_HIP_CHECK(hipEventRecord(c->ev_resid, s));
+    return AIM_OK;
+  }
+
+  // end of a batch, host side: wait for the copy, count the steps of each
+  // column up to its convergence; over = true when no column is left in
+  // this cycle
+  aim_status close_resolve(bool& over) {
+    over = false;
+    const int c1 = pend_c1;
+    if (c1 <= jfin) return AIM_OK;
+    AIM_HIP_CHECK(hipEventSynchronize(c->ev_resid));
     bool left = false, changed = false;
     for (int r = 0; r < nrhs; ++r) {
       if (!act[r]) continue;
+      est_prev[r] = res.est[r];
       for (int jj = jfin; jj < c1; ++jj) {
         res.iters[r]++;
         jdone[r] = jj + 1;
@@ -946,6 +1003,11 @@ struct GmresRun {
     while (phase != DONE) {
       if (phase == TOP) {
         TRY(top());
+        continue;
+      }
+      if (batch && j >= jend) {
+        // a look-ahead batch is complete: close it first (it may end the cycle)
+        TRY(after_step());
         continue;
       }
       if (!(j < restart && total < maxit)) {
@@ -1047,6 +1109,7 @@ struct SolveRun {
   std::vector<double> est, tr;
   int matvecs = 0, restarts = 0, outer = 0;
   double tin_min = 0;
+  bool look = false;   // run to the end (aim_solve): GMRES batches look ahead
   GmresResult gr;
   std::unique_ptr<GmresRun> run;
   Phase phase = FINAL;
@@ -1072,6 +1135,7 @@ struct SolveRun {
       run.reset(new (std::nothrow) GmresRun(c, w, op, nrhs, rhs, x, std::vector<double>(nrhs, tol), maxit, restart,
                                             gr));
       if (!run) return AIM_E_OOM;
+      run->look = look;
       TRY(run->start());
       phase = FP64_RUN;
     } else {
@@ -1125,6 +1189,7 @@ struct SolveRun {
     run.reset(new (std::nothrow) GmresRun(c, w, op | AIM_OP_GRID_FP32, nrhs, w.r, w.d, tin, maxit - tot_it, restart,
                                           gr));
     if (!run) return AIM_E_OOM;
+    run->look = look;
     TRY(run->start());
     phase = MIX_INNER;
     return AIM_OK;
@@ -1241,6 +1306,7 @@ aim_status solve(Ctx* c, int form, int precision, int nrhs, const double2* b, do
   if (!c->gw.V) return AIM_E_STATE;
   if (restart > c->gw.restart || nrhs > c->gw.nrhs) return AIM_E_ARG;
   SolveRun sr(c, c->gw, form, precision, nrhs, b, x, tol, maxit, restart);
+  sr.look = true;
   TRY(sr.begin());
   TRY(sr.advance(std::numeric_limits<long>::max()));
   if (info) sr.fill(info, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());

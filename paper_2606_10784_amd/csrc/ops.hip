@@ -1211,10 +1211,13 @@ aim_status setup_device(Ctx* c) {
   TRY(dev_alloc(c, (void**)&c->d_rhs, (size_t)N * c->max_rhs * 16));
   TRY(dev_alloc(c, (void**)&c->d_phi, (size_t)AIM_MAX_RHS * 8));
   TRY(dev_alloc(c, (void**)&c->d_dot, (size_t)c->max_rhs * 24));   // sums, then the values
-  if (hipHostMalloc((void**)&c->h_resid, (size_t)c->max_rhs * kResidPitch * 8) != hipSuccess) {
+  // coherent pinned memory: the Givens kernel writes the estimates into it
+  if (hipHostMalloc((void**)&c->h_resid, (size_t)c->max_rhs * kResidPitch * 8, hipHostMallocCoherent) != hipSuccess) {
     c->h_resid = nullptr;
     return AIM_E_OOM;
   }
+  AIM_HIP_CHECK(hipHostGetDevicePointer((void**)&c->d_resid_map, c->h_resid, 0));
+  AIM_HIP_CHECK(hipEventCreateWithFlags(&c->ev_resid, hipEventDisableTiming));
   TRY(dev_alloc(c, (void**)&c->d_red, (size_t)std::max(5 * N, 64) * std::max(c->max_rhs, 1) * 8));
   AIM_HIP_CHECK(hipStreamSynchronize(s));
   return AIM_OK;
