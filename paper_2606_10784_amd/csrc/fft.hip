@@ -202,6 +202,13 @@ __device__ __forceinline__ void dft_r(cplx<T>* v) {
 // lanes of a wave spread over all banks.
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
+// The column pass pads one slot per 256 bytes in both precisions: per 16
+// FP64 or per 32 FP32 complex values.  In its fused pass consecutive lanes
+// step 8 CB values apart (256 B), so the pad shifts each lane by one value
+// (4 banks in FP64, 2 in FP32) and a cycle's lanes (16 of 16 B, 32 of 8 B)
+// cover distinct banks.  The buffer is sized with padded(), which covers both.
+template <typename T>
+__device__ __forceinline__ int cidx(int i) { return i + (i >> (sizeof(T) == 4 ? 5 : 4)); }
 
 // w^r for r = 1..R-1 from w = w^1 by a product tree of depth <= 4
 template <typename V, int R>
@@ -431,7 +438,7 @@ __device__ __forceinline__ void ct_pass_w(cplx<T>* buf, const cplx<T>* w) {
       const int m = t % S, base = (t / S) * S * R + m;
       V v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = buf[pidx((base + S * r) * NCOL + c)];
+      for (int r = 0; r < R; ++r) v[r] = buf[cidx<T>((base + S * r) * NCOL + c)];
       if (!INV) {
         dft_r<T, R, false>(v);
         apply_twiddle<T, false, S, R>(v, w[q]);
@@ -440,7 +447,7 @@ __device__ __forceinline__ void ct_pass_w(cplx<T>* buf, const cplx<T>* w) {
         dft_r<T, R, true>(v);
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[pidx((base + S * r) * NCOL + c)] = v[r];
+      for (int r = 0; r < R; ++r) buf[cidx<T>((base + S * r) * NCOL + c)] = v[r];
     }
   }
   __syncthreads();
@@ -786,7 +793,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       dft16_halfin<T, false>(v[q]);
       apply_twiddle<T, false, S1, 16>(v[q], w1[q]);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) buf[pidx((m + r * S1) * CB + c)] = v[q][r];
+      for (int r = 0; r < 16; ++r) buf[cidx<T>((m + r * S1) * CB + c)] = v[q][r];
     }
   }
   __syncthreads();
@@ -801,7 +808,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       if constexpr (!PRE) load_spec(bb, cv[q]);
       V u[RL];
 #pragma unroll
-      for (int r = 0; r < RL; ++r) u[r] = buf[pidx((g * RL + r) * CB + c)];
+      for (int r = 0; r < RL; ++r) u[r] = buf[cidx<T>((g * RL + r) * CB + c)];
       int lowc;
       const bool mir = mirrored(g, lowc);
       dft_r<T, RL, false>(u);
@@ -809,7 +816,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       for (int r = 0; r < RL; ++r) u[r] = cmul(u[r], mir ? cv[q][RL - 1 - r] : cv[q][r]);
       dft_r<T, RL, true>(u);
 #pragma unroll
-      for (int r = 0; r < RL; ++r) buf[pidx((g * RL + r) * CB + c)] = u[r];
+      for (int r = 0; r < RL; ++r) buf[cidx<T>((g * RL + r) * CB + c)] = u[r];
     }
   }
   __syncthreads();
@@ -823,7 +830,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       const int c = bb % CB, m = bb / CB;
       V u[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) u[r] = buf[pidx((m + r * S1) * CB + c)];
+      for (int r = 0; r < 16; ++r) u[r] = buf[cidx<T>((m + r * S1) * CB + c)];
       apply_twiddle<T, true, S1, 16>(u, w1[q]);
       dft16_halfout<T, true>(u);
 #pragma unroll

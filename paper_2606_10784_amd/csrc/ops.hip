@@ -806,6 +806,55 @@ __global__ void k_gram_hat_blocks(int N, int nrhs, const double* h, const double
   }
 }
 
+// Hats, N >= GP: parallel cyclic reduction of a truncated system in LDS.
+// Block b solves the GP unknowns starting GH before its GP - 2 GH outputs
+// (cyclic indices), with no coupling past the window's ends; by the same
+// 0.268^d decay the outputs, GH or more unknowns from either end, carry a
+// truncation error below 1e-18 relative.  Step s (s = 1, 2, .., GP/2)
+// eliminates the couplings at distance s from every equation; after log2 GP
+// steps each equation holds a single unknown.
+constexpr int GP = 256, GPO = GP - 2 * GH;
+
+__global__ __launch_bounds__(GP) void k_gram_hat_pcr(int N, const double* __restrict__ h,
+                                                     const double2* __restrict__ x, int64_t ldx,
+                                                     double2* __restrict__ y, int64_t ldy) {
+  __shared__ double sa[GP], sb[GP], sc[GP], sdx[GP], sdy[GP];
+  const int t = threadIdx.x, r = blockIdx.y;
+  int gi = (int)((blockIdx.x * (int64_t)GPO - GH + t) % N);
+  if (gi < 0) gi += N;
+  const int gm = gi == 0 ? N - 1 : gi - 1;
+  const double2 xv = x[(size_t)r * ldx + gi];
+  // row gi of G: h_{i-1}/6, (h_{i-1} + h_i)/3, h_i/6; cut at the window's ends
+  double a = t > 0 ? h[gm] / 6.0 : 0.0;
+  double b = (h[gm] + h[gi]) / 3.0;
+  double c = t < GP - 1 ? h[gi] / 6.0 : 0.0;
+  double dx = xv.x, dy = xv.y;
+#pragma unroll
+  for (int st = 1; st < GP; st <<= 1) {
+    sa[t] = a; sb[t] = b; sc[t] = c; sdx[t] = dx; sdy[t] = dy;
+    __syncthreads();
+    double na = 0.0, nc = 0.0, nb = b, ndx = dx, ndy = dy;
+    if (t - st >= 0) {
+      const double al = -a / sb[t - st];
+      na = al * sa[t - st];
+      nb += al * sc[t - st];
+      ndx += al * sdx[t - st];
+      ndy += al * sdy[t - st];
+    }
+    if (t + st < GP) {
+      const double ga = -c / sb[t + st];
+      nc = ga * sc[t + st];
+      nb += ga * sa[t + st];
+      ndx += ga * sdx[t + st];
+      ndy += ga * sdy[t + st];
+    }
+    __syncthreads();
+    a = na; b = nb; c = nc; dx = ndx; dy = ndy;
+  }
+  const int o = (int)(blockIdx.x * (int64_t)GPO) + t - GH;   // output index (not wrapped)
+  if (t >= GH && t < GP - GH && o < N) y[(size_t)r * ldy + o] = make_double2(dx / b, dy / b);
+}
+
 // Hats, small N: cyclic Thomas with Sherman-Morrison, one thread per column.
 // scratch: 3N doubles per column.
 __global__ void k_gram_hat_small(int N, int nrhs, const double* h, const double2* x, int64_t ldx,
@@ -1551,6 +1600,9 @@ static aim_status gram_inv(Ctx* c, int nrhs, const double2* x, int64_t ldx, doub
   if (t.basis == AIM_PULSE) {
     hipLaunchKernelGGL(k_gram_pulse, dim3((N + 255) / 256, nrhs), dim3(256), 0, c->stream, N, nrhs, c->d_h, x, ldx,
                        y, ldy);
+  } else if (N >= GP) {
+    const int nblk = (N + GPO - 1) / GPO;
+    hipLaunchKernelGGL(k_gram_hat_pcr, dim3(nblk, nrhs), dim3(GP), 0, c->stream, N, c->d_h, x, ldx, y, ldy);
   } else if (N >= GM) {
     const int nblk = (N + GB - 1) / GB;
     hipLaunchKernelGGL(k_gram_hat_blocks, dim3((nblk + 63) / 64, nrhs), dim3(64), 0, c->stream, N, nrhs, c->d_h, x,
