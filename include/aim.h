@@ -175,9 +175,13 @@ typedef struct {
    its tables and buffers, one Krylov workspace (exact) for max_rhs
    right-hand sides and the longer of `restart` (a step-wise solver's) and
    p->max_restart (aim_solve's), whether the caller or the library owns it,
-   and its grid-kernel spectrum in the shared cache; near-field pairs are
-   bounded from the geometry (eps over the mean segment length).  Host-only,
-   for admission control; 0 for invalid parameters.                            */
+   its grid-kernel spectrum in the shared cache, and the largest temporary
+   aim_setup holds on top of these (the n x n transform a new spectrum is
+   extracted from, or the near-field build's work arrays); near-field pairs
+   are bounded from the geometry (eps over the mean segment length).
+   Host-only, for admission control; 0 for invalid parameters.  Spectra that
+   stay cached after their last context (aim_cache_idle_bytes) are not part
+   of any context's estimate.                                                  */
 size_t aim_footprint_bytes(const aim_params* p, int32_t restart);
 
 /* Device bytes of a GMRES(restart) Krylov workspace for nrhs right-hand sides
@@ -365,6 +369,11 @@ aim_status aim_profile_stop(aim_ctx ctx, double* avg_ms, int64_t* samples, int64
    destroyed, up to 8 GiB of cached spectra.  aim_cache_clear frees the
    unreferenced ones and returns the bytes freed.  Thread-safe.               */
 size_t aim_cache_clear(void);
+
+/* Device bytes of the cached spectra that no context uses (what
+   aim_cache_clear would free now).  An admission budget counts them beside
+   the footprints of its contexts.  Thread-safe.                              */
+size_t aim_cache_idle_bytes(void);
 
 void aim_destroy(aim_ctx ctx);
 const char* aim_strerror(aim_status s);

@@ -107,6 +107,7 @@ EXPORTS = {
     "aim_solver_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(AimSolveInfo)]),
     "aim_solver_end": (ctypes.c_int, [ctypes.c_void_p]),
     "aim_cache_clear": (ctypes.c_size_t, []),
+    "aim_cache_idle_bytes": (ctypes.c_size_t, []),
     "aim_destroy": (None, [ctypes.c_void_p]),
     "aim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
@@ -500,6 +501,10 @@ def aim_profile_stop(ctx):
 
 def aim_cache_clear():
     return int(_lib().aim_cache_clear())
+
+
+def aim_cache_idle_bytes():
+    return int(_lib().aim_cache_idle_bytes())
 
 
 def header_functions(path=None):

@@ -247,6 +247,7 @@ aim_status setup_dual(Ctx* c);                          // T^-1 coefficients of 
 aim_status acquire_spectrum(Ctx* c, double keps);
 void release_spectrum(Ctx* c);
 size_t cache_clear();
+size_t cache_idle_bytes();
 // y(:, r) = op x(:, r), column strides ldx / ldy (elements), FP64 vectors
 aim_status matvec(Ctx* c, int op, int nrhs, const double2* x, int64_t ldx, double2* y, int64_t ldy);
 // The column pass of a split matvec: tile sets of `pairs` pairs at `tiles`

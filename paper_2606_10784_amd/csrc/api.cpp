@@ -111,6 +111,10 @@ size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   // solver's (restart), whichever is longer
   const int rs = std::max(restart, p->max_restart);
   if (rs > 0) b += gmres_work_bytes(N, rs, R);
+  // the largest transient of set-up: the full n x n transform the spectrum
+  // is extracted from (when it is not cached), or the near-field build's
+  // work arrays (row of each pair, anchors, quadrature table)
+  b += std::max(n * n * 16, near * 4 + N * 8 + 256);
   if (p->dual && p->basis == AIM_PULSE && p->xy) {   // the dual hat context (no Krylov space)
     const std::vector<double> rxy = refined_xy(p);
     aim_params q = dual_params(p, rxy);
@@ -366,6 +370,8 @@ aim_status aim_profile_stop(aim_ctx ctx, double* avg_ms, int64_t* samples, int64
 }
 
 size_t aim_cache_clear(void) { return cache_clear(); }
+
+size_t aim_cache_idle_bytes(void) { return cache_idle_bytes(); }
 
 void aim_destroy(aim_ctx ctx) {
   if (!ctx) return;

@@ -1090,6 +1090,14 @@ void release_spectrum(Ctx* c) {
   c->d_Cf = nullptr;
 }
 
+size_t cache_idle_bytes() {
+  std::lock_guard<std::mutex> lk(g_spec_mu);
+  size_t idle = 0;
+  for (SpecEntry* e : g_spec)
+    if (e->refs == 0) idle += e->bytes;
+  return idle;
+}
+
 size_t cache_clear() {
   std::lock_guard<std::mutex> lk(g_spec_mu);
   size_t freed = 0;

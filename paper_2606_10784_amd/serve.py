@@ -8,7 +8,10 @@ HIP stream from its own worker thread (set-up, right-hand sides, GMRES solve
 of all its incidences as one batch, monostatic RCS, release), so requests
 that arrive while others are on the GPU overlap with them on the device.
 Grid-kernel spectra are shared through the library's resident cache, so
-requests with the same grid and k*eps do not recompute them.
+requests with the same grid and k*eps do not recompute them.  The budget
+counts each admitted request's footprint (its tables, Krylov space, spectrum
+and the largest set-up temporary) and the cached spectra no request uses; the
+latter are dropped when a request would not fit beside them.
 
 Each solve depends only on its own request: a result is the same alone and
 in any mix (tests check this bitwise).  The executor is injectable so the
@@ -90,7 +93,33 @@ def gpu_footprint(req, restart):
                                    max_rhs=len(req.phis), restart=restart)
 
 
-class GpuExecutor:
+class GpuCache:
+    """The library's spectrum cache as seen by admission: the spectra no
+    context uses stay resident outside every footprint, so a server counts
+    them against its budget and drops them when they stand in the way."""
+
+    def cache_idle_bytes(self):
+        from . import aim
+        return aim.aim_cache_idle_bytes()
+
+    def cache_clear(self):
+        from . import aim
+        aim.aim_cache_clear()
+
+
+def admit_fits(exe, reserved, need, budget):
+    """A request of footprint `need` fits beside `reserved` bytes if the two
+    fit the budget once the idle cached spectra (if the executor has a
+    cache) are dropped; they are dropped only then."""
+    if reserved + need > budget:
+        return False
+    idle = getattr(exe, "cache_idle_bytes", None)
+    if idle is not None and reserved + need + idle() > budget:
+        exe.cache_clear()
+    return True
+
+
+class GpuExecutor(GpuCache):
     """Runs one request on the calling thread's own stream."""
 
     def __init__(self, restart=1000, maxit=4000, keep_solution=False):
@@ -193,7 +222,7 @@ class Server:
                 else:
                     pending.append(r)
                 nxt += 1
-            while pending and active < self.slots and reserved + fp[pending[0].rid] <= self.budget:
+            while pending and active < self.slots and admit_fits(self.exe, reserved, fp[pending[0].rid], self.budget):
                 r = pending.popleft()
                 reserved += fp[r.rid]
                 active += 1
@@ -224,7 +253,7 @@ class Server:
         return [results[r.rid] for r in reqs]
 
 
-class GpuStepEngine:
+class GpuStepEngine(GpuCache):
     """Step-wise requests for StepServer: set-up (context, right-hand sides,
     aim solver with its caller-owned Krylov workspace) on the request's own
     stream, one Arnoldi step per round for every running solver, retirement
@@ -366,7 +395,7 @@ class StepServer:
                         pending.append(r)
                     nxt += 1
                 while pending and len(setting_up) + len(running) < self.slots and \
-                        reserved + fp[pending[0].rid] <= self.budget:
+                        admit_fits(self.eng, reserved, fp[pending[0].rid], self.budget):
                     r = pending.popleft()
                     reserved += fp[r.rid]
                     results[r.rid].admit = time.perf_counter() - t0

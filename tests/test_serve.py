@@ -43,6 +43,52 @@ def _reqs(arrivals):
             for i, a in enumerate(arrivals)]
 
 
+class CachedExecutor(FakeExecutor):
+    """A stand-in with a spectrum cache: finished requests leave `idle` bytes
+    of cached spectra until the server clears them."""
+
+    def __init__(self, fps, durations, idle_per_request):
+        super().__init__(fps, durations)
+        self.idle = 0
+        self.per = idle_per_request
+        self.clears = 0
+
+    def __call__(self, req, res):
+        super().__call__(req, res)
+        with self.lock:
+            self.idle += self.per
+
+    def cache_idle_bytes(self):
+        with self.lock:
+            return self.idle
+
+    def cache_clear(self):
+        with self.lock:
+            self.idle = 0
+            self.clears += 1
+
+
+@pytest.mark.parametrize("stepwise", [False, True])
+def test_admission_counts_idle_cached_spectra(stepwise):
+    """Idle cached spectra count against the budget: a request that fits
+    beside the reserved footprints but not beside the idle cache gets the
+    cache dropped first; with a budget that holds both, nothing is dropped."""
+    reqs = _reqs([0.0, 0.001, 0.002, 0.003])
+    fps = {0: 60, 1: 60, 2: 60, 3: 60}
+    dur = {i: 0.01 for i in fps}
+    for budget, expect_clear in ((100, True), (1000, False)):
+        if stepwise:
+            exe = CachedStepEngine(fps, {i: 3 for i in fps}, idle_per_request=50)
+            srv = serve.StepServer(exe, hbm_budget=budget, slots=2)
+        else:
+            exe = CachedExecutor(fps, dur, idle_per_request=50)
+            srv = serve.Server(exe, hbm_budget=budget, slots=2)
+        res = srv.run(reqs)
+        assert all(r.status == "ok" for r in res)
+        assert srv.max_reserved <= budget
+        assert (exe.clears > 0) == expect_clear
+
+
 def test_admission_respects_budget_slots_and_fifo():
     reqs = _reqs([0.0, 0.001, 0.002, 0.003, 0.004, 0.005, 0.006])
     fps = {0: 40, 1: 40, 2: 40, 3: 10, 4: 90, 5: 10, 6: 200}
@@ -149,6 +195,31 @@ class FakeStepEngine:
 
     def discard(self, job):
         self.discarded += 1
+
+
+class CachedStepEngine(FakeStepEngine):
+    """Step-wise stand-in with a spectrum cache (see CachedExecutor)."""
+
+    def __init__(self, fps, steps, idle_per_request):
+        super().__init__(fps, steps)
+        self.lock = threading.Lock()
+        self.idle = 0
+        self.per = idle_per_request
+        self.clears = 0
+
+    def finish(self, req, job, res):
+        super().finish(req, job, res)
+        with self.lock:
+            self.idle += self.per
+
+    def cache_idle_bytes(self):
+        with self.lock:
+            return self.idle
+
+    def cache_clear(self):
+        with self.lock:
+            self.idle = 0
+            self.clears += 1
 
 
 def test_step_server_admission_budget_slots_fifo():
