@@ -1562,6 +1562,79 @@ __global__ __launch_bounds__(256) void k_dual_in(int N, int nrhs, int D, const d
   }
 }
 
+// k_dual_in for the banded T^-1 (D >= 0): the block's x and 1/h window
+// (256 + 2 kTauD values, cyclic) is staged in LDS; each sum runs over the
+// same terms in the same order as tinv_at.
+__global__ __launch_bounds__(256) void k_dual_in_band(int N, const double* __restrict__ tau,
+                                                      const double* __restrict__ ih, const double2* __restrict__ x,
+                                                      int64_t ldx, double2* __restrict__ u, int64_t ldu) {
+  constexpr int W = 256 + 2 * kTauD;
+  __shared__ double2 xs[W];
+  __shared__ double hs[W];
+  __shared__ double2 zs[256];
+  const int t = threadIdx.x, r = blockIdx.y;
+  const double2* xr = x + (size_t)r * ldx;
+  const int64_t base = (int64_t)blockIdx.x * 255 - 1 - kTauD;   // unknown of window slot 0
+  for (int k = t; k < W; k += 256) {
+    int q = (int)((base + k) % N);
+    if (q < 0) q += N;
+    xs[k] = xr[q];
+    hs[k] = ih[q];
+  }
+  __syncthreads();
+  const int j = blockIdx.x * 255 + t - 1;   // this thread's z index (j = -1: the halo)
+  if (j < N) {
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int d = -kTauD; d <= kTauD; ++d) {
+      const int k = t + kTauD + d;
+      const double f = tau[d < 0 ? -d : d] * hs[k];
+      ax += f * xs[k].x;
+      ay += f * xs[k].y;
+    }
+    zs[t] = make_double2(ax, ay);
+  }
+  __syncthreads();
+  if (t >= 1 && j < N) {
+    double2* ur = u + (size_t)r * ldu;
+    const double2 zj = zs[t], zm = zs[t - 1];
+    ur[2 * j + 1] = zj;
+    ur[2 * j] = make_double2(0.5 * (zm.x + zj.x), 0.5 * (zm.y + zj.y));
+  }
+}
+
+// k_dual_gather and k_dual_out in one pass for the banded T^-1: the block
+// forms g_q = w_2q / 2 + w_2q+1 + w_2q+2 / 2 over its output window plus
+// kTauD on each side (cyclic) in LDS, then y_i = (T^-1 g)_i / h_i with the
+// terms in tinv_at's order.
+__global__ __launch_bounds__(256) void k_dual_out_band(int N, const double* __restrict__ tau,
+                                                       const double* __restrict__ ih, const double2* __restrict__ w,
+                                                       int64_t ldw, double2* __restrict__ y, int64_t ldy) {
+  constexpr int W = 256 + 2 * kTauD;
+  __shared__ double2 gs[W];
+  const int t = threadIdx.x, r = blockIdx.y;
+  const double2* wr = w + (size_t)r * ldw;
+  const int64_t base = (int64_t)blockIdx.x * 256 - kTauD;
+  for (int k = t; k < W; k += 256) {
+    int q = (int)((base + k) % N);
+    if (q < 0) q += N;
+    const double2 a = wr[2 * q], b = wr[2 * q + 1], e = wr[q == N - 1 ? 0 : 2 * q + 2];
+    gs[k] = make_double2(0.5 * a.x + b.x + 0.5 * e.x, 0.5 * a.y + b.y + 0.5 * e.y);
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + t;
+  if (i >= N) return;
+  double ax = 0.0, ay = 0.0;
+#pragma unroll
+  for (int d = -kTauD; d <= kTauD; ++d) {
+    const int k = t + kTauD + d;
+    const double f = tau[d < 0 ? -d : d];
+    ax += f * gs[k].x;
+    ay += f * gs[k].y;
+  }
+  y[(size_t)r * ldy + i] = make_double2(ax * ih[i], ay * ih[i]);
+}
+
 // g_j = w_2j / 2 + w_2j+1 + w_2j+2 / 2 (R w)
 __global__ void k_dual_gather(int N, int nrhs, const double2* __restrict__ w, int64_t ldw, double2* __restrict__ g,
                               int64_t ldg) {
@@ -1589,15 +1662,25 @@ static aim_status tm_precond(Ctx* c, bool filtered, bool f32, int nrhs, const do
   Ctx* d = c->dual;
   const int N = c->t.N, N2 = d->t.N;
   const dim3 g((N + 255) / 256, nrhs);
-  hipLaunchKernelGGL(k_dual_in, dim3((N + 254) / 255, nrhs), dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau,
-                     c->d_ih, x, ldx, d->d_tmp1, (int64_t)N2);
+  const bool band = c->tau_D >= 0;
+  if (band)
+    hipLaunchKernelGGL(k_dual_in_band, dim3((N + 254) / 255, nrhs), dim3(256), 0, c->stream, N, c->d_tau, c->d_ih, x,
+                       ldx, d->d_tmp1, (int64_t)N2);
+  else
+    hipLaunchKernelGGL(k_dual_in, dim3((N + 254) / 255, nrhs), dim3(256), 0, c->stream, N, nrhs, c->tau_D,
+                       c->d_tau, c->d_ih, x, ldx, d->d_tmp1, (int64_t)N2);
   AIM_HIP_CHECK(hipGetLastError());
   const int nop = (filtered ? AIM_OP_N_ALPHA : AIM_OP_N) | (f32 ? AIM_OP_GRID_FP32 : 0);
   TRY(matvec(d, nop, nrhs, d->d_tmp1, N2, d->d_tmp2, N2));
-  hipLaunchKernelGGL(k_dual_gather, g, dim3(256), 0, c->stream, N, nrhs, d->d_tmp2, (int64_t)N2, d->d_tmp1,
-                     (int64_t)N);
-  hipLaunchKernelGGL(k_dual_out, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_ih, d->d_tmp1,
-                     (int64_t)N, y, ldy);
+  if (band) {
+    hipLaunchKernelGGL(k_dual_out_band, g, dim3(256), 0, c->stream, N, c->d_tau, c->d_ih, d->d_tmp2, (int64_t)N2, y,
+                       ldy);
+  } else {
+    hipLaunchKernelGGL(k_dual_gather, g, dim3(256), 0, c->stream, N, nrhs, d->d_tmp2, (int64_t)N2, d->d_tmp1,
+                       (int64_t)N);
+    hipLaunchKernelGGL(k_dual_out, g, dim3(256), 0, c->stream, N, nrhs, c->tau_D, c->d_tau, c->d_ih, d->d_tmp1,
+                       (int64_t)N, y, ldy);
+  }
   AIM_HIP_CHECK(hipGetLastError());
   return AIM_OK;
 }
