@@ -754,16 +754,23 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
     lowc = low > W / 2 ? W - low : low;
     return low > W / 2;
   };
-  auto load_spec = [&](int bb, V* cv) {
+  auto load_spec_part = [&](int bb, V* cv, int r0, int r1) {
     const int g = bb % NG, c = bb / NG;
     int kx, kxq, lowc;
     col_of(b, c, N, CB, kx, kxq);
     mirrored(g, lowc);
     const V* Cp = Cq + (size_t)kxq * HS + lowc * RL;
 #pragma unroll
-    for (int r = 0; r < RL; ++r) cv[r] = Cp[r];
+    for (int r = 0; r < RL; ++r)
+      if (r >= r0 && r < r1) cv[r] = Cp[r];
   };
+  auto load_spec = [&](int bb, V* cv) { load_spec_part(bb, cv, 0, RL); };
   constexpr bool PRE = sizeof(T) == 8 && N <= 2048 && PERF * RL <= 16;
+  // FP64 above N = 2048 (one block per CU): half of the spectrum loads go
+  // out once the first pass has left its values in LDS, so their latency
+  // overlaps the middle pass in registers the first pass has freed, and the
+  // other half right after the middle pass (all of them at once would spill)
+  constexpr bool LATE = sizeof(T) == 8 && !PRE && MID && PERF * RL <= 16;
   V cv[PERF][RL];
   if constexpr (PRE) {
 #pragma unroll
@@ -796,8 +803,22 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       for (int r = 0; r < 16; ++r) buf[cidx<T>((m + r * S1) * CB + c)] = v[q][r];
     }
   }
+  if constexpr (LATE) {
+#pragma unroll
+    for (int q = 0; q < PERF; ++q) {
+      const int bb = tid + q * NT;
+      if ((NBF % NT) == 0 || bb < NBF) load_spec_part(bb, cv[q], 0, RL / 2);
+    }
+  }
   __syncthreads();
   if constexpr (MID) ct_pass_w<T, N, CB, NT, false, SM, 16>(buf, wm);
+  if constexpr (LATE) {
+#pragma unroll
+    for (int q = 0; q < PERF; ++q) {
+      const int bb = tid + q * NT;
+      if ((NBF % NT) == 0 || bb < NBF) load_spec_part(bb, cv[q], RL / 2, RL);
+    }
+  }
   // last forward pass (contiguous groups of RL), spectrum multiply in the
   // stored frequency order, first inverse pass; lanes run along the groups
 #pragma unroll
@@ -805,7 +826,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
     const int bb = tid + q * NT;
     if ((NBF % NT) == 0 || bb < NBF) {
       const int g = bb % NG, c = bb / NG;
-      if constexpr (!PRE) load_spec(bb, cv[q]);
+      if constexpr (!PRE && !LATE) load_spec(bb, cv[q]);
       V u[RL];
 #pragma unroll
       for (int r = 0; r < RL; ++r) u[r] = buf[cidx<T>((g * RL + r) * CB + c)];
