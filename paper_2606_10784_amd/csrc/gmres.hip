@@ -242,6 +242,18 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(int N, int j, int nchunk
     double ax = 0, ay = 0, bx = 0, by = 0;
     const double2* pi = pr + (size_t)i * nchunk * 2;
     int c = 0;
+    for (; c + 7 < nchunk; c += 8) {   // 16 loads in flight, summed in chunk order
+      double2 t[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) t[q] = pi[2 * c + q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        ax += t[2 * q].x;
+        ay += t[2 * q].y;
+        bx += t[2 * q + 1].x;
+        by += t[2 * q + 1].y;
+      }
+    }
     for (; c + 3 < nchunk; c += 4) {   // 8 loads in flight, summed in chunk order
       double2 t[8];
 #pragma unroll
