@@ -483,13 +483,34 @@ template <int N> constexpr int last_radix() {
 // pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror N - q); the last slot pair
 // of the last block holds the self-mirrored columns 0 and N/2.
 // ---------------------------------------------------------------------------
+// CB is the tile width (columns per tile, the row passes' piece); CW the
+// columns one column-pass block transforms: CB, or 1 where two columns do
+// not fit the LDS budget (FP64 at N = 4096), so that two blocks share a CU
+// (the two blocks of a tile then take one column each).
 template <typename T, int N> struct ColCfg {
   static constexpr int BYTES = 80000;   // padded LDS per column block: two blocks per CU
   static constexpr int CB0 = BYTES / (padded(N) * (int)sizeof(cplx<T>));
   static constexpr int CB1 = CB0 < 2 ? 2 : (CB0 > 16 ? 16 : CB0);
   static constexpr int CB = (CB1 >= 16) ? 16 : (CB1 >= 8 ? 8 : (CB1 >= 4 ? 4 : 2));
-  static constexpr int NT = (N * CB / 16 >= 512) ? 512 : 256;
+  static constexpr int CW = CB0 < 2 ? 1 : CB;
+  static constexpr int NT = (N * CW / 16 >= 512) ? 512 : 256;
 };
+
+// Column-pass block b -> tile tb and first column c0 within the tile.  With
+// one column per block the two columns of a tile go to blocks 8 apart, which
+// the launch deals to the same XCD, so the halves of each tile line meet in
+// one L2.
+template <typename T, int N>
+__device__ __forceinline__ void col_block_of(int b, int& tb, int& c0) {
+  if constexpr (ColCfg<T, N>::CW == ColCfg<T, N>::CB) {
+    tb = b;
+    c0 = 0;
+  } else {
+    static_assert(ColCfg<T, N>::CW == 1 && ColCfg<T, N>::CB == 2, "one column of two per block");
+    tb = (b >> 4) * 8 + (b & 7);
+    c0 = (b >> 3) & 1;
+  }
+}
 
 __device__ __forceinline__ void col_of(int b, int c, int N, int CB, int& kx, int& kxq) {
   const int q = b * (CB / 2) + (c >> 1) + 1;
@@ -706,10 +727,12 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 // column is the zero padding), in place: column FFT, spectrum multiply,
 // inverse column FFT (the MODE 0 body of k_cols and of k_cols_group).
 template <typename T, int N>
-__device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict__ tile, int nr, int b,
+__device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict__ tile, int nr, int b, int c0_,
                                                const cplx<T>* __restrict__ Cq, const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
-  constexpr int CB = ColCfg<T, N>::CB;
+  constexpr int CB = ColCfg<T, N>::CB;   // tile width (global layout)
+  constexpr int CW = ColCfg<T, N>::CW;   // columns of this block, c0 .. c0 + CW - 1 (LDS layout)
+  const int c0 = CW == CB ? 0 : c0_;
   constexpr int NT = ColCfg<T, N>::NT;
   const int tid = threadIdx.x;
   static_assert(N >= 32, "column pass assumes at least two forward passes");
@@ -718,9 +741,9 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
   constexpr int SM = N / 256;                   // middle radix-16 pass stride
   constexpr bool MID = SM >= RL && SM >= 1;
   static_assert(!MID || SM / 16 < RL, "at most one middle pass per direction");
-  constexpr int NB1 = S1 * CB, PER1 = (NB1 + NT - 1) / NT;
-  constexpr int NBM = (N / 16) * CB, PERM = (NBM + NT - 1) / NT;
-  constexpr int NG = N / RL, NBF = NG * CB, PERF = (NBF + NT - 1) / NT;
+  constexpr int NB1 = S1 * CW, PER1 = (NB1 + NT - 1) / NT;
+  constexpr int NBM = (N / 16) * CW, PERM = (NBM + NT - 1) / NT;
+  constexpr int NG = N / RL, NBF = NG * CW, PERF = (NBF + NT - 1) / NT;
   // forward pass 1 (stride N/16, radix 16) from HBM: inputs m + S1 r with
   // r >= 8 lie in the zero half
   V v[PER1][16];
@@ -728,11 +751,11 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
   for (int q = 0; q < PER1; ++q) {
     const int bb = tid + q * NT;
     if ((NB1 % NT) == 0 || bb < NB1) {
-      const int c = bb % CB, m = bb / CB;
+      const int c = bb % CW, m = bb / CW;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int i = m + r * S1;
-        v[q][r] = i < nr ? tile[(size_t)i * CB + c] : mk<T>(0, 0);
+        v[q][r] = i < nr ? tile[(size_t)i * CB + c0 + c] : mk<T>(0, 0);
       }
     }
   }
@@ -757,7 +780,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
   auto load_spec_part = [&](int bb, V* cv, int r0, int r1) {
     const int g = bb % NG, c = bb / NG;
     int kx, kxq, lowc;
-    col_of(b, c, N, CB, kx, kxq);
+    col_of(b, c0 + c, N, CB, kx, kxq);
     mirrored(g, lowc);
     const V* Cp = Cq + (size_t)kxq * HS + lowc * RL;
 #pragma unroll
@@ -783,24 +806,24 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
 #pragma unroll
   for (int q = 0; q < PER1; ++q) {
     const int bb = tid + q * NT;
-    w1[q] = ((NB1 % NT) == 0 || bb < NB1) ? tw_base<T, N, S1, 16>(bb / CB, tw) : mk<T>(1, 0);
+    w1[q] = ((NB1 % NT) == 0 || bb < NB1) ? tw_base<T, N, S1, 16>(bb / CW, tw) : mk<T>(1, 0);
   }
   if constexpr (MID) {
 #pragma unroll
     for (int q = 0; q < PERM; ++q) {
       const int bb = tid + q * NT;
-      wm[q] = ((NBM % NT) == 0 || bb < NBM) ? tw_base<T, N, SM, 16>((bb / CB) % SM, tw) : mk<T>(1, 0);
+      wm[q] = ((NBM % NT) == 0 || bb < NBM) ? tw_base<T, N, SM, 16>((bb / CW) % SM, tw) : mk<T>(1, 0);
     }
   }
 #pragma unroll
   for (int q = 0; q < PER1; ++q) {
     const int bb = tid + q * NT;
     if ((NB1 % NT) == 0 || bb < NB1) {
-      const int c = bb % CB, m = bb / CB;
+      const int c = bb % CW, m = bb / CW;
       dft16_halfin<T, false>(v[q]);
       apply_twiddle<T, false, S1, 16>(v[q], w1[q]);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) buf[cidx<T>((m + r * S1) * CB + c)] = v[q][r];
+      for (int r = 0; r < 16; ++r) buf[cidx<T>((m + r * S1) * CW + c)] = v[q][r];
     }
   }
   if constexpr (LATE) {
@@ -811,7 +834,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
     }
   }
   __syncthreads();
-  if constexpr (MID) ct_pass_w<T, N, CB, NT, false, SM, 16>(buf, wm);
+  if constexpr (MID) ct_pass_w<T, N, CW, NT, false, SM, 16>(buf, wm);
   if constexpr (LATE) {
 #pragma unroll
     for (int q = 0; q < PERF; ++q) {
@@ -829,7 +852,7 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       if constexpr (!PRE && !LATE) load_spec(bb, cv[q]);
       V u[RL];
 #pragma unroll
-      for (int r = 0; r < RL; ++r) u[r] = buf[cidx<T>((g * RL + r) * CB + c)];
+      for (int r = 0; r < RL; ++r) u[r] = buf[cidx<T>((g * RL + r) * CW + c)];
       int lowc;
       const bool mir = mirrored(g, lowc);
       dft_r<T, RL, false>(u);
@@ -837,27 +860,27 @@ __device__ __forceinline__ void cols_conv_tile(cplx<T>* buf, cplx<T>* __restrict
       for (int r = 0; r < RL; ++r) u[r] = cmul(u[r], mir ? cv[q][RL - 1 - r] : cv[q][r]);
       dft_r<T, RL, true>(u);
 #pragma unroll
-      for (int r = 0; r < RL; ++r) buf[cidx<T>((g * RL + r) * CB + c)] = u[r];
+      for (int r = 0; r < RL; ++r) buf[cidx<T>((g * RL + r) * CW + c)] = u[r];
     }
   }
   __syncthreads();
-  if constexpr (MID) ct_pass_w<T, N, CB, NT, true, SM, 16>(buf, wm);
+  if constexpr (MID) ct_pass_w<T, N, CW, NT, true, SM, 16>(buf, wm);
   // last inverse pass (stride N/16, radix 16) straight to HBM: outputs
   // m + S1 r, only r < 8 can be a kept row
 #pragma unroll
   for (int q = 0; q < PER1; ++q) {
     const int bb = tid + q * NT;
     if ((NB1 % NT) == 0 || bb < NB1) {
-      const int c = bb % CB, m = bb / CB;
+      const int c = bb % CW, m = bb / CW;
       V u[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) u[r] = buf[cidx<T>((m + r * S1) * CB + c)];
+      for (int r = 0; r < 16; ++r) u[r] = buf[cidx<T>((m + r * S1) * CW + c)];
       apply_twiddle<T, true, S1, 16>(u, w1[q]);
       dft16_halfout<T, true>(u);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int i = m + r * S1;
-        if (i < nr) tile[(size_t)i * CB + c] = u[r];
+        if (i < nr) tile[(size_t)i * CB + c0 + c] = u[r];
       }
     }
   }
@@ -869,24 +892,27 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols(
     const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
   constexpr int CB = ColCfg<T, N>::CB;
+  constexpr int CW = ColCfg<T, N>::CW;
   constexpr int NT = ColCfg<T, N>::NT;
   constexpr int NBLK = N / CB;
-  __shared__ V buf[padded(N * CB)];
+  __shared__ V buf[padded(N * CW)];
   const int b = blockIdx.x;
   const int pair = blockIdx.y;
   const int tid = threadIdx.x;
   if constexpr (MODE == 0) {
-    cols_conv_tile<T, N>(buf, Tb + ((size_t)pair * NBLK + b) * ldt * CB, nr, b, Cq, tw);
+    int tb, c0;
+    col_block_of<T, N>(b, tb, c0);
+    cols_conv_tile<T, N>(buf, Tb + ((size_t)pair * NBLK + tb) * ldt * CB, nr, tb, c0, Cq, tw);
   } else {
-    const int kx0 = b * CB;
-    for (int idx = tid; idx < N * CB; idx += NT) {
-      const int i = idx / CB, c = idx % CB;
+    const int kx0 = b * CW;
+    for (int idx = tid; idx < N * CW; idx += NT) {
+      const int i = idx / CW, c = idx % CW;
       buf[pidx(idx)] = Tb[(size_t)i * N + kx0 + c];
     }
     __syncthreads();
-    fft_passes<T, N, CB, NT, false, 1>(buf, tw);
-    for (int idx = tid; idx < N * CB; idx += NT) {
-      const int i = idx / CB, c = idx % CB;
+    fft_passes<T, N, CW, NT, false, 1>(buf, tw);
+    for (int idx = tid; idx < N * CW; idx += NT) {
+      const int i = idx / CW, c = idx % CW;
       Tb[(size_t)i * N + kx0 + c] = buf[pidx(idx)];
     }
   }
@@ -908,10 +934,12 @@ __global__ __launch_bounds__((ColCfg<T, N>::NT)) void k_cols_group(ColBatch batc
                                                                  const cplx<T>* __restrict__ tw) {
   using V = cplx<T>;
   constexpr int CB = ColCfg<T, N>::CB;
-  __shared__ V buf[padded(N * CB)];
-  const int e = blockIdx.y, b = blockIdx.x;
-  V* tile = (V*)batch.tile[e] + (size_t)b * batch.ldt[e] * CB;
-  cols_conv_tile<T, N>(buf, tile, batch.nr[e], b, Cq, tw);
+  __shared__ V buf[padded(N * ColCfg<T, N>::CW)];
+  const int e = blockIdx.y;
+  int tb, c0;
+  col_block_of<T, N>(blockIdx.x, tb, c0);
+  V* tile = (V*)batch.tile[e] + (size_t)tb * batch.ldt[e] * CB;
+  cols_conv_tile<T, N>(buf, tile, batch.nr[e], tb, c0, Cq, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -965,7 +993,7 @@ aim_status launch_cols(int n, int mode, cplx<T>* Tb, int nr, int ldt, int pairs,
   switch (n) {
 #define CASE(NN)                                                                          \
   case NN: {                                                                              \
-    dim3 g(NN / ColCfg<T, NN>::CB, pairs);                                                \
+    dim3 g(NN / ColCfg<T, NN>::CW, pairs);                                                \
     if (mode == 0)                                                                        \
       hipExtLaunchKernelGGL((k_cols<T, NN, 0>), g, dim3(ColCfg<T, NN>::NT), 0, s, ev_start, ev_stop, 0, \
                             Tb, nr, ldt, Cq, tw);                                         \
@@ -1007,7 +1035,7 @@ aim_status launch_cols_group(int n, int count, void* const* tiles, const int* nr
   switch (n) {
 #define CASE(NN)                                                                                              \
   case NN:                                                                                                    \
-    hipLaunchKernelGGL((k_cols_group<T, NN>), dim3(NN / ColCfg<T, NN>::CB, count), dim3(ColCfg<T, NN>::NT), 0, \
+    hipLaunchKernelGGL((k_cols_group<T, NN>), dim3(NN / ColCfg<T, NN>::CW, count), dim3(ColCfg<T, NN>::NT), 0, \
                        s, bt, Cq, tw);                                                                        \
     break;
     AIM_FOR_SIZES(CASE)
