@@ -713,7 +713,35 @@ __global__ __launch_bounds__(256) void k_interp_band(
   const double w0 = (double)W0[o];
   const double w1 = nch > 1 ? (double)W1[o] : 0.0;
   const double w2 = nch > 1 ? (double)W2[o] : 0.0;
+  // bands up to KU * L - 1 wide: the lane's band values (the same for every
+  // rhs) are loaded once, ahead of everything else, and each rhs issues all
+  // its x loads before its first sum; the terms are added in the order of
+  // the general loop below
+  constexpr int KU = 4;
+  const bool fast = Cd && w < KU * L;
+  double2 cu[KU], cl[KU];
+  int ju[KU], il[KU];
+  if (fast) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const int d = l + k * L, dl = d + 1;
+      ju[k] = row + d >= N ? row + d - N : row + d;
+      il[k] = row - dl < 0 ? row - dl + N : row - dl;
+      cu[k] = d <= w ? Cd[(size_t)d * N + row] : make_double2(0.0, 0.0);
+      cl[k] = dl <= w ? Cd[(size_t)dl * N + il[k]] : make_double2(0.0, 0.0);
+    }
+  }
   for (int r = 0; r < nrhs; ++r) {
+    const double2* xr = x + (size_t)r * ldx;
+    double2 xu[KU], xl[KU];
+    if (fast) {
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const int d = l + k * L;
+        xu[k] = d <= w ? xr[ju[k]] : make_double2(0.0, 0.0);
+        xl[k] = d + 1 <= w ? xr[il[k]] : make_double2(0.0, 0.0);
+      }
+    }
     const cplx<T> v0 = V[(size_t)r * n_act + a];
     double ax = w0 * (double)v0.x, ay = w0 * (double)v0.y;
     if (nch > 1) {
@@ -722,8 +750,19 @@ __global__ __launch_bounds__(256) void k_interp_band(
       ax += sg * (w1 * (double)v1.x + w2 * (double)v2.x);
       ay += sg * (w1 * (double)v1.y + w2 * (double)v2.y);
     }
-    if (Cd) {
-      const double2* xr = x + (size_t)r * ldx;
+    if (fast) {
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const int d = l + k * L;
+        if (d > w) break;
+        ax += cu[k].x * xu[k].x - cu[k].y * xu[k].y;
+        ay += cu[k].x * xu[k].y + cu[k].y * xu[k].x;
+        if (d + 1 <= w) {
+          ax += cl[k].x * xl[k].x - cl[k].y * xl[k].y;
+          ay += cl[k].x * xl[k].y + cl[k].y * xl[k].x;
+        }
+      }
+    } else if (Cd) {
       for (int d = l; d <= w; d += L) {
         int ju = row + d;
         if (ju >= N) ju -= N;
