@@ -558,44 +558,66 @@ __global__ void k_near_build(NearGeo G, int basis, int64_t nnz, const int32_t* _
 // ---------------------------------------------------------------------------
 // anterpolation: U[ch*nrhs + r][a] = sum_e w_ch[e] x[r*ldx + basis_e]
 // ---------------------------------------------------------------------------
-template <typename T, typename TW>
+// right-hand sides per k_anterp block in batches of four or more
+constexpr int kAnterpRhs = 4;
+
+template <typename T, typename TW, int ARB>
 __global__ __launch_bounds__(256) void k_anterp(int n_act, int nrhs, const int32_t* __restrict__ at_ptr,
                                                 const int32_t* __restrict__ at_basis, const TW* __restrict__ w0,
                                                 const TW* __restrict__ w1, const TW* __restrict__ w2,
                                                 const double2* __restrict__ x, int64_t ldx,
                                                 cplx<T>* __restrict__ U) {
-  // 16 lanes per active grid point, shuffle reduction
+  // 16 lanes per active grid point, shuffle reduction; blockIdx.y picks a
+  // channel and a run of up to ARB right-hand sides, which share the entry
+  // loads (basis index, weight) and keep their own sums
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int a = gid >> 4, l = gid & 15;
-  const int pair = blockIdx.y;              // ch * nrhs + r
+  const int nrb = (nrhs + ARB - 1) / ARB;
+  const int ch = blockIdx.y / nrb, r0 = (blockIdx.y - ch * nrb) * ARB;
   if (a >= n_act) return;                   // whole 16-lane groups exit together
-  const int ch = pair / nrhs, r = pair - ch * nrhs;
+  const int nr = ARB == 1 ? 1 : min(ARB, nrhs - r0);
   const TW* w = ch == 0 ? w0 : (ch == 1 ? w1 : w2);
-  const double2* xr = x + (size_t)r * ldx;
-  T sx = 0, sy = 0;
+  const double2* xr = x + (size_t)r0 * ldx;
+  T sx[ARB], sy[ARB];
+#pragma unroll
+  for (int k = 0; k < ARB; ++k) sx[k] = sy[k] = 0;
   const int e1 = at_ptr[a + 1];
   int e = at_ptr[a] + l;
   for (; e + 16 < e1; e += 32) {   // two entries per lane in flight
     const int b0 = at_basis[e], b1 = at_basis[e + 16];
     const T w0e = (T)w[e], w1e = (T)w[e + 16];
-    const double2 x0 = xr[b0], x1 = xr[b1];
-    sx += w0e * (T)x0.x;
-    sy += w0e * (T)x0.y;
-    sx += w1e * (T)x1.x;
-    sy += w1e * (T)x1.y;
+#pragma unroll
+    for (int k = 0; k < ARB; ++k) {
+      if (k < nr) {
+        const double2 x0 = xr[(size_t)k * ldx + b0], x1 = xr[(size_t)k * ldx + b1];
+        sx[k] += w0e * (T)x0.x;
+        sy[k] += w0e * (T)x0.y;
+        sx[k] += w1e * (T)x1.x;
+        sy[k] += w1e * (T)x1.y;
+      }
+    }
   }
   if (e < e1) {
-    const double2 xv = xr[at_basis[e]];
+    const int b0 = at_basis[e];
     const T ww = (T)w[e];
-    sx += ww * (T)xv.x;
-    sy += ww * (T)xv.y;
+#pragma unroll
+    for (int k = 0; k < ARB; ++k) {
+      if (k < nr) {
+        const double2 xv = xr[(size_t)k * ldx + b0];
+        sx[k] += ww * (T)xv.x;
+        sy[k] += ww * (T)xv.y;
+      }
+    }
   }
 #pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) {
-    sx += __shfl_xor(sx, off, 16);
-    sy += __shfl_xor(sy, off, 16);
+  for (int k = 0; k < ARB; ++k) {
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+      sx[k] += __shfl_xor(sx[k], off, 16);
+      sy[k] += __shfl_xor(sy[k], off, 16);
+    }
+    if (l == 0 && k < nr) U[(size_t)(ch * nrhs + r0 + k) * n_act + a] = mk<T>(sx[k], sy[k]);
   }
-  if (l == 0) U[(size_t)pair * n_act + a] = mk<T>(sx, sy);
 }
 
 // ---------------------------------------------------------------------------
@@ -1411,18 +1433,24 @@ static aim_status grid_pre(Ctx* c, const int* chans, int nch, int nrhs, const do
   cplx<T>* U = (cplx<T>*)c->d_U;
   cplx<T>* Tb = (cplx<T>*)c->d_T;
   const bool f32 = sizeof(T) == 4;
-  dim3 ga((unsigned)(((size_t)t.n_act * 16 + 255) / 256), pairs);
+  // a single rhs keeps one sum per lane; batches share the entry loads
+  const int arb = nrhs >= kAnterpRhs ? kAnterpRhs : 1;
+  dim3 ga((unsigned)(((size_t)t.n_act * 16 + 255) / 256), nch * ((nrhs + arb - 1) / arb));
   {
   ProfScope ps(c, AIM_K_ANTERP);
+#define AIM_ANTERP(TW, WS)                                                                                          \
+  if (arb == 1)                                                                                                     \
+    hipLaunchKernelGGL((k_anterp<T, TW, 1>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr, c->d_at_basis,       \
+                       WS[chans[0]], WS[chans[nch > 1 ? 1 : 0]], WS[chans[nch > 2 ? 2 : 0]], x, ldx, U);             \
+  else                                                                                                              \
+    hipLaunchKernelGGL((k_anterp<T, TW, kAnterpRhs>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr,             \
+                       c->d_at_basis, WS[chans[0]], WS[chans[nch > 1 ? 1 : 0]], WS[chans[nch > 2 ? 2 : 0]], x, ldx, U);
   if (f32) {
-    hipLaunchKernelGGL((k_anterp<T, float>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr, c->d_at_basis,
-                       c->d_at_wf[chans[0]], c->d_at_wf[chans[nch > 1 ? 1 : 0]], c->d_at_wf[chans[nch > 2 ? 2 : 0]],
-                       x, ldx, U);
+    AIM_ANTERP(float, c->d_at_wf)
   } else {
-    hipLaunchKernelGGL((k_anterp<T, double>), ga, dim3(256), 0, s, t.n_act, nrhs, c->d_at_ptr, c->d_at_basis,
-                       c->d_at_w[chans[0]], c->d_at_w[chans[nch > 1 ? 1 : 0]], c->d_at_w[chans[nch > 2 ? 2 : 0]],
-                       x, ldx, U);
+    AIM_ANTERP(double, c->d_at_w)
   }
+#undef AIM_ANTERP
   }
   AIM_HIP_CHECK(hipGetLastError());
   ProfScope ps(c, AIM_K_ROWS_FWD);
