@@ -484,31 +484,35 @@ template <int N> constexpr int last_radix() {
 // of the last block holds the self-mirrored columns 0 and N/2.
 // ---------------------------------------------------------------------------
 // CB is the tile width (columns per tile, the row passes' piece); CW the
-// columns one column-pass block transforms: CB, or 1 where two columns do
-// not fit the LDS budget (FP64 at N = 4096), so that two blocks share a CU
-// (the two blocks of a tile then take one column each).
+// columns one column-pass block transforms: as many as fit the LDS budget
+// of two blocks per CU.  Tiles are at least 64 bytes wide, so the row
+// passes read and write whole 64-byte pieces; where CW is narrower (N >=
+// 2048 in either precision) the CB / CW blocks of a tile take CW columns
+// each.
 template <typename T, int N> struct ColCfg {
   static constexpr int BYTES = 80000;   // padded LDS per column block: two blocks per CU
   static constexpr int CB0 = BYTES / (padded(N) * (int)sizeof(cplx<T>));
-  static constexpr int CB1 = CB0 < 2 ? 2 : (CB0 > 16 ? 16 : CB0);
-  static constexpr int CB = (CB1 >= 16) ? 16 : (CB1 >= 8 ? 8 : (CB1 >= 4 ? 4 : 2));
-  static constexpr int CW = CB0 < 2 ? 1 : CB;
+  static constexpr int CW1 = CB0 < 2 ? 1 : (CB0 > 16 ? 16 : CB0);
+  static constexpr int CW = (CW1 >= 16) ? 16 : (CW1 >= 8 ? 8 : (CW1 >= 4 ? 4 : (CW1 >= 2 ? 2 : 1)));
+  // tiles at least 64 bytes wide, so the row passes move whole 64-byte pieces
+  static constexpr int CB64 = 64 / (int)sizeof(cplx<T>);
+  static constexpr int CB = CW > CB64 ? CW : CB64;
   static constexpr int NT = (N * CW / 16 >= 512) ? 512 : 256;
 };
 
-// Column-pass block b -> tile tb and first column c0 within the tile.  With
-// one column per block the two columns of a tile go to blocks 8 apart, which
-// the launch deals to the same XCD, so the halves of each tile line meet in
-// one L2.
+// Column-pass block b -> tile tb and first column c0 within the tile.  The
+// K = CB / CW blocks of a tile are 8 apart, which the launch deals to the
+// same XCD, so the parts of each tile line meet in one L2.
 template <typename T, int N>
 __device__ __forceinline__ void col_block_of(int b, int& tb, int& c0) {
-  if constexpr (ColCfg<T, N>::CW == ColCfg<T, N>::CB) {
+  constexpr int CB = ColCfg<T, N>::CB, CW = ColCfg<T, N>::CW, K = CB / CW;   // blocks per tile
+  if constexpr (K == 1) {
     tb = b;
     c0 = 0;
   } else {
-    static_assert(ColCfg<T, N>::CW == 1 && ColCfg<T, N>::CB == 2, "one column of two per block");
-    tb = (b >> 4) * 8 + (b & 7);
-    c0 = (b >> 3) & 1;
+    static_assert(K * CW == CB && (K & (K - 1)) == 0 && (N / CB) % 8 == 0, "tile split into 2^k blocks");
+    tb = (b / (8 * K)) * 8 + (b & 7);
+    c0 = ((b >> 3) & (K - 1)) * CW;
   }
 }
 

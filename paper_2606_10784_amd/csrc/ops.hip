@@ -709,10 +709,13 @@ __global__ void k_near_to_band(int64_t nnz, int N, int w, const int32_t* __restr
   if (d <= w) Cd[(size_t)d * N + i] = C[q];
 }
 
+// band widths below this take the several-rhs form of the band product
+constexpr int kBandFastW = 64;
+
 // interpolation + banded near field, 16 lanes per basis row:
 //   y_i = scale * ( sum_ch sgn_ch W_ch . V_ch + sum_{d<=w} Cd[d][i] x_{i+d}
 //                   + sum_{1<=d<=w} Cd[d][i-d] x_{i-d} )   (indices mod N)
-template <typename T, typename TW>
+template <typename T, typename TW, bool FAST>
 __global__ __launch_bounds__(256) void k_interp_band(
     int N, int nrhs, int nch, const TW* __restrict__ W0, const TW* __restrict__ W1, const TW* __restrict__ W2,
     double sg, const int32_t* __restrict__ aidx, const cplx<T>* __restrict__ V, int n_act, int w,
@@ -735,15 +738,15 @@ __global__ __launch_bounds__(256) void k_interp_band(
   const double w0 = (double)W0[o];
   const double w1 = nch > 1 ? (double)W1[o] : 0.0;
   const double w2 = nch > 1 ? (double)W2[o] : 0.0;
-  // bands up to KU * L - 1 wide: the lane's band values (the same for every
-  // rhs) are loaded once, ahead of everything else, and each rhs issues all
-  // its x loads before its first sum; the terms are added in the order of
-  // the general loop below
-  constexpr int KU = 4;
-  const bool fast = Cd && w < KU * L;
+  // FAST (several rhs, a band up to KU * L - 1 wide): the lane's band values
+  // (the same for every rhs) are loaded once, ahead of everything else, and
+  // each rhs issues all its x loads before its first sum; the terms are
+  // added in the order of the general loop below.  The held values take
+  // registers (a third of the occupancy), which one rhs does not repay.
+  constexpr int KU = kBandFastW / L;
   double2 cu[KU], cl[KU];
   int ju[KU], il[KU];
-  if (fast) {
+  if constexpr (FAST) {
 #pragma unroll
     for (int k = 0; k < KU; ++k) {
       const int d = l + k * L, dl = d + 1;
@@ -756,7 +759,7 @@ __global__ __launch_bounds__(256) void k_interp_band(
   for (int r = 0; r < nrhs; ++r) {
     const double2* xr = x + (size_t)r * ldx;
     double2 xu[KU], xl[KU];
-    if (fast) {
+    if constexpr (FAST) {
 #pragma unroll
       for (int k = 0; k < KU; ++k) {
         const int d = l + k * L;
@@ -772,7 +775,7 @@ __global__ __launch_bounds__(256) void k_interp_band(
       ax += sg * (w1 * (double)v1.x + w2 * (double)v2.x);
       ay += sg * (w1 * (double)v1.y + w2 * (double)v2.y);
     }
-    if (fast) {
+    if constexpr (FAST) {
 #pragma unroll
       for (int k = 0; k < KU; ++k) {
         const int d = l + k * L;
@@ -1511,14 +1514,19 @@ static aim_status interp(Ctx* c, const int* chans, int nch, double sg, bool near
     // a multiple of 8 blocks (the kernel's XCD-aware order); the extra ones exit
     const size_t nb = ((size_t)t.N * 16 + 255) / 256;
     dim3 g((unsigned)(8 * ((nb + 7) / 8)));
-    if (sizeof(T) == 4)
-      hipLaunchKernelGGL((k_interp_band<T, float>), g, dim3(256), 0, c->stream, t.N, nrhs, nch,
-                         c->d_Wf[chans[0]], c->d_Wf[chans[nch > 1 ? 1 : 0]], c->d_Wf[chans[nch > 2 ? 2 : 0]], sg,
-                         c->d_aidx, (const cplx<T>*)c->d_V, t.n_act, t.band_w, Cd, x, ldx, y, ldy, scale);
-    else
-      hipLaunchKernelGGL((k_interp_band<T, double>), g, dim3(256), 0, c->stream, t.N, nrhs, nch,
-                         c->d_W[chans[0]], c->d_W[chans[nch > 1 ? 1 : 0]], c->d_W[chans[nch > 2 ? 2 : 0]], sg,
-                         c->d_aidx, (const cplx<T>*)c->d_V, t.n_act, t.band_w, Cd, x, ldx, y, ldy, scale);
+    const bool fast = Cd && nrhs > 1 && t.band_w < kBandFastW;
+#define AIM_BAND(TW, WT, F)                                                                                   \
+  hipLaunchKernelGGL((k_interp_band<T, TW, F>), g, dim3(256), 0, c->stream, t.N, nrhs, nch, WT[chans[0]],     \
+                     WT[chans[nch > 1 ? 1 : 0]], WT[chans[nch > 2 ? 2 : 0]], sg, c->d_aidx, (const cplx<T>*)c->d_V, \
+                     t.n_act, t.band_w, Cd, x, ldx, y, ldy, scale)
+    if (sizeof(T) == 4) {
+      if (fast) AIM_BAND(float, c->d_Wf, true);
+      else AIM_BAND(float, c->d_Wf, false);
+    } else {
+      if (fast) AIM_BAND(double, c->d_W, true);
+      else AIM_BAND(double, c->d_W, false);
+    }
+#undef AIM_BAND
     AIM_HIP_CHECK(hipGetLastError());
     return AIM_OK;
   }
