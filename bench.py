@@ -445,7 +445,8 @@ def spectrum(args):
         from oracle import aim as oaim
         w = wl.paper_circle(wl.PULSE)
         N = w.n_unknowns
-        A = oaim.AimOracle(w.xy, w.k, w.eta, wl.PULSE, w.m, w.eps, alpha=w.alpha, near=False)
+        # n: the library's FFT length for the 600-point side (its numerical filter's DFT bins)
+        A = oaim.AimOracle(w.xy, w.k, w.eta, wl.PULSE, w.m, w.eps, alpha=w.alpha, near=False, n=2048)
         th = 2 * math.pi * np.arange(N) / N
         t0 = time.perf_counter()
         for nu in (0, 17, 45, 90):

@@ -114,7 +114,8 @@ typedef struct {
   double k;               /* wavenumber (rad / length unit), > 0                    */
   double eta;             /* medium impedance (ohm)                                 */
   int32_t basis;          /* AIM_PULSE (TM systems) or AIM_HAT (TE systems)         */
-  int32_t m;              /* grid points per side (power of two, 16..2048)          */
+  int32_t m;              /* grid points per side, 16..2048; the FFT length n is
+                             the smallest power of two >= 2m (n_pad of aim_info) */
   double eps;             /* grid step; grid centred at 0, L = (m-1) eps / 2        */
   int32_t quad;           /* Gauss-Legendre nodes per segment in the stencils (>=1) */
   int32_t near_radius;    /* anchor Chebyshev radius of the near zone, 3..m-4       */

@@ -21,8 +21,10 @@ Readings taken where the paper is silent:
     The per-node form (stencil_weights_node) gives every quadrature node its
     own P x P stencil at its own cell (nodes -(P/2-1) .. P/2, so P = 4 is the
     same cubic stencil); the paper's Sec. IV uses order 10.
-  * padding n = 2m (default) with the ring |d| = m of the kernel zero, or the
-    paper's n = 2m - 1.
+  * padding n = 2m (default) with the ring |d| = m of the kernel zero, the
+    paper's n = 2m - 1, or any given n >= 2m - 1 (the GPU library's FFT length
+    is the smallest power of two >= 2m): every such embedding gives the same
+    Toeplitz product; the numerical filter depends on n through its DFT bins.
   * the cutoff keeps bins with qx^2 + qy^2 <= (alpha n eps / 2 pi)^2,
     inclusive, with q in FFT order.
   * the accurate operators S and N get a near-field correction
@@ -65,11 +67,15 @@ class GeometryError(ValueError):
 
 
 class Grid:
-    def __init__(self, m: int, eps: float, pad: int = 0):
+    def __init__(self, m: int, eps: float, pad: int = 0, n: int | None = None):
         self.m = int(m)
         self.eps = float(eps)
         self.L = 0.5 * (self.m - 1) * self.eps
         self.n = 2 * self.m if pad == 0 else 2 * self.m - 1
+        if n is not None:
+            if int(n) < 2 * self.m - 1:
+                raise ValueError("a circulant embedding needs n >= 2m - 1")
+            self.n = int(n)
         self.pad = pad
 
     def coord(self, i):
@@ -300,14 +306,15 @@ class AimOracle:
     """The discrete AIM operators of one geometry / frequency / grid."""
 
     def __init__(self, xy, k, eta, basis, m, eps, p=10, near_radius=6, pad=0,
-                 alpha=math.inf, near=True, near_rows=None, node_order=0):
+                 alpha=math.inf, near=True, near_rows=None, node_order=0, n=None):
         """node_order = 0: one 4 x 4 stencil per basis (with the near-field
         correction); node_order = P: the per-node order-P Lambda, which has
-        no near-field correction, so only S^alpha (and the Gram solve)."""
+        no near-field correction, so only S^alpha (and the Gram solve).
+        n: length of the circulant embedding (>= 2m - 1), default from pad."""
         self.xy = np.asarray(xy, dtype=float)
         self.k, self.eta, self.basis = float(k), float(eta), int(basis)
         self.N = self.xy.shape[0]
-        self.grid = Grid(m, eps, pad)
+        self.grid = Grid(m, eps, pad, n)
         self.p = p
         self.R = near_radius
         self.node_order = int(node_order)

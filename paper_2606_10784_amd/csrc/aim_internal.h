@@ -75,10 +75,20 @@ __host__ __device__ inline int spec_last_radix(int n) {
 // Rows per tile of the row/column intermediate (the tile stride is ldt rows
 // of CB values).  The row passes touch every tile of a pair at this stride,
 // so a row count with a large power-of-two factor concentrates them on few
-// HBM channels (960 rows at CB = 2 in FP64, a 30 720 B = 15 * 2^11 B stride:
-// the inverse row pass 22 % slower than at 958 rows).  A multiple of 4 gets
+// HBM channels (960 rows of 32-byte FP64 pieces, a 30 720 B = 15 * 2^11 B
+// stride: the inverse row pass 22 % slower than at 958 rows).  A multiple of 4 gets
 // one padding row, which leaves at most a factor 2 in the row count.
 inline int tile_rows(int nr) { return nr % 4 == 0 ? nr + 1 : nr; }
+
+// FFT length of an m-point grid side: the smallest power of two >= 2m.  Any
+// length >= 2m - 1 embeds the Toeplitz grid kernel (offsets |d| <= m - 1) in
+// a circulant without wrap-around (Sec. III-A, eq. (8)); the offsets
+// m <= |d| <= n - m of the embedding are zero.
+inline int fft_length(int m) {
+  int n = 32;
+  while (n < 2 * m) n *= 2;
+  return n;
+}
 
 __host__ __device__ inline int spec_row_len(int n) {
   const int rl = spec_last_radix(n);

@@ -62,7 +62,7 @@ static aim_params dual_params(const aim_params* p, const std::vector<double>& rx
 
 size_t footprint(const aim_params* p, int restart, const HostTables* t) {
   // grid work + spectra + near field + stencils + Krylov space
-  const size_t N = p->n_vertices, m = p->m, n = 2 * m, R = p->max_rhs;
+  const size_t N = p->n_vertices, m = p->m, n = fft_length(p->m), R = p->max_rhs;
   const size_t nch = p->basis == AIM_HAT ? 3 : 1;
   const size_t H = n / 2 + 1;
   const size_t nr = t ? t->nr : m;

@@ -2,12 +2,13 @@
 //
 // The grid product G_grid u is evaluated as
 //     [F^-1( F(c) . F(b) )]_restr,   b = u zero-padded from m x m to n x n,
-// with n = 2m and the spectrum F(c) of the circulant kernel resident in HBM as
-// an even-symmetric quarter (Sec. III-A/B).  Three passes:
+// with n the smallest power of two >= 2m and the spectrum F(c) of the
+// circulant kernel resident in HBM as an even-symmetric quarter (Sec.
+// III-A/B).  Three passes:
 //   rows_fwd : scatter the active grid values of one grid row into LDS,
 //              length-n FFT along x, write the row (only rows [y0, y0+nr)
 //              that hold active points, compacted);
-//   cols_conv: for a block of CB columns: length-n FFT along y (rows >= nr are
+//   cols_conv: for a block of CW columns: length-n FFT along y (rows >= nr are
 //              zero), multiply by the spectrum, inverse FFT, keep nr rows;
 //   rows_inv : inverse FFT along x, gather the active points of the row.
 // The circulant product commutes with cyclic shifts, so compacting the rows to

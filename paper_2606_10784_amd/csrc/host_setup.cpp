@@ -100,7 +100,7 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
   const int N = p->n_vertices;
   const int m = p->m;
   if (N < 8) { err = "need at least 8 vertices"; return AIM_E_ARG; }
-  if (m < 16 || m > 2048 || (m & (m - 1))) { err = "m must be a power of two in [16, 2048]"; return AIM_E_ARG; }
+  if (m < 16 || m > 2048) { err = "m must be in [16, 2048]"; return AIM_E_ARG; }
   if (!(p->eps > 0) || !(p->k > 0) || !(p->eta > 0)) { err = "eps, k, eta must be positive"; return AIM_E_ARG; }
   if (p->quad < 1 || p->quad > 64) { err = "quad must be in [1, 64]"; return AIM_E_ARG; }
   if (p->near_radius < 3 || p->near_radius + 3 > m - 1) { err = "near_radius out of range"; return AIM_E_ARG; }
@@ -112,7 +112,7 @@ aim_status build_host_tables(const aim_params* p, HostTables& t, std::string& er
   t.N = N;
   t.basis = p->basis;
   t.m = m;
-  t.n = 2 * m;
+  t.n = fft_length(m);
   t.p = p->quad;
   t.R = p->near_radius;
   t.k = p->k;

@@ -1,7 +1,8 @@
 // Device set-up and operator application of libaim (gfx950).
 //
-//  * kernel sampling:  c[d] = g(eps |d|), c[0] = 0 (Sec. III-C), ring |d| = m
-//    of the n = 2m embedding zero; spectrum F(c) by the FFT kernels (eq. (8))
+//  * kernel sampling:  c[d] = g(eps |d|) for |d| <= m - 1, c[0] = 0 (Sec.
+//    III-C), the other offsets of the length-n embedding (n >= 2m; for n = 2m
+//    the ring |d| = m) zero; spectrum F(c) by the FFT kernels (eq. (8))
 //  * numerical filter: quarter spectrum masked to |kappa| <= alpha (Sec. III-B)
 //  * near field: exact Galerkin entries of eq. (4) / the Maue form of eq. (2)
 //    minus their grid approximation, FP64, one thread per nonzero; singular
@@ -88,10 +89,13 @@ __global__ void k_sample_kernel(int m, int n, double keps, double2* c) {
   const int qx = blockIdx.x * blockDim.x + threadIdx.x;
   const int qy = blockIdx.y;
   if (qx >= n) return;
-  const int dx = qx < m ? qx : qx - n;   // qx == m: ring, |d| = m -> 0
+  // offsets |d| >= m (positions m .. n - m; for n = 2m the ring |d| = m) are
+  // outside the grid's Toeplitz kernel and stay zero
+  const int dx = qx < m ? qx : qx - n;
   const int dy = qy < m ? qy : qy - n;
+  const bool in = (qx < m || qx > n - m) && (qy < m || qy > n - m);
   double2 v = make_double2(0.0, 0.0);
-  if (qx != m && qy != m && (dx != 0 || dy != 0)) v = green_grid(keps, dx, dy);
+  if (in && (dx != 0 || dy != 0)) v = green_grid(keps, dx, dy);
   c[(size_t)qy * n + qx] = v;
 }
 
@@ -165,7 +169,7 @@ __global__ void k_fill_from_octant(int m, int n, const double2* __restrict__ tab
   const int qy = blockIdx.y;
   if (qx >= n) return;
   double2 v = make_double2(0.0, 0.0);
-  if (qx != m && qy != m) {
+  if ((qx < m || qx > n - m) && (qy < m || qy > n - m)) {   // |d| <= m - 1
     int ax = qx < m ? qx : n - qx, ay = qy < m ? qy : n - qy;
     if (ax > ay) {
       const int t = ax;

@@ -179,14 +179,16 @@ def paper_circle(basis: int = PULSE) -> Workload:
     f = 0.4 GHz, mesh size h = pi/(15 k) (lambda/30), p = 10, grid step
     2.4 m / 599, cutoff alpha = 8 k.  The mesh of its figures is not given; a
     circle of radius 1 m (inside the paper's L = 1.2 m grid) with N = 30 k a
-    segments.  The grid side is 1024 instead of 600 (only a larger zero
-    margin for the padded convolution)."""
+    segments.  The grid is the paper's, 600 points per side (L = 1.2 m); the
+    library embeds it in FFTs of length 2048 (the paper's embedding has
+    2m - 1 = 1199): the unfiltered products are the same, the numerical
+    filter's DFT bins are finer."""
     c0 = 299792458.0
     k = 2.0 * math.pi * 0.4e9 / c0
     a = 1.0
     n = int(round(30.0 * k * a))
     return Workload(f"paper_circle_f0.4GHz_N{n}" + ("_hat" if basis == HAT else ""), circle(a, n), k, ETA0, basis,
-                    1024, 2.4 / 599.0, alpha=8.0 * k)
+                    600, 2.4 / 599.0, alpha=8.0 * k)
 
 
 def scaled_cylinder(n: int, a: float, m: int, eps: float, basis: int = PULSE) -> Workload:

@@ -42,8 +42,9 @@ def test_setup_rejects_bad_arguments_without_device():
     lib = aim._lib()
     h = ctypes.c_void_p()
     assert lib.aim_setup(None, ctypes.byref(h)) == aim.AIM_E_ARG
-    p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, 48, 0.1)   # m not a power of two
-    assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
+    for bad_m in (15, 2049):                                                      # m outside 16..2048
+        p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, bad_m, 0.1)
+        assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_ARG
     p, _keep = aim.make_params(wl.circle(1.0, 64), wl.K0, wl.ETA0, 0, 16, 0.1)   # contour leaves grid
     assert lib.aim_setup(ctypes.byref(p), ctypes.byref(h)) == aim.AIM_E_GEOM
     p, _keep = aim.make_params(wl.circle(0.4, 8), 4 * wl.K0, wl.ETA0, 0, 16, 0.1)  # k h > 2 pi

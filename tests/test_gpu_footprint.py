@@ -20,7 +20,9 @@ from paper_2606_10784_amd import aim  # noqa: E402
 
 
 def _spectrum_bytes(m, mixed):
-    n = 2 * m
+    n = 32
+    while n < 2 * m:
+        n *= 2
     rl = n
     while rl > 16:
         rl >>= 4

@@ -89,7 +89,8 @@ C0 = 299792458.0
 KP = 2 * math.pi * 0.4e9 / C0
 NP = int(round(30 * KP))          # h = pi / (15 k), radius 1 m
 EPSP = 2.4 / 599
-MP = 1024
+MP = 600                          # the paper's grid side; FFT length 2048
+NP_FFT = 2048
 ALPHAP = 8 * KP
 NUS = np.arange(0, NP // 2 + 1)
 
@@ -106,7 +107,7 @@ def test_node_map_fig2_spectrum_matches_oracle(paper_node):
     xy, ctx = paper_node
     nus = np.array([0, 3, 17, 40, 66, 100, 126])
     lam = ctx.fourier_spectrum("S_ALPHA", nus)
-    orc = oaim.AimOracle(xy, KP, wl.ETA0, 0, MP, EPSP, alpha=ALPHAP, node_order=10)
+    orc = oaim.AimOracle(xy, KP, wl.ETA0, 0, MP, EPSP, alpha=ALPHAP, node_order=10, n=NP_FFT)
     th = 2 * math.pi * np.arange(NP) / NP
     E = np.exp(1j * np.outer(th, nus))
     Y = orc.gram_inv(orc.apply('S_ALPHA', E))

@@ -1,5 +1,6 @@
 """Every grid size the library supports (m = 16 .. 1024, FFT lengths n =
-32 .. 2048; n = 4096 is covered by the full-size star), each with its own
+32 .. 2048; n = 4096 is covered by the full-size star; grid sides that are
+not powers of two take the next power-of-two FFT length), each with its own
 radix split and folded spectrum layout, against the oracle: a circle filling
 most of the grid with an odd number of segments (ragged against every lane
 group and tile), pulses and hats, two right-hand sides, FP64 to 1e-12 and
@@ -56,6 +57,38 @@ def test_every_grid_size_matches_oracle(m, basis):
         assert e32 < 1e-5
     z = torch.zeros_like(xt)
     assert torch.count_nonzero(ctx.matvec("S_ALPHA", z)).item() == 0
+
+
+ODD_SIZES = [(48, 1, 128), (600, 0, 2048)]
+
+
+@pytest.mark.parametrize("m,basis,n_fft", ODD_SIZES, ids=[f"m{m}_{'hat' if b else 'pulse'}" for m, b, _ in ODD_SIZES])
+def test_grid_side_not_a_power_of_two(m, basis, n_fft):
+    """A grid side that is not a power of two (48; the paper's Sec. IV grid
+    of 600 points) runs on the FFT length n = the smallest power of two
+    >= 2m: the oracle with the same embedding length gives the same
+    operators, filtered ones included (the numerical filter's DFT bins
+    follow n)."""
+    xy, _ = _case(m, basis)
+    n = xy.shape[0]
+    alpha = wl.alpha_half_bins(EPS)
+    print(f"odd grid side m={m} basis={basis} N={n}", flush=True)
+    ctx = aim.Context(xy, K, ETA, basis, m, EPS, max_rhs=2, precision=aim.AIM_MIXED)
+    assert ctx.info()["n_pad"] == n_fft
+    ctx.filter(alpha)
+    orc = oaim.AimOracle(xy, K, ETA, basis, m, EPS, alpha=alpha, n=n_fft)
+    rng = np.random.default_rng(m)
+    x = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    xt = torch.from_numpy(x).cuda()
+    for op in (("S", "S_ALPHA", "TM") if basis == 0 else ("S_ALPHA", "N", "TE_CP")):
+        ref = orc.apply(op, x.T).T
+        y = ctx.matvec(op, xt).cpu().numpy()
+        yf = ctx.matvec(aim.OPS[op] | aim.AIM_OP_GRID_FP32, xt).cpu().numpy()
+        e64 = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        e32 = np.max(np.abs(yf - ref)) / np.max(np.abs(ref))
+        print(op, e64, e32)
+        assert e64 < (1e-10 if op == "TE_CP" else 1e-12)
+        assert e32 < 1e-5
 
 
 @pytest.mark.parametrize("basis", [0, 1])

@@ -4,8 +4,9 @@ analytic and S^alpha by the AIM numerical filter; Fig. 3: G^-1 S G^-1 N and
 G^-1 S^alpha G^-1 N) at the paper's parameters: f = 0.4 GHz, h = pi/(15k),
 p = 10, grid spacing 2.4 m / 599, alpha = 8k.  The mesh of those figures is
 not given; a circle of radius 1 m is used (it fits the paper's L = 1.2 m
-grid), with a 1024-point grid side instead of 600 (a larger zero margin
-does not change a padded convolution).
+grid), on the paper's 600-point grid side.  The library embeds it in FFTs of
+length 2048 (the smallest power of two >= 2m); the oracle uses the same
+embedding length, since the numerical filter's DFT bins follow it.
 
 Parity: each quotient against the oracle's AIM operator applied to the same
 mode (FP64, element bound 1e-11 of the largest |lambda|).  Physics: the
@@ -34,7 +35,8 @@ K = 2 * math.pi * 0.4e9 / C0
 A_RAD = 1.0
 N = int(round(30 * K * A_RAD))          # h = pi / (15 k)
 EPS = 2.4 / 599
-M = 1024
+M = 600
+N_FFT = 2048                            # the library's embedding of the 600-point side
 ALPHA = 8 * K
 NUS = np.arange(0, N // 2 + 1)
 
@@ -55,8 +57,9 @@ def _oracle_quot(orc, op, nus, gram):
 def fig2():
     xy = wl.circle(A_RAD, N)
     ctx = aim.Context(xy, K, wl.ETA0, 0, M, EPS, quad=10, max_rhs=32)
+    assert ctx.info()["n_pad"] == N_FFT
     ctx.filter(ALPHA)
-    orc = oaim.AimOracle(xy, K, wl.ETA0, 0, M, EPS, alpha=ALPHA)
+    orc = oaim.AimOracle(xy, K, wl.ETA0, 0, M, EPS, alpha=ALPHA, n=N_FFT)
     return ctx, orc
 
 
@@ -65,7 +68,7 @@ def fig3():
     xy = wl.circle(A_RAD, N)
     ctx = aim.Context(xy, K, wl.ETA0, 1, M, EPS, quad=10, max_rhs=32)
     ctx.filter(ALPHA)
-    orc = oaim.AimOracle(xy, K, wl.ETA0, 1, M, EPS, alpha=ALPHA)
+    orc = oaim.AimOracle(xy, K, wl.ETA0, 1, M, EPS, alpha=ALPHA, n=N_FFT)
     return ctx, orc
 
 

@@ -72,6 +72,7 @@ CASES = {
     "star_hat": (wl.star5(0.6, 256), wl.K0, 1, 64, 0.05),
     "irregular_pulse": (wl.irregular_polygon(np.random.default_rng(7), 2.0, 300), wl.K0, 0, 128, 1 / 25),
     "irregular_hat": (wl.irregular_polygon(np.random.default_rng(9), 1.5, 160, depth=0.2), 3 * wl.K0, 1, 64, 0.06),
+    "circle_pulse_m48": (wl.circle(1.8, 300), wl.K0, 0, 48, 0.1),       # a grid side that is not a power of two
 }
 
 
@@ -115,7 +116,8 @@ def test_host_node_map_matches_oracle(dumper, tmp_path, order, basis):
 def test_host_errors(dumper, tmp_path):
     t = str(tmp_path)
     xy = wl.circle(1.0, 64)
-    assert _run(dumper, t, xy, wl.K0, 0, 48, 0.1)["status"] == AIM_E_ARG          # m not a power of two
+    for bad_m in (15, 2049):                                                        # m outside 16..2048
+        assert _run(dumper, t, xy, wl.K0, 0, bad_m, 0.1)["status"] == AIM_E_ARG
     assert _run(dumper, t, xy, wl.K0, 0, 16, 0.1)["status"] == AIM_E_GEOM         # contour leaves the grid
     assert _run(dumper, t, wl.circle(0.4, 8), 4 * wl.K0, 0, 16, 0.1)["status"] == AIM_E_ARG   # k h > 2 pi
     assert _run(dumper, t, wl.circle(0.4, 7), wl.K0, 0, 16, 0.1)["status"] == AIM_E_ARG      # < 8 vertices

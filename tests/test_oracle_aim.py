@@ -57,11 +57,12 @@ def _dft_matrix(n):
     return np.exp(-2j * math.pi * np.outer(q, q) / n)
 
 
-@pytest.mark.parametrize("pad", [0, 1])
-def test_filtered_kernel_against_explicit_dft(pad):
+@pytest.mark.parametrize("pad,n", [(0, None), (1, None), (0, 16)])
+def test_filtered_kernel_against_explicit_dft(pad, n):
     """c^alpha = F^-1(mask . F(c)) written with explicit DFT matrices on a
-    tiny grid, then compared with the oracle table."""
-    grid = aim.Grid(6, 0.1, pad)
+    tiny grid, then compared with the oracle table; n = 2m, the paper's
+    2m - 1, and a longer embedding (16 > 2m, as a power-of-two FFT length)."""
+    grid = aim.Grid(6, 0.1, pad, n)
     T = aim.kernel_table(grid, K)
     c = aim.circulant_kernel(grid, T)
     n = grid.n
@@ -90,6 +91,29 @@ def test_circulant_embedding_ring_and_self_term():
     assert np.all(c[grid.m, :] == 0) and np.all(c[:, grid.m] == 0)
     assert c[0, 0] == 0
     assert c[3, grid.n - 2] == T[3, 2]
+
+
+def test_embedding_length_leaves_the_toeplitz_product_unchanged():
+    """Any embedding n >= 2m - 1 reproduces the direct Toeplitz sum (eq. (8)):
+    the FFT product at n = 2m - 1, 2m and 64 > 2m equals the direct sum over
+    the active points, and the longer embedding is zero at the offsets
+    m <= |d| <= n - m."""
+    xy = wl.circle(0.9, 40)
+    x = wl.probe_vector(40, seed=5)
+    ref = None
+    for pad, n in ((1, None), (0, None), (0, 64)):
+        A = aim.AimOracle(xy, K, wl.ETA0, 0, 24, 0.1, pad=pad, n=n, near=False)
+        u = A.anterpolate('phi', x)
+        direct = A.grid_apply(A.T, u)
+        fft = A.grid_apply_fft(aim.spectrum(A.grid, A.T), u)
+        assert np.linalg.norm(fft - direct) < 1e-13 * np.linalg.norm(direct)
+        ref = direct if ref is None else ref
+        assert np.array_equal(direct, ref)
+        c = aim.circulant_kernel(A.grid, A.T)
+        far = np.arange(A.grid.m, A.grid.n - A.grid.m + 1)
+        assert np.all(c[far, :] == 0) and np.all(c[:, far] == 0)
+    with pytest.raises(ValueError):
+        aim.Grid(24, 0.1, n=46)
 
 
 def test_identity_filter_and_kept_fraction():
@@ -322,12 +346,13 @@ def test_node_operator_symmetric_and_refuses_near_field_ops():
 
 
 def test_paper_grid_m600_fig2_gap():
-    """Fig. 2 at the paper's own grid: m = 600 points on L = 1.2 m with the
-    2m - 1 circulant of Sec. III-A (the library runs m = 1024, n = 2m).  The
-    numerically filtered S^alpha follows the analytic filter (eq. (6) on the
-    circle) within 2.2 % below 0.45 alpha a on both grids; the larger grid
-    changes the window of eq. (9) and the bin spacing, so the gaps differ, by
-    about 1 % of the gap itself (measured 2.149 % against 2.165 %)."""
+    """Fig. 2 at the paper's own grid: m = 600 points on L = 1.2 m, with the
+    2m - 1 circulant of Sec. III-A and with the library's embedding (n = 2048,
+    the smallest power-of-two FFT length >= 2m).  The numerically filtered
+    S^alpha follows the analytic filter (eq. (6) on the circle) within 2.2 %
+    below 0.45 alpha a for both; the numerical filter's DFT bins follow n, so
+    the gaps differ, by about 2 % of the gap itself (measured 2.149 % against
+    2.187 %)."""
     w = wl.paper_circle(0)
     N, k, a = w.n_unknowns, w.k, 1.0
     th = 2 * math.pi * (np.arange(N) + 0.5) / N
@@ -336,10 +361,10 @@ def test_paper_grid_m600_fig2_gap():
     ex = mie.circle_eig_S_alpha(ns, k, a, w.alpha)
     sc = np.maximum(np.abs(ex), 0.2 * np.abs(ex).max())
     gaps = {}
-    for m, pad in ((600, 1), (1024, 0)):
-        A = aim.AimOracle(w.xy, k, w.eta, 0, m, w.eps, alpha=w.alpha, near=False, pad=pad)
+    for pad, nfft in ((1, None), (0, 2048)):
+        A = aim.AimOracle(w.xy, k, w.eta, 0, 600, w.eps, alpha=w.alpha, near=False, pad=pad, n=nfft)
         lam = np.array([np.vdot(np.exp(1j * n * th), A.op_S_alpha(np.exp(1j * n * th))) / (N * h) for n in ns])
-        gaps[m] = np.abs(lam - ex) / sc
-    print("max gap m=600 (2m-1):", gaps[600].max(), " m=1024 (2m):", gaps[1024].max())
-    assert gaps[600].max() < 0.022 and gaps[1024].max() < 0.022
-    assert 0.0 < np.max(np.abs(gaps[600] - gaps[1024])) < 0.1 * gaps[600].max()
+        gaps[A.grid.n] = np.abs(lam - ex) / sc
+    print("max gap m=600, n=1199:", gaps[1199].max(), " n=2048:", gaps[2048].max())
+    assert gaps[1199].max() < 0.022 and gaps[2048].max() < 0.022
+    assert 0.0 < np.max(np.abs(gaps[1199] - gaps[2048])) < 0.1 * gaps[1199].max()
