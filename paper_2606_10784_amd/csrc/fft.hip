@@ -479,10 +479,11 @@ template <int N> constexpr int last_radix() {
 }
 
 // ---------------------------------------------------------------------------
-// column blocks: CB columns per block; columns kx and N - kx share a block so
-// the even-symmetric quarter spectrum is read once.  Block b, slot c holds
-// pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror N - q); the last slot pair
-// of the last block holds the self-mirrored columns 0 and N/2.
+// tiles: CB columns per tile; columns kx and N - kx share a tile (and a
+// column-pass block) so the even-symmetric quarter spectrum is read once.
+// Tile b, slot c holds pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror
+// N - q); the last slot pair of the last tile holds the self-mirrored
+// columns 0 and N/2.
 // ---------------------------------------------------------------------------
 // CB is the tile width (columns per tile, the row passes' piece); CW the
 // columns one column-pass block transforms: as many as fit the LDS budget
@@ -520,7 +521,7 @@ __device__ __forceinline__ void col_block_of(int b, int& tb, int& c0) {
 __device__ __forceinline__ void col_of(int b, int c, int N, int CB, int& kx, int& kxq) {
   const int q = b * (CB / 2) + (c >> 1) + 1;
   const int half = c & 1;
-  if (q >= N / 2) {            // last pair slot of the last block
+  if (q >= N / 2) {            // last pair slot of the last tile
     kx = half ? N / 2 : 0;
     kxq = kx;
   } else {
@@ -529,20 +530,8 @@ __device__ __forceinline__ void col_of(int b, int c, int N, int CB, int& kx, int
   }
 }
 
-__device__ __forceinline__ void slot_of(int kx, int N, int CB, int& b, int& c) {
-  const int q = kx <= N / 2 ? kx : N - kx;
-  const int nblk = N / CB;
-  if (q == 0 || q == N / 2) {
-    b = nblk - 1;
-    c = CB - 2 + (q == 0 ? 0 : 1);
-  } else {
-    b = (q - 1) / (CB / 2);
-    c = 2 * ((q - 1) % (CB / 2)) + (kx > N / 2 ? 1 : 0);
-  }
-}
-
 // XCD-aware row order: consecutive rows go to the same XCD (blocks are
-// dealt round-robin over 8 XCDs), so the halves of a tile line written by
+// dealt round-robin over 8 XCDs), so the pieces of a tile line written by
 // neighbouring rows meet in one L2.
 __device__ __forceinline__ int xcd_row(int bid, int nrows) {
   const int per = (nrows + 7) / 8;
