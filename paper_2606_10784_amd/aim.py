@@ -118,6 +118,11 @@ def _lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libaim.so not built ({LIB_PATH}); run paper_2606_10784_amd/build.py")
+        # torch first: its HIP and HSA runtimes are then the ones the library
+        # binds to (same sonames).  Loaded the other way round, torch maps its
+        # own copies beside the system ones and the process holds two HSA
+        # runtimes on one device, which crashes at the first device work.
+        _torch()
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in EXPORTS.items():
             fn = getattr(lib, name)

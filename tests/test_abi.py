@@ -140,3 +140,19 @@ def test_workspace_size_and_checks_on_the_host():
     f20 = aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, restart=0, max_restart=20)
     assert f20 - f0 == need
     assert aim.aim_footprint_bytes(xy, wl.K0, wl.ETA0, 0, 64, 0.05, restart=20, max_restart=20) == f20
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not map a second HIP / HSA
+    runtime: torch ships its own copies (same sonames), and two HSA runtimes
+    on one device crash the process at the first device work."""
+    import subprocess
+    import sys
+    code = ("from paper_2606_10784_amd import aim; aim._lib(); import torch; "
+            "maps = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'amdhip64' in l}), "
+            "len({l.split()[-1] for l in maps.splitlines() if 'hsa-runtime64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split() == ["1", "1"], r.stdout
