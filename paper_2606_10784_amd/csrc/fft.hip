@@ -205,7 +205,7 @@ __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
 // The column pass pads one slot per 256 bytes in both precisions: per 16
 // FP64 or per 32 FP32 complex values.  In its fused pass consecutive lanes
-// step 8 CB values apart (256 B), so the pad shifts each lane by one value
+// step 8 CW values apart (256 B), so the pad shifts each lane by one value
 // (4 banks in FP64, 2 in FP32) and a cycle's lanes (16 of 16 B, 32 of 8 B)
 // cover distinct banks.  The buffer is sized with padded(), which covers both.
 template <typename T>
@@ -479,9 +479,10 @@ template <int N> constexpr int last_radix() {
 }
 
 // ---------------------------------------------------------------------------
-// tiles: CB columns per tile; columns kx and N - kx share a tile (and a
-// column-pass block) so the even-symmetric quarter spectrum is read once.
-// Tile b, slot c holds pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror
+// tiles: CB columns per tile; columns kx and N - kx share a tile (and,
+// with two or more columns per column-pass block, a block; with one, the two
+// blocks run on one XCD) so the even-symmetric quarter spectrum is fetched
+// once.  Tile b, slot c holds pair q = b*(CB/2) + c/2 + 1 (c odd: the mirror
 // N - q); the last slot pair of the last tile holds the self-mirrored
 // columns 0 and N/2.
 // ---------------------------------------------------------------------------
@@ -539,7 +540,7 @@ __device__ __forceinline__ int xcd_row(int bid, int nrows) {
 }
 
 // ---------------------------------------------------------------------------
-// kernels.  T layout (tiled): [pair][block][row][CB] with ldt >= nr rows
+// kernels.  T layout (tiled): [pair][tile][row][CB] with ldt >= nr rows
 // per tile (tile_rows); rows nr .. ldt-1 are never read or written
 // ---------------------------------------------------------------------------
 template <int N> constexpr int row_threads() { return N / 16 < 64 ? 64 : (N / 16 > 256 ? 256 : N / 16); }
@@ -594,7 +595,7 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fwd(
     __syncthreads();
   }
   chain_passes<T, N, NT, false, 16, N, false>(buf, wt);
-  // pairs of lanes fill the CB-wide segments of the tiled layout; the LDS
+  // groups of CB lanes fill the CB-wide segments of the tiled layout; the LDS
   // reads of a thread are all issued before its stores
   V* out = Tb + (size_t)pair * NBLK * ldt * CB + (size_t)row * CB;
   constexpr int PER = (N + NT - 1) / NT;
@@ -710,14 +711,14 @@ __global__ __launch_bounds__(row_threads<N>()) void k_rows_fft_inplace(cplx<T>* 
 }
 
 // Pass 2 (MODE 0): column FFT, spectrum multiply, inverse column FFT, in
-// place on one tile [row][CB] of T (nr <= N/2 rows kept, the rest is the
+// place on CW columns of one tile [row][CB] of T (nr <= N/2 rows kept, the rest is the
 // zero padding).  The column FFT is an in-place decimation in frequency, so
 // position p holds frequency ky_of_pos(N, p); the spectrum Cq is stored in
 // that order, folded over ky -> N - ky ([kxq][spec_row_len(N)]), and the
 // inverse is the matching decimation in time.
-// MODE 1 (set-up): plain forward FFT of CB consecutive columns of a
+// MODE 1 (set-up): plain forward FFT of CW consecutive columns of a
 // row-major N x N array.
-// The column pass of one tile [row][CB] (nr kept rows, the rest of the
+// The column pass of CW columns of one tile [row][CB] (nr kept rows, the rest of the
 // column is the zero padding), in place: column FFT, spectrum multiply,
 // inverse column FFT (the MODE 0 body of k_cols and of k_cols_group).
 template <typename T, int N>
