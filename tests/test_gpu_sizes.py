@@ -59,17 +59,20 @@ def test_every_grid_size_matches_oracle(m, basis):
     assert torch.count_nonzero(ctx.matvec("S_ALPHA", z)).item() == 0
 
 
-ODD_SIZES = [(48, 1, 128), (600, 0, 2048)]
+# (m, basis, FFT length, circle sized for grid side m_case): 1500 keeps the
+# m = 600 circle on a 4096-point embedding
+ODD_SIZES = [(17, 1, 64, 17), (48, 1, 128, 48), (600, 0, 2048, 600), (1500, 0, 4096, 600)]
 
 
-@pytest.mark.parametrize("m,basis,n_fft", ODD_SIZES, ids=[f"m{m}_{'hat' if b else 'pulse'}" for m, b, _ in ODD_SIZES])
-def test_grid_side_not_a_power_of_two(m, basis, n_fft):
-    """A grid side that is not a power of two (48; the paper's Sec. IV grid
-    of 600 points) runs on the FFT length n = the smallest power of two
-    >= 2m: the oracle with the same embedding length gives the same
+@pytest.mark.parametrize("m,basis,n_fft,m_case", ODD_SIZES,
+                         ids=[f"m{m}_{'hat' if b else 'pulse'}" for m, b, _, _ in ODD_SIZES])
+def test_grid_side_not_a_power_of_two(m, basis, n_fft, m_case):
+    """A grid side that is not a power of two (17, 48, the paper's Sec. IV
+    grid of 600 points, 1500) runs on the FFT length n = the smallest power
+    of two >= 2m: the oracle with the same embedding length gives the same
     operators, filtered ones included (the numerical filter's DFT bins
     follow n)."""
-    xy, _ = _case(m, basis)
+    xy, _ = _case(m_case, basis)
     n = xy.shape[0]
     alpha = wl.alpha_half_bins(EPS)
     print(f"odd grid side m={m} basis={basis} N={n}", flush=True)
