@@ -74,13 +74,14 @@ def mixed_gram(xy):
 class TMCalderonOracle:
     """TM Calderon operators of one geometry / frequency / grid."""
 
-    def __init__(self, xy, k, eta, m, eps, p=10, near_radius=6, alpha=np.inf):
+    def __init__(self, xy, k, eta, m, eps, p=10, near_radius=6, alpha=np.inf, n=None):
+        """n: length of the grid's circulant embedding (default 2m)."""
         self.xy = np.asarray(xy, dtype=float)
         self.k, self.eta = float(k), float(eta)
         self.N = self.xy.shape[0]
-        self.primal = AimOracle(self.xy, k, eta, 0, m, eps, p=p, near_radius=near_radius, alpha=alpha)
+        self.primal = AimOracle(self.xy, k, eta, 0, m, eps, p=p, near_radius=near_radius, alpha=alpha, n=n)
         self.dual = AimOracle(refined_polygon(self.xy), k, eta, 1, m, eps, p=p, near_radius=near_radius,
-                              alpha=alpha)
+                              alpha=alpha, n=n)
         self.R = dual_combination(self.N)
         self.G = mixed_gram(self.xy)
 

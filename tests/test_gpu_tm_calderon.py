@@ -60,6 +60,25 @@ def test_tm_calderon_operators_match_oracle(name, xy, eps):
         assert errf < 1e-5
 
 
+def test_tm_calderon_on_a_grid_side_not_a_power_of_two():
+    """The pulse space and its dual hats share a 40-point grid side (FFT
+    length 128): the preconditioned operators equal the oracle's with the
+    same embedding length."""
+    xy, eps = wl.circle(0.5, 40), 0.05
+    alpha = math.sqrt(2 * math.pi) / eps
+    ctx = aim.Context(xy, K, wl.ETA0, 0, 40, eps, precision=aim.AIM_MIXED, max_rhs=2, dual=1, max_restart=0)
+    assert ctx.info()["n_pad"] == 128
+    ctx.filter(alpha)
+    orc = odual.TMCalderonOracle(xy, K, wl.ETA0, 40, eps, alpha=alpha, n=128)
+    x = np.random.default_rng(11).standard_normal((40, 2)) + 1j * np.random.default_rng(12).standard_normal((40, 2))
+    for op in ("TM_PC", "TM_CP", "TM_CP_UNF"):
+        ref = orc.apply(op, x)
+        y = ctx.matvec(op, _cols(x)).cpu().numpy().T
+        err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+        print(op, "m=40", err)
+        assert err < 1e-12
+
+
 def test_n_alpha_matches_oracle():
     xy = wl.star5(1.0, 64)
     eps = 0.08
